@@ -1,0 +1,173 @@
+/*
+ * dbq.h -- C ABI of the MI355X deflated-BiCGStab library for Wilson and twisted-mass
+ * fermion systems A x = b with many right-hand sides.
+ *
+ * Method: Abdel-Rehim, Morgan and Wilcox, "Deflated BiCGStab for linear equations in QCD
+ * problems" (Lattice 2007).  Sec. 1 sets the problem (many right-hand sides, kappa near
+ * kappa_c, gamma5 A gamma5 = A^dagger), Sec. 2 the D-BiCGStab(k) algorithm, Sec. 3 the first
+ * right-hand side by GMRES-DR(m,k) and the definition of kappa_c, Sec. 4 the twisted-mass
+ * operator and the projection over previous shifts' solutions.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Lattice: extents L[4] = {Lx, Ly, Lz, Lt}, all even and >= 2, periodic; V = Lx*Ly*Lz*Lt;
+ * lexicographic site index lex = x + Lx*(y + Ly*(z + Lz*t)); n = 12*V.
+ * Spinor fields (caller layout): complex128 (interleaved re, im doubles), [nrhs][V][4 spin][3 colour],
+ * so element index 12*lex + 3*spin + colour inside one right-hand side.
+ * Gauge field (caller layout): complex128 [4 mu][V][3][3]; links[mu][x] = U_mu(x), the SU(3)
+ * matrix on the link x -> x + mu.  Rows must be unitary with determinant 1 for the single-precision
+ * path (it stores two rows and rebuilds the third as conj(row0 x row1)).
+ * Operator: A(mu) = I - kappa*H + i*mu*gamma5,
+ *   (H psi)(x) = sum_mu [(1 - gamma_mu) U_mu(x) psi(x+mu) + (1 + gamma_mu) U_mu(x-mu)^dagger psi(x-mu)],
+ *   chiral gamma basis with gamma5 = diag(1, 1, -1, -1); the dagger is A(mu)^dagger = gamma5 A(-mu) gamma5.
+ * Memory: every large array (fields, vectors, bases) is a DEVICE pointer owned by the caller;
+ * scalar outputs (theta, stats, norms) are HOST pointers.  The library owns only the workspace
+ * inside a dbq_ctx (allocated lazily, reused across calls, freed by dbq_destroy).
+ * Streams: all work is ordered on the context's stream; solver calls synchronise that stream
+ * before returning, wilson_apply and link_force do not.
+ * Errors: every call returns a dbq_status and never throws; dbq_last_error() gives the message.
+ * Invalid arguments (odd or zero extents, k >= m, nrhs < 1, null pointers) return DBQ_EINVAL
+ * without launching anything.
+ * Tolerances: tol means ||b - A x||_2 / ||b||_2 <= tol, judged on an FP64 residual recomputed
+ * from the final x.  max_mv caps matrix-vector products per right-hand side.
+ */
+#ifndef DBQ_H
+#define DBQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dbq_ctx dbq_ctx;
+
+typedef enum {
+  DBQ_OK = 0,
+  DBQ_NOT_CONVERGED = 1, /* the paper's "F": x holds the best iterate, stats are valid */
+  DBQ_EINVAL = -1,
+  DBQ_EBREAKDOWN = -2,   /* BiCGStab broke down more than 10 times */
+  DBQ_ESINGULAR = -3,    /* projected k x k matrix numerically singular (cond > 1e12) */
+  DBQ_EHIP = -4,
+  DBQ_ENOMEM = -5
+} dbq_status;
+
+typedef enum {
+  DBQ_FP64 = 0,  /* FP64 vectors, FP64 18-real links */
+  DBQ_MIXED = 1  /* FP32 vectors and 12-real links inside BiCGStab, FP64 reliable updates */
+} dbq_prec;
+
+typedef struct {
+  int32_t L[4];
+  const void* links; /* device, complex128 [4][V][3][3] */
+  double kappa;
+  double mu;         /* twisted mass; 0 for plain Wilson */
+} dbq_operator;
+
+typedef struct {
+  int64_t matvecs;          /* operator applications charged to this right-hand side */
+  int64_t iterations;       /* BiCGStab iterations (GMRES-DR: cycles) */
+  int64_t restarts;         /* BiCGStab breakdown restarts */
+  int64_t reliable_updates; /* FP64 residual recomputations (mixed precision) */
+  double rel_true_resid;    /* ||b - A x|| / ||b|| in FP64 at exit */
+  double seconds;           /* wall time of the call (shared by all rhs of a call) */
+  int32_t status;           /* dbq_status of this right-hand side */
+  int32_t pad;
+} dbq_stats;
+
+/* Context: hip_stream is a hipStream_t (NULL = the null stream).  The stream must live as long
+ * as the context.  Returns DBQ_OK and a context in *out. */
+int dbq_create(dbq_ctx** out, void* hip_stream);
+int dbq_destroy(dbq_ctx* ctx);
+const char* dbq_last_error(const dbq_ctx* ctx);
+/* Change the stream later calls are ordered on. */
+int dbq_set_stream(dbq_ctx* ctx, void* hip_stream);
+
+/* Geometry tables of the even-odd site order used inside the library (Sec. 3 solves the
+ * even-odd preconditioned system; here even-odd is the storage order of the full operator):
+ * eo = parity*V/2 + (lex >> 1), parity = (x+y+z+t) mod 2.
+ * lex_of_eo: DEVICE int32 [V]; nbr: DEVICE int32 [8][V] with nbr[2*mu][eo] = eo index of x+mu and
+ * nbr[2*mu+1][eo] = eo index of x-mu.  dbq_geometry_host fills HOST arrays with the same values
+ * from the same index arithmetic on the CPU. */
+int dbq_geometry(dbq_ctx* ctx, const int32_t L[4], int32_t* lex_of_eo, int32_t* nbr);
+int dbq_geometry_host(const int32_t L[4], int32_t* lex_of_eo, int32_t* nbr);
+
+/* out = A(mu) in (dagger = 0) or A(mu)^dagger in (dagger = 1) for nrhs right-hand sides
+ * (Sec. 1 operator; the matrix-vector product every solver in the paper is costed in).
+ * in, out: DEVICE complex128 [nrhs][V][12], must not overlap.  prec = DBQ_MIXED computes in
+ * FP32 with 12-real links and returns the FP32 result widened to complex128. */
+int wilson_apply(dbq_ctx* ctx, const dbq_operator* op, const void* in, void* out,
+                 int32_t nrhs, int32_t dagger, int32_t prec);
+
+/* First right-hand side by GMRES-DR(m,k) (Sec. 1 and Sec. 3): restarted GMRES whose restart
+ * keeps the k harmonic Ritz vectors of smallest |theta|; convergence is tested once per cycle,
+ * so matvecs = m + (m-k)(cycles-1) when x0 = 0.
+ * b: DEVICE complex128 [V][12]; x: DEVICE complex128 [V][12], in: initial guess, out: solution.
+ * V_out: DEVICE complex128 column-major n x k (column j at V_out + j*n), orthonormal, spanning the
+ * final cycle's harmonic Ritz vectors; theta: HOST double [2*k] (re, im) sorted by |theta|;
+ * k_out: HOST, the number of columns returned (k, or k-1 when the k-th and (k+1)-th values are a
+ * complex-conjugate pair, which would make the left-right projection singular).
+ * Returns DBQ_NOT_CONVERGED when max_mv is reached first; V_out and theta are still written.
+ * Requires 2 <= k < m <= 128. */
+int gmresdr_first_rhs(dbq_ctx* ctx, const dbq_operator* op, const void* b, void* x,
+                      int32_t m, int32_t k, double tol, int64_t max_mv,
+                      void* V_out, double* theta, int32_t* k_out, dbq_stats* stats);
+
+/* D-BiCGStab(k) (Sec. 2) for a batch of nops operators (lattices of possibly different size),
+ * operator i with nrhs[i] right-hand sides:
+ *   r0 = b - A x0;  solve (U^H A V) y = U^H r0 with U = gamma5 V;  x0 += V y;  BiCGStab from x0.
+ * With dagger = 1 the system is A^dagger x = b and the roles swap (right vectors gamma5 V, left V).
+ * V[i]: DEVICE complex128 column-major n_i x k[i] (k[i] = 0: no deflation, plain BiCGStab).
+ * B[i]: DEVICE complex128 [nrhs[i]][V_i][12]; X[i]: same shape, in: x0, out: solution.
+ * per_rhs: HOST array of sum(nrhs) stats, in operator order.  prec: dbq_prec.
+ * Returns the worst status over all right-hand sides (an error status if any, else
+ * DBQ_NOT_CONVERGED if any did not converge). */
+int dbicgstab_solve(dbq_ctx* ctx, const dbq_operator* ops, int32_t nops,
+                    const void* const* V, const int32_t* k, const void* const* B,
+                    void* const* X, const int32_t* nrhs, double tol, int64_t max_mv,
+                    int32_t prec, int32_t dagger, dbq_stats* per_rhs);
+
+/* Minimal-residual projection over previous shifts' solutions (Sec. 4): for each rhs j,
+ * d = argmin ||r0 - A_new Q_j d|| with r0 = b_j - A_new x0_j, then x0_j += Q_j d.  The paper writes
+ * the normal equations Q^H A^H A Q d = Q^H A^H r0; this solves the same least-squares problem
+ * through a QR factorisation of W = A_new Q_j (classical Gram-Schmidt twice) so cond(W) is not
+ * squared.  Q: DEVICE complex128 [nrhs][nq][V][12]; B, X0: DEVICE complex128 [nrhs][V][12] (X0
+ * in/out); rnorm_before_after: HOST double [2*nrhs] = ||r0||, ||r_new|| per rhs.
+ * Costs (1 if x0 != 0) + nq matrix-vector products per rhs.  1 <= nq <= 32. */
+int project_shifts(dbq_ctx* ctx, const dbq_operator* op_new, const void* Q, int32_t nq,
+                   const void* B, void* X0, int32_t nrhs, double* rnorm_before_after);
+
+/* Gradient of L = sum_j Re(eta_j^H A^{-1} b_j) with respect to the links, given the solutions
+ * x_j = A^{-1} b_j and the adjoint solutions lambda_j = A^{-H} eta_j (dL = -Re(lambda^H dA x)):
+ *   G_mu(y) = kappa * sum_j sum_spin [ lambda(y) ((1-gamma_mu) x(y+mu))^H + x(y) ((1+gamma_mu) lambda(y+mu))^H ].
+ * lambda, x: DEVICE complex128 [nrhs][V][12].
+ * kind 0: F = DEVICE double [4][V][8], F[mu][y][a] = Re(i tr[T_a U_mu(y) G_mu(y)^H]), T_a = Gell-Mann/2,
+ *         the derivative along U -> exp(i theta T_a) U.
+ * kind 1: F = DEVICE complex128 [4][V][3][3] = G itself (dL = Re sum conj(G) dU). */
+int link_force(dbq_ctx* ctx, const dbq_operator* op, const void* lambda, const void* x,
+               int32_t nrhs, int32_t kind, void* F);
+
+/* kappa_c (Sec. 3: the kappa at which the real part of A's smallest eigenvalue vanishes), i.e.
+ * 1 / max Re lambda(H), from a thick-restarted Arnoldi iteration on H (restart keeps the k Ritz
+ * vectors of largest real part).  lambda: HOST double [2] = rightmost eigenvalue of H;
+ * resid: HOST, ||H v - lambda v|| / ||v|| of its Ritz vector.  Requires 2 <= k < m <= 128. */
+int kappa_critical(dbq_ctx* ctx, const int32_t L[4], const void* links, int32_t m, int32_t k,
+                   double tol, int64_t max_mv, double* kappa_c, double* lambda, double* resid);
+
+/* Instrumentation: with timing on, every Dslash launch inside the library is bracketed with HIP
+ * events on the context stream; dbq_kernel_time returns the accumulated milliseconds, launch
+ * count and the algorithmic HBM bytes of the launches of one kernel class
+ * (0 = Dslash FP64, 1 = Dslash FP32) since the last reset. */
+int dbq_set_timing(dbq_ctx* ctx, int32_t on);
+int dbq_kernel_time(dbq_ctx* ctx, int32_t kind, double* total_ms, int64_t* launches,
+                    double* algorithmic_bytes);
+int dbq_reset_timing(dbq_ctx* ctx);
+
+/* Library version string. */
+const char* dbq_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DBQ_H */

@@ -1,0 +1,432 @@
+// Fused BiCGStab vector updates and inner products for a batch of right-hand sides (Sec. 2 runs
+// BiCGStab after the deflation step; Sec. 1 motivates it as a non-restarted method).
+//
+// One iteration = 5 launches:  BI_P (p = r + beta (p - omega v)),  Dslash v = A p with <rhat, v>
+// -> alpha,  BI_S (r <- s = r - alpha v),  Dslash t = A s with <t, s>, <t, t> -> omega,
+// BI_XR (x += alpha p + omega s; r = s - omega t; <rhat, r>, ||r||^2 -> rho, beta, tests).
+// The scalars live in RhsScal on the device; each reduction finishes in the last block to arrive
+// with a fixed summation order, so results do not depend on block scheduling.
+#include "kernels.h"
+
+namespace dbq {
+
+namespace {
+
+template <typename E>
+struct ET;
+template <>
+struct ET<double2> {
+  typedef double R;
+  static constexpr int NC = 1;
+  __device__ __forceinline__ static void ld(const double2* p, long long i, zd (&z)[1]) {
+    double2 v = p[i];
+    z[0] = zd{v.x, v.y};
+  }
+  __device__ __forceinline__ static void st(double2* p, long long i, const zd (&z)[1]) {
+    p[i] = make_double2(z[0].re, z[0].im);
+  }
+};
+template <>
+struct ET<float4> {
+  typedef float R;
+  static constexpr int NC = 2;
+  __device__ __forceinline__ static void ld(const float4* p, long long i, zf (&z)[2]) {
+    float4 v = p[i];
+    z[0] = zf{v.x, v.y};
+    z[1] = zf{v.z, v.w};
+  }
+  __device__ __forceinline__ static void st(float4* p, long long i, const zf (&z)[2]) {
+    p[i] = make_float4(z[0].re, z[0].im, z[1].re, z[1].im);
+  }
+};
+
+template <typename R>
+__device__ __forceinline__ cx<R> narrow(zd a) {
+  return cx<R>{R(a.re), R(a.im)};
+}
+
+__device__ __forceinline__ bool fin(double v) { return isfinite(v); }
+
+// reduce the partials of every rhs (one wavefront per rhs) and apply `fn(rhs, a0, a1, a2)`
+template <typename Fn>
+__device__ void reduce_rhs(const VecSet& vs, const double* partials, Fn fn) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  constexpr int NW = BL_BS / 64;
+  for (int rhs = w; rhs < vs.nrhs; rhs += NW) {
+    const int nch = (vs.nelem[rhs] + BL_CHUNK - 1) / BL_CHUNK;
+    const double* pp = partials + (long long)rhs * vs.pstride * 3;
+    double a0 = 0, a1 = 0, a2 = 0;
+    for (int j = lane; j < nch; j += 64) {
+      a0 += pp[3 * j];
+      a1 += pp[3 * j + 1];
+      a2 += pp[3 * j + 2];
+    }
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    a2 = wave_sum(a2);
+    if (lane == 0) fn(rhs, a0, a1, a2);
+  }
+}
+
+__device__ __forceinline__ void store_partial(const VecSet& vs, double* partials, int rhs, int ch,
+                                              double (&red)[3]) {
+  __shared__ double sh[3 * (BL_BS / 64)];
+  block_sum<3, BL_BS>(red, sh);
+  if (threadIdx.x == 0) {
+    double* pp = partials + ((long long)rhs * vs.pstride + ch) * 3;
+    pp[0] = red[0];
+    pp[1] = red[1];
+    pp[2] = red[2];
+  }
+}
+
+// end of an iteration: rho_new = <rhat, r>, rr = ||r||^2
+__device__ void fin_xr(RhsScal& q, double a0, double a1, double a2) {
+  if (!q.active) return;
+  q.iters += 1;
+  q.rr = a2;
+  if (!fin(a0) || !fin(a1) || !fin(a2)) {
+    q.flags |= F_NAN;
+    q.active = 0;
+    return;
+  }
+  const zd rn{a0, a1};
+  if (a2 <= q.stop2) q.flags |= F_CONV;
+  if (q.delta2 > 0.0) {
+    if (a2 > q.rr_max) q.rr_max = a2;
+    if (a2 < q.delta2 * q.rr_max) q.flags |= F_RELIABLE;
+  }
+  if (norm2(rn) <= 1e-28 * q.rhat2 * a2) q.flags |= F_BREAK;
+  if (q.flags & F_OMEGA0) q.flags |= F_BREAK;
+  if (q.omega.re != 0.0 || q.omega.im != 0.0)
+    q.beta = cdiv(rn, q.rho) * cdiv(q.alpha, q.omega);
+  else
+    q.beta = zd{0.0, 0.0};
+  q.rho_prev = q.rho;
+  q.rho = rn;
+  if (q.flags & (F_CONV | F_RELIABLE | F_BREAK | F_NAN)) q.active = 0;
+}
+
+template <typename E, int OP>
+__global__ __launch_bounds__(BL_BS) void k_bicg_step(VecSet vs, E* __restrict__ x,
+                                                     E* __restrict__ r,
+                                                     const E* __restrict__ rhat,
+                                                     E* __restrict__ p, const E* __restrict__ v,
+                                                     const E* __restrict__ t,
+                                                     RhsScal* __restrict__ sc,
+                                                     double* __restrict__ partials,
+                                                     unsigned int* __restrict__ counter) {
+  typedef typename ET<E>::R R;
+  constexpr int NC = ET<E>::NC;
+  const int lb = xcd_block(blockIdx.x, vs.nblocks);
+  const int2 bm = vs.blk[lb];
+  const int rhs = bm.x, ch = bm.y;
+  const bool act = sc[rhs].active != 0;
+  double red[3] = {0.0, 0.0, 0.0};
+  if (act) {
+    const long long base = vs.off[rhs];
+    const int ne = vs.nelem[rhs];
+    const cx<R> al = narrow<R>(sc[rhs].alpha), om = narrow<R>(sc[rhs].omega),
+                be = narrow<R>(sc[rhs].beta);
+#pragma unroll
+    for (int e = 0; e < BL_EPT; ++e) {
+      const int idx = ch * BL_CHUNK + e * BL_BS + threadIdx.x;
+      if (idx < ne) {
+        const long long i = base + idx;
+        if (OP == BI_P) {
+          cx<R> rr[NC], pp[NC], vv[NC];
+          ET<E>::ld(r, i, rr);
+          ET<E>::ld(p, i, pp);
+          ET<E>::ld(v, i, vv);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) pp[c] = rr[c] + be * (pp[c] - om * vv[c]);
+          ET<E>::st(p, i, pp);
+        } else if (OP == BI_S) {
+          cx<R> rr[NC], vv[NC];
+          ET<E>::ld(r, i, rr);
+          ET<E>::ld(v, i, vv);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) rr[c] = rr[c] - al * vv[c];
+          ET<E>::st(r, i, rr);
+        } else {
+          cx<R> xx[NC], pp[NC], ss[NC], tt[NC], hh[NC];
+          ET<E>::ld(x, i, xx);
+          ET<E>::ld(p, i, pp);
+          ET<E>::ld(r, i, ss);
+          ET<E>::ld(t, i, tt);
+          ET<E>::ld(rhat, i, hh);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            xx[c] = xx[c] + al * pp[c] + om * ss[c];
+            ss[c] = ss[c] - om * tt[c];
+            const zd a{double(hh[c].re), double(hh[c].im)}, b{double(ss[c].re), double(ss[c].im)};
+            const zd d = cmulc(a, b);
+            red[0] += d.re;
+            red[1] += d.im;
+            red[2] += b.re * b.re + b.im * b.im;
+          }
+          ET<E>::st(x, i, xx);
+          ET<E>::st(r, i, ss);
+        }
+      }
+    }
+  }
+  if (OP == BI_XR) {
+    store_partial(vs, partials, rhs, ch, red);
+    if (last_block_arrive(counter, unsigned(vs.nblocks))) {
+      reduce_rhs(vs, partials, [&](int j, double a0, double a1, double a2) {
+        fin_xr(sc[j], a0, a1, a2);
+      });
+      last_block_reset(counter);
+    }
+  }
+}
+
+__device__ void fin_aux(int op, RhsScal& q, double a0, double a1, double a2) {
+  if (op == AX_INIT) {
+    if (!q.active) return;
+    q.rho = zd{a2, 0.0};
+    q.rhat2 = a2;
+    q.rr = a2;
+    q.rr_max = a2;
+    q.rho_prev = q.alpha = q.omega = zd{1.0, 0.0};
+    q.beta = zd{0.0, 0.0};
+    q.iters = 0;
+    q.flags = 0;
+    if (!fin(a2)) {
+      q.flags = F_NAN;
+      q.active = 0;
+    } else if (a2 <= q.stop2) {
+      q.flags = F_CONV;
+      q.active = 0;
+    }
+  } else if (op == AX_RESTART) {
+    if (!q.sel) return;
+    q.rho = zd{a2, 0.0};
+    q.rhat2 = a2;
+    q.rr = a2;
+    q.rho_prev = q.alpha = q.omega = zd{1.0, 0.0};
+    q.beta = zd{0.0, 0.0};
+    q.flags = 0;
+    q.active = 1;
+  } else {  // AX_REPLACE
+    if (!q.sel) return;
+    const zd rn{a0, a1};
+    if (q.omega.re != 0.0 || q.omega.im != 0.0)
+      q.beta = cdiv(rn, q.rho_prev) * cdiv(q.alpha, q.omega);
+    else
+      q.beta = zd{0.0, 0.0};
+    q.rho = rn;
+    q.rr = a2;
+    q.rr_max = a2;
+    q.flags = 0;
+    q.active = 1;
+    if (norm2(rn) <= 1e-28 * q.rhat2 * a2) {
+      q.flags = F_BREAK;
+      q.active = 0;
+    }
+  }
+}
+
+// FP64 working vectors
+template <int OP>
+__global__ __launch_bounds__(BL_BS) void k_aux64(VecSet vs, const double2* __restrict__ r64,
+                                                 double2* __restrict__ r,
+                                                 double2* __restrict__ rhat,
+                                                 double2* __restrict__ p, double2* __restrict__ v,
+                                                 RhsScal* __restrict__ sc,
+                                                 double* __restrict__ partials,
+                                                 unsigned int* __restrict__ counter) {
+  const int lb = xcd_block(blockIdx.x, vs.nblocks);
+  const int2 bm = vs.blk[lb];
+  const int rhs = bm.x, ch = bm.y;
+  const bool act = OP == AX_INIT ? sc[rhs].active != 0 : sc[rhs].sel != 0;
+  double red[3] = {0.0, 0.0, 0.0};
+  if (act) {
+    const long long base = vs.off[rhs];
+    const int ne = vs.nelem[rhs];
+    for (int e = 0; e < BL_EPT; ++e) {
+      const int idx = ch * BL_CHUNK + e * BL_BS + threadIdx.x;
+      if (idx >= ne) continue;
+      const long long i = base + idx;
+      if (OP == AX_REPLACE) {
+        const double2 a = r64[i];
+        r[i] = a;
+        const double2 h = rhat[i];
+        red[0] += h.x * a.x + h.y * a.y;
+        red[1] += h.x * a.y - h.y * a.x;
+        red[2] += a.x * a.x + a.y * a.y;
+      } else {
+        const double2 a = r[i];
+        rhat[i] = a;
+        p[i] = make_double2(0.0, 0.0);
+        v[i] = make_double2(0.0, 0.0);
+        red[2] += a.x * a.x + a.y * a.y;
+      }
+    }
+  }
+  store_partial(vs, partials, rhs, ch, red);
+  if (last_block_arrive(counter, unsigned(vs.nblocks))) {
+    reduce_rhs(vs, partials, [&](int j, double a0, double a1, double a2) {
+      fin_aux(OP, sc[j], a0, a1, a2);
+    });
+    last_block_reset(counter);
+  }
+}
+
+// FP32 working vectors fed from / narrowed from FP64 ones (element e <-> FP64 elements 2e, 2e+1)
+template <int OP>
+__global__ __launch_bounds__(BL_BS) void k_aux32(VecSet vs, VecSet vs64,
+                                                 const double2* __restrict__ r64,
+                                                 float4* __restrict__ r, float4* __restrict__ rhat,
+                                                 float4* __restrict__ p, float4* __restrict__ v,
+                                                 float4* __restrict__ x32,
+                                                 RhsScal* __restrict__ sc,
+                                                 double* __restrict__ partials,
+                                                 unsigned int* __restrict__ counter) {
+  const int lb = xcd_block(blockIdx.x, vs.nblocks);
+  const int2 bm = vs.blk[lb];
+  const int rhs = bm.x, ch = bm.y;
+  const bool act = OP == AX_INIT ? sc[rhs].active != 0 : sc[rhs].sel != 0;
+  double red[3] = {0.0, 0.0, 0.0};
+  if (act) {
+    const long long base = vs.off[rhs];
+    const long long base64 = vs64.off[rhs];
+    const int ne = vs.nelem[rhs];
+    for (int e = 0; e < BL_EPT; ++e) {
+      const int idx = ch * BL_CHUNK + e * BL_BS + threadIdx.x;
+      if (idx >= ne) continue;
+      const long long i = base + idx;
+      if (OP == AX_RESTART) {
+        const float4 a = r[i];
+        rhat[i] = a;
+        p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        red[2] += double(a.x) * a.x + double(a.y) * a.y + double(a.z) * a.z + double(a.w) * a.w;
+      } else {
+        const double2 d0 = r64[base64 + 2 * (long long)idx];
+        const double2 d1 = r64[base64 + 2 * (long long)idx + 1];
+        const float4 a = make_float4(float(d0.x), float(d0.y), float(d1.x), float(d1.y));
+        r[i] = a;
+        if (OP == AX_INIT) {
+          rhat[i] = a;
+          p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+          v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+          x32[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        } else {
+          const float4 h = rhat[i];
+          red[0] += double(h.x) * a.x + double(h.y) * a.y + double(h.z) * a.z + double(h.w) * a.w;
+          red[1] += double(h.x) * a.y - double(h.y) * a.x + double(h.z) * a.w - double(h.w) * a.z;
+        }
+        red[2] += double(a.x) * a.x + double(a.y) * a.y + double(a.z) * a.z + double(a.w) * a.w;
+      }
+    }
+  }
+  store_partial(vs, partials, rhs, ch, red);
+  if (last_block_arrive(counter, unsigned(vs.nblocks))) {
+    reduce_rhs(vs, partials, [&](int j, double a0, double a1, double a2) {
+      fin_aux(OP, sc[j], a0, a1, a2);
+    });
+    last_block_reset(counter);
+  }
+}
+
+__global__ __launch_bounds__(BL_BS) void k_xacc(VecSet vs, VecSet vs64, double2* __restrict__ x64,
+                                                float4* __restrict__ x32,
+                                                const RhsScal* __restrict__ sc) {
+  const int lb = xcd_block(blockIdx.x, vs.nblocks);
+  const int2 bm = vs.blk[lb];
+  const int rhs = bm.x, ch = bm.y;
+  if (!sc[rhs].sel) return;
+  const long long base = vs.off[rhs];
+  const long long base64 = vs64.off[rhs];
+  const int ne = vs.nelem[rhs];
+  for (int e = 0; e < BL_EPT; ++e) {
+    const int idx = ch * BL_CHUNK + e * BL_BS + threadIdx.x;
+    if (idx >= ne) continue;
+    const long long i = base + idx;
+    const float4 a = x32[i];
+    double2* d = x64 + base64 + 2 * (long long)idx;
+    double2 d0 = d[0], d1 = d[1];
+    d0.x += a.x;
+    d0.y += a.y;
+    d1.x += a.z;
+    d1.y += a.w;
+    d[0] = d0;
+    d[1] = d1;
+    x32[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
+template <typename E>
+void step(hipStream_t s, int op, const VecSet& vs, E* x, E* r, const E* rhat, E* p, const E* v,
+          const E* t, RhsScal* sc, double* partials, unsigned int* counter) {
+  dim3 g(vs.nblocks), b(BL_BS);
+  switch (op) {
+    case BI_P:
+      hipLaunchKernelGGL((k_bicg_step<E, BI_P>), g, b, 0, s, vs, x, r, rhat, p, v, t, sc,
+                         partials, counter);
+      break;
+    case BI_S:
+      hipLaunchKernelGGL((k_bicg_step<E, BI_S>), g, b, 0, s, vs, x, r, rhat, p, v, t, sc,
+                         partials, counter);
+      break;
+    default:
+      hipLaunchKernelGGL((k_bicg_step<E, BI_XR>), g, b, 0, s, vs, x, r, rhat, p, v, t, sc,
+                         partials, counter);
+      break;
+  }
+  DBQ_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void bicg_step_f64(hipStream_t s, int op, const VecSet& vs, double2* x, double2* r,
+                   const double2* rhat, double2* p, const double2* v, const double2* t,
+                   RhsScal* sc, double* partials, unsigned int* counter) {
+  step<double2>(s, op, vs, x, r, rhat, p, v, t, sc, partials, counter);
+}
+void bicg_step_f32(hipStream_t s, int op, const VecSet& vs, float4* x, float4* r,
+                   const float4* rhat, float4* p, const float4* v, const float4* t,
+                   RhsScal* sc, double* partials, unsigned int* counter) {
+  step<float4>(s, op, vs, x, r, rhat, p, v, t, sc, partials, counter);
+}
+
+void bicg_aux_f64(hipStream_t s, int op, const VecSet& vs, const double2* r64, double2* r,
+                  double2* rhat, double2* p, double2* v, RhsScal* sc, double* partials,
+                  unsigned int* counter) {
+  dim3 g(vs.nblocks), b(BL_BS);
+  if (op == AX_INIT)
+    hipLaunchKernelGGL((k_aux64<AX_INIT>), g, b, 0, s, vs, r64, r, rhat, p, v, sc, partials, counter);
+  else if (op == AX_RESTART)
+    hipLaunchKernelGGL((k_aux64<AX_RESTART>), g, b, 0, s, vs, r64, r, rhat, p, v, sc, partials,
+                       counter);
+  else
+    hipLaunchKernelGGL((k_aux64<AX_REPLACE>), g, b, 0, s, vs, r64, r, rhat, p, v, sc, partials,
+                       counter);
+  DBQ_HIP(hipGetLastError());
+}
+
+void bicg_aux_f32(hipStream_t s, int op, const VecSet& vs32, const VecSet& vs64,
+                  const double2* r64, float4* r, float4* rhat, float4* p, float4* v, float4* x32,
+                  RhsScal* sc, double* partials, unsigned int* counter) {
+  dim3 g(vs32.nblocks), b(BL_BS);
+  if (op == AX_INIT)
+    hipLaunchKernelGGL((k_aux32<AX_INIT>), g, b, 0, s, vs32, vs64, r64, r, rhat, p, v, x32, sc,
+                       partials, counter);
+  else if (op == AX_RESTART)
+    hipLaunchKernelGGL((k_aux32<AX_RESTART>), g, b, 0, s, vs32, vs64, r64, r, rhat, p, v, x32,
+                       sc, partials, counter);
+  else
+    hipLaunchKernelGGL((k_aux32<AX_REPLACE>), g, b, 0, s, vs32, vs64, r64, r, rhat, p, v, x32,
+                       sc, partials, counter);
+  DBQ_HIP(hipGetLastError());
+}
+
+void bicg_xacc(hipStream_t s, const VecSet& vs32, const VecSet& vs64, double2* x64, float4* x32,
+               const RhsScal* sc) {
+  hipLaunchKernelGGL(k_xacc, dim3(vs32.nblocks), dim3(BL_BS), 0, s, vs32, vs64, x64, x32, sc);
+  DBQ_HIP(hipGetLastError());
+}
+
+}  // namespace dbq

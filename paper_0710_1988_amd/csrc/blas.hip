@@ -1,0 +1,325 @@
+// Tall-skinny FP64 products for the deflation projection (Sec. 2: U^H A V, U^H r0, x0 + V y with
+// U = gamma5 V), the minimal-residual projection over previous solutions (Sec. 4) and the
+// Gram-Schmidt steps of GMRES-DR's Arnoldi process.  All of them stream long vectors once and
+// are bound by HBM bandwidth; the gamma5 of the left vectors is a sign folded into the loads.
+#include "kernels.h"
+
+namespace dbq {
+
+namespace {
+
+constexpr int G_BS = 256;
+constexpr int G_EPT = 8;
+constexpr int G_CHUNK = G_BS * G_EPT;
+
+__device__ __forceinline__ double g5sign(long long e, long long V, int g5) {
+  return (g5 && ((e / (6 * V)) & 1)) ? -1.0 : 1.0;
+}
+
+// Each block: one chunk of G_CHUNK rows x one (TA x TB) tile of (i, j) pairs.  Tile index is
+// the fastest-varying logical block index so that all tiles of a chunk run on one XCD and
+// re-read the chunk from its L2.
+template <int TA, int TB>
+__global__ __launch_bounds__(G_BS) void k_gram(const double2* __restrict__ A, long long lda, int na,
+                                               const double2* __restrict__ B, long long ldb, int nb,
+                                               long long n, long long V, int g5, int ntA, int ntB,
+                                               int nblocks, double* __restrict__ work) {
+  const int lb = xcd_block(blockIdx.x, nblocks);
+  const int ntiles = ntA * ntB;
+  const int chunk = lb / ntiles;
+  const int tile = lb - chunk * ntiles;
+  const int ta = tile / ntB, tb = tile - (tile / ntB) * ntB;
+  const int i0 = ta * TA, j0 = tb * TB;
+  double acc[TA][TB][2];
+#pragma unroll
+  for (int a = 0; a < TA; ++a)
+#pragma unroll
+    for (int b = 0; b < TB; ++b) acc[a][b][0] = acc[a][b][1] = 0.0;
+  for (int e = 0; e < G_EPT; ++e) {
+    const long long row = (long long)chunk * G_CHUNK + e * G_BS + threadIdx.x;
+    if (row >= n) break;
+    const double sg = g5sign(row, V, g5);
+    double2 bv[TB];
+#pragma unroll
+    for (int b = 0; b < TB; ++b)
+      bv[b] = (j0 + b < nb) ? B[(long long)(j0 + b) * ldb + row] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int a = 0; a < TA; ++a) {
+      double2 av = (i0 + a < na) ? A[(long long)(i0 + a) * lda + row] : make_double2(0.0, 0.0);
+      av.x *= sg;
+      av.y *= sg;
+#pragma unroll
+      for (int b = 0; b < TB; ++b) {
+        // conj(av) * bv
+        acc[a][b][0] += av.x * bv[b].x + av.y * bv[b].y;
+        acc[a][b][1] += av.x * bv[b].y - av.y * bv[b].x;
+      }
+    }
+  }
+  constexpr int NV = TA * TB * 2, NW = G_BS / 64;
+  __shared__ double sh[NV * NW];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int a = 0; a < TA; ++a)
+#pragma unroll
+    for (int b = 0; b < TB; ++b)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const double v = wave_sum(acc[a][b][q]);
+        if (lane == 0) sh[((a * TB + b) * 2 + q) * NW + w] = v;
+      }
+  __syncthreads();
+  double* out = work + ((long long)chunk * ntiles + tile) * NV;
+  for (int v = threadIdx.x; v < NV; v += G_BS) {
+    double s = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) s += sh[v * NW + k];
+    out[v] = s;
+  }
+}
+
+// C[i + j*na] = sum over chunks of the tile partials, in chunk order
+template <int TA, int TB>
+__global__ void k_gram_final(const double* __restrict__ work, int nchunks, int ntA, int ntB, int na,
+                             int nb, double2* __restrict__ C) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= na * nb) return;
+  const int i = id % na, j = id / na;
+  const int ta = i / TA, a = i - ta * TA, tb = j / TB, b = j - tb * TB;
+  const int tile = ta * ntB + tb, ntiles = ntA * ntB;
+  double re = 0, im = 0;
+  for (int c = 0; c < nchunks; ++c) {
+    const double* p = work + ((long long)c * ntiles + tile) * (TA * TB * 2) + (a * TB + b) * 2;
+    re += p[0];
+    im += p[1];
+  }
+  C[i + (long long)j * na] = make_double2(re, im);
+}
+
+template <int TA, int TB>
+void gram_impl(hipStream_t s, const double2* A, long long lda, int na, const double2* B,
+               long long ldb, int nb, long long n, long long V, int g5, double2* C, double* work,
+               size_t work_elems) {
+  const int nchunks = int((n + G_CHUNK - 1) / G_CHUNK);
+  const int ntA = (na + TA - 1) / TA, ntB = (nb + TB - 1) / TB;
+  const long long nblocks = (long long)nchunks * ntA * ntB;
+  DBQ_CHECK(size_t(nblocks) * TA * TB * 2 <= work_elems, "gram: workspace too small");
+  DBQ_CHECK(nblocks < (1ll << 31), "gram: too many blocks");
+  hipLaunchKernelGGL((k_gram<TA, TB>), dim3(unsigned(nblocks)), dim3(G_BS), 0, s, A, lda, na, B,
+                     ldb, nb, n, V, g5, ntA, ntB, int(nblocks), work);
+  DBQ_HIP(hipGetLastError());
+  const int tot = na * nb;
+  hipLaunchKernelGGL((k_gram_final<TA, TB>), dim3((tot + 127) / 128), dim3(128), 0, s, work,
+                     nchunks, ntA, ntB, na, nb, C);
+  DBQ_HIP(hipGetLastError());
+}
+
+// Y_j = beta*Y_j + sum_i sg(e) A_i M_ij for a tile of TB columns (grid.y) of Y
+template <int TB>
+__global__ __launch_bounds__(256) void k_combine(const double2* __restrict__ A, long long lda,
+                                                 int na, const double2* __restrict__ M, int ldm,
+                                                 double2* __restrict__ Y, long long ldy, int nb,
+                                                 long long n, long long V, int g5, int beta) {
+  const long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j0 = blockIdx.y * TB;
+  if (row >= n) return;
+  const double sg = g5sign(row, V, g5);
+  double acc[TB][2];
+#pragma unroll
+  for (int b = 0; b < TB; ++b) acc[b][0] = acc[b][1] = 0.0;
+  for (int i = 0; i < na; ++i) {
+    const double2 av = A[(long long)i * lda + row];
+#pragma unroll
+    for (int b = 0; b < TB; ++b) {
+      if (j0 + b < nb) {
+        const double2 m = M[i + (long long)(j0 + b) * ldm];
+        acc[b][0] += av.x * m.x - av.y * m.y;
+        acc[b][1] += av.x * m.y + av.y * m.x;
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < TB; ++b) {
+    if (j0 + b >= nb) continue;
+    double2* y = Y + (long long)(j0 + b) * ldy + row;
+    double2 o = make_double2(sg * acc[b][0], sg * acc[b][1]);
+    if (beta == 1) {
+      const double2 yv = *y;
+      o.x += yv.x;
+      o.y += yv.y;
+    } else if (beta == -1) {
+      const double2 yv = *y;
+      o.x = yv.x - o.x;
+      o.y = yv.y - o.y;
+    }
+    *y = o;
+  }
+}
+
+__global__ void k_scale(const double2* __restrict__ x, double2* __restrict__ y, long long n,
+                        const double* __restrict__ nrm2) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double f = 1.0 / sqrt(*nrm2);
+  const double2 v = x[i];
+  y[i] = make_double2(v.x * f, v.y * f);
+}
+
+__global__ __launch_bounds__(256) void k_norm2(const double2* __restrict__ x, long long ld,
+                                               long long n, int nchunks,
+                                               double* __restrict__ work) {
+  const int vec = blockIdx.y;
+  const int chunk = blockIdx.x;
+  double s[1] = {0.0};
+  for (int e = 0; e < G_EPT; ++e) {
+    const long long row = (long long)chunk * G_CHUNK + e * G_BS + threadIdx.x;
+    if (row < n) {
+      const double2 v = x[(long long)vec * ld + row];
+      s[0] += v.x * v.x + v.y * v.y;
+    }
+  }
+  __shared__ double sh[G_BS / 64];
+  block_sum<1, G_BS>(s, sh);
+  if (threadIdx.x == 0) work[(long long)vec * nchunks + chunk] = s[0];
+}
+
+__global__ void k_norm2_final(const double* __restrict__ work, int nchunks, int count,
+                              double* __restrict__ out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= count) return;
+  double s = 0;
+  for (int c = 0; c < nchunks; ++c) s += work[(long long)v * nchunks + c];
+  out[v] = s;
+}
+
+__global__ void k_copy(const double2* __restrict__ x, double2* __restrict__ y, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i];
+}
+
+__global__ void k_sub(const double2* __restrict__ a, const double2* __restrict__ b,
+                      double2* __restrict__ y, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const double2 u = a[i], v = b[i];
+    y[i] = make_double2(u.x - v.x, u.y - v.y);
+  }
+}
+
+__global__ void k_write_col(double2* __restrict__ M, int ld, int col, int count,
+                            const double2* __restrict__ h1, const double2* __restrict__ h2,
+                            const double* __restrict__ nrm2, int diag_row) {
+  const int i = threadIdx.x;
+  for (int r = i; r < count; r += blockDim.x) {
+    const double2 a = h1[r], b = h2[r];
+    M[r + (long long)col * ld] = make_double2(a.x + b.x, a.y + b.y);
+  }
+  if (i == 0) M[diag_row + (long long)col * ld] = make_double2(sqrt(*nrm2), 0.0);
+}
+
+__global__ void k_set_e1(double2* __restrict__ c, int len, const double* __restrict__ nrm2) {
+  for (int r = threadIdx.x; r < len; r += blockDim.x)
+    c[r] = make_double2(r == 0 ? sqrt(*nrm2) : 0.0, 0.0);
+}
+
+// deterministic start vector: splitmix64 of (seed, index) mapped to [-1, 1) per real component
+__global__ void k_fill_hash(double2* __restrict__ x, long long n, unsigned long long seed) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  unsigned long long z = seed + 0x9E3779B97F4A7C15ull * (unsigned long long)(i + 1);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  const double a = double(z >> 43) * (1.0 / 1048576.0) - 1.0;            // 21 bits
+  const double b = double((z >> 11) & 0xFFFFFull) * (1.0 / 524288.0) - 1.0;  // 20 bits
+  x[i] = make_double2(a, b);
+}
+
+__global__ void k_zero(double2* __restrict__ x, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = make_double2(0.0, 0.0);
+}
+
+inline unsigned nb256(long long n) { return unsigned((n + 255) / 256); }
+
+}  // namespace
+
+void write_col_f64(hipStream_t s, double2* M, int ld, int col, int count, const double2* h1,
+                   const double2* h2, const double* nrm2, int diag_row) {
+  hipLaunchKernelGGL(k_write_col, dim3(1), dim3(64), 0, s, M, ld, col, count, h1, h2, nrm2,
+                     diag_row);
+  DBQ_HIP(hipGetLastError());
+}
+
+void set_e1_f64(hipStream_t s, double2* c, int len, const double* nrm2) {
+  hipLaunchKernelGGL(k_set_e1, dim3(1), dim3(64), 0, s, c, len, nrm2);
+  DBQ_HIP(hipGetLastError());
+}
+
+void fill_hash_f64(hipStream_t s, double2* x, long long n, unsigned long long seed) {
+  hipLaunchKernelGGL(k_fill_hash, dim3(nb256(n)), dim3(256), 0, s, x, n, seed);
+  DBQ_HIP(hipGetLastError());
+}
+
+void zero_f64(hipStream_t s, double2* x, long long n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_zero, dim3(nb256(n)), dim3(256), 0, s, x, n);
+  DBQ_HIP(hipGetLastError());
+}
+
+size_t gram_work_elems(long long n, int na, int nb) {
+  const long long nchunks = (n + G_CHUNK - 1) / G_CHUNK;
+  // the larger of the two tilings
+  const long long t1 = nchunks * ((na + 7) / 8) * ((nb + 3) / 4) * 8 * 4 * 2;
+  const long long t2 = nchunks * ((na + 15) / 16) * 16 * 2;
+  return size_t(t1 > t2 ? t1 : t2);
+}
+
+void gram_f64(hipStream_t s, const double2* A, long long lda, int na, const double2* B,
+              long long ldb, int nb, long long n, long long V, int g5, double2* C, double* work,
+              size_t work_elems) {
+  if (na <= 0 || nb <= 0) return;
+  if (nb == 1)
+    gram_impl<16, 1>(s, A, lda, na, B, ldb, nb, n, V, g5, C, work, work_elems);
+  else
+    gram_impl<8, 4>(s, A, lda, na, B, ldb, nb, n, V, g5, C, work, work_elems);
+}
+
+void combine_f64(hipStream_t s, const double2* A, long long lda, int na, const double2* M, int ldm,
+                 double2* Y, long long ldy, int nb, long long n, long long V, int g5, int beta) {
+  if (nb <= 0) return;
+  if (na <= 0 && beta != 0) return;
+  constexpr int TB = 8;
+  dim3 grid(nb256(n), (nb + TB - 1) / TB);
+  hipLaunchKernelGGL((k_combine<TB>), grid, dim3(256), 0, s, A, lda, na, M, ldm, Y, ldy, nb, n, V,
+                     g5, beta);
+  DBQ_HIP(hipGetLastError());
+}
+
+void scale_f64(hipStream_t s, const double2* x, double2* y, long long n, const double* nrm2) {
+  hipLaunchKernelGGL(k_scale, dim3(nb256(n)), dim3(256), 0, s, x, y, n, nrm2);
+  DBQ_HIP(hipGetLastError());
+}
+
+void norm2_f64(hipStream_t s, const double2* x, long long ld, int count, long long n, double* out,
+               double* work, size_t work_elems) {
+  const int nchunks = int((n + G_CHUNK - 1) / G_CHUNK);
+  DBQ_CHECK(size_t(nchunks) * count <= work_elems, "norm2: workspace too small");
+  hipLaunchKernelGGL(k_norm2, dim3(nchunks, count), dim3(G_BS), 0, s, x, ld, n, nchunks, work);
+  DBQ_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_norm2_final, dim3((count + 63) / 64), dim3(64), 0, s, work, nchunks, count,
+                     out);
+  DBQ_HIP(hipGetLastError());
+}
+
+void copy_f64(hipStream_t s, const double2* x, double2* y, long long n) {
+  hipLaunchKernelGGL(k_copy, dim3(nb256(n)), dim3(256), 0, s, x, y, n);
+  DBQ_HIP(hipGetLastError());
+}
+
+void sub_f64(hipStream_t s, const double2* a, const double2* b, double2* y, long long n) {
+  hipLaunchKernelGGL(k_sub, dim3(nb256(n)), dim3(256), 0, s, a, b, y, n);
+  DBQ_HIP(hipGetLastError());
+}
+
+}  // namespace dbq

@@ -1,0 +1,219 @@
+// Shared device/host helpers of the dbq library: errors, complex arithmetic, even-odd lattice
+// indexing, XCD-aware block numbering and deterministic block reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+#include "dbq.h"
+
+namespace dbq {
+
+// ----------------------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define DBQ_HIP(call)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      throw ::dbq::Error(DBQ_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+#define DBQ_CHECK(cond, msg)                                   \
+  do {                                                         \
+    if (!(cond)) throw ::dbq::Error(DBQ_EINVAL, (msg));        \
+  } while (0)
+
+// ----------------------------------------------------------------------------- complex
+template <typename T>
+struct cx {
+  T re, im;
+};
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator-(cx<T> a) { return {-a.re, -a.im}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.re, s * a.im}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
+// conj(a) * b
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+// i * a
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> ti(cx<T> a) { return {-a.im, a.re}; }
+template <typename T>
+__host__ __device__ __forceinline__ T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cdiv(cx<T> a, cx<T> b) {
+  // Smith's algorithm keeps the intermediate quotient in range
+  if (fabs(b.re) >= fabs(b.im)) {
+    T r = b.im / b.re, d = b.re + b.im * r;
+    return {(a.re + a.im * r) / d, (a.im - a.re * r) / d};
+  } else {
+    T r = b.re / b.im, d = b.re * r + b.im;
+    return {(a.re * r + a.im) / d, (a.im * r - a.re) / d};
+  }
+}
+typedef cx<double> zd;
+typedef cx<float> zf;
+
+// ----------------------------------------------------------------------------- fast division
+// q = n / d for 0 <= n < 2^31 via a 32-bit magic multiplier (round-up method of Granlund and
+// Montgomery): l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1, q = (umulhi(n, m) + n) >> l.
+struct FastDiv {
+  uint32_t d, m, l;
+  FastDiv() : d(1), m(1), l(0) {}
+  explicit FastDiv(uint32_t dv) : d(dv) {
+    l = 0;
+    while ((1ull << l) < dv) ++l;
+    uint64_t t = ((1ull << 32) * ((1ull << l) - dv)) / dv;
+    m = uint32_t(t + 1);
+  }
+  __host__ __device__ __forceinline__ uint32_t div(uint32_t n) const {
+#if defined(__HIP_DEVICE_COMPILE__)
+    uint32_t hi = __umulhi(n, m);
+#else
+    uint32_t hi = uint32_t((uint64_t(n) * m) >> 32);
+#endif
+    return (hi + n) >> l;
+  }
+};
+
+// ----------------------------------------------------------------------------- lattice geometry
+// Even-odd order of the full lattice: eo = p*V/2 + (lex >> 1), p = (x+y+z+t) & 1.  Since Lx is
+// even, lex >> 1 = x/2 + (Lx/2)*(y + Ly*(z + Lz*t)) and each value is taken once per parity.
+struct Geom {
+  int L[4];
+  int V, Vh, Lxh;
+  FastDiv dLxh, dLy, dLz;
+};
+
+inline Geom make_geom(const int32_t L[4]) {
+  Geom g;
+  for (int i = 0; i < 4; ++i) g.L[i] = L[i];
+  g.V = L[0] * L[1] * L[2] * L[3];
+  g.Vh = g.V / 2;
+  g.Lxh = L[0] / 2;
+  g.dLxh = FastDiv(uint32_t(g.Lxh));
+  g.dLy = FastDiv(uint32_t(L[1]));
+  g.dLz = FastDiv(uint32_t(L[2]));
+  return g;
+}
+
+// coordinates (x, y, z, t) and parity of even-odd index s
+__host__ __device__ __forceinline__ void eo_coords(const Geom& g, int s, int c[4], int& p) {
+  p = s >= g.Vh ? 1 : 0;
+  uint32_t h = uint32_t(s - p * g.Vh);
+  uint32_t r = g.dLxh.div(h);
+  int xh = int(h - r * uint32_t(g.Lxh));
+  uint32_t r2 = g.dLy.div(r);
+  c[1] = int(r - r2 * uint32_t(g.L[1]));
+  uint32_t r3 = g.dLz.div(r2);
+  c[2] = int(r2 - r3 * uint32_t(g.L[2]));
+  c[3] = int(r3);
+  c[0] = 2 * xh + ((p + c[1] + c[2] + c[3]) & 1);
+}
+
+__host__ __device__ __forceinline__ int lex_index(const Geom& g, const int c[4]) {
+  return c[0] + g.L[0] * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3]));
+}
+
+__host__ __device__ __forceinline__ int eo_of_coords(const Geom& g, const int c[4]) {
+  int p = (c[0] + c[1] + c[2] + c[3]) & 1;
+  return p * g.Vh + (lex_index(g, c) >> 1);
+}
+
+// eo index of the neighbour x + dir*mu (dir = +1 or -1), periodic
+template <int MU, int DIR>
+__host__ __device__ __forceinline__ int eo_neighbour(const Geom& g, const int c[4]) {
+  int d[4] = {c[0], c[1], c[2], c[3]};
+  int v = d[MU] + DIR;
+  if (DIR > 0) v = (v == g.L[MU]) ? 0 : v;
+  else v = (v < 0) ? g.L[MU] - 1 : v;
+  d[MU] = v;
+  return eo_of_coords(g, d);
+}
+
+// ----------------------------------------------------------------------------- launch helpers
+// Workgroups are dispatched round-robin over the 8 XCDs of an MI355X, each with its own L2.
+// Renumber so that each XCD receives one contiguous range of logical blocks (neighbouring
+// sites, and all right-hand sides of one site block, then share an L2).  A bijection of
+// [0, n) for any n.
+__device__ __forceinline__ int xcd_block(int b, int n) {
+  constexpr int NX = 8;
+  int q = n / NX, r = n % NX;
+  int x = b % NX, loc = b / NX;
+  int start = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+  return start + loc;
+}
+
+// sum over a 64-lane wavefront, fixed butterfly order (deterministic)
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-wide sum of NV doubles per thread; result valid in thread 0. Fixed order.
+template <int NV, int BS>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* sh /* [NV * BS/64] */) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  constexpr int NW = BS / 64;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) sh[i * NW + w] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double s = 0;
+      for (int j = 0; j < NW; ++j) s += sh[i * NW + j];
+      v[i] = s;
+    }
+  }
+}
+
+// Last-block detection: every block has stored its partials; returns true in the block that
+// finishes last (all others' partials are then visible after the acquire fence).
+__device__ __forceinline__ bool last_block_arrive(unsigned int* counter, unsigned int nblocks) {
+  __shared__ int s_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned int old = atomicAdd(counter, 1u);
+    s_last = (old == nblocks - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (s_last) {
+    __threadfence();
+    return true;
+  }
+  return false;
+}
+
+__device__ __forceinline__ void last_block_reset(unsigned int* counter) {
+  if (threadIdx.x == 0) atomicExch(counter, 0u);
+}
+
+}  // namespace dbq

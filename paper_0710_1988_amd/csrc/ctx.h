@@ -1,0 +1,71 @@
+// Library context: stream, workspace pool, pinned staging buffer, kernel timing.
+#pragma once
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+struct dbq_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+
+  // ---- workspace pool: device buffers kept across calls, handed out per call
+  struct Buf {
+    void* p;
+    size_t bytes;
+    bool busy;
+  };
+  std::vector<Buf> pool;
+
+  // ---- pinned host staging for scalar readbacks
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+
+  // ---- timing of Dslash launches (kind 0 = FP64, 1 = FP32)
+  bool timing = false;
+  struct Timer {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;  // recorded, not yet read
+    std::vector<hipEvent_t> spare;
+    double ms = 0;
+    int64_t n = 0;
+    double bytes = 0;
+  } timers[2];
+
+  // ---- geometry-independent counters for the last-block reductions (one per kernel class)
+  unsigned int* counters = nullptr;  // device, NCOUNTERS entries, kept zero between launches
+};
+
+namespace dbq {
+
+constexpr int NCOUNTERS = 64;
+
+void* ws_get(dbq_ctx* c, size_t bytes);
+void ws_release(dbq_ctx* c, void* p);
+void* pinned_get(dbq_ctx* c, size_t bytes);
+unsigned int* counter(dbq_ctx* c, int i);
+
+// RAII: everything taken from the pool inside a scope is returned at its end
+struct WsScope {
+  dbq_ctx* c;
+  size_t mark;
+  WsScope(const WsScope&) = delete;
+  WsScope& operator=(const WsScope&) = delete;
+  explicit WsScope(dbq_ctx* ctx);
+  ~WsScope();
+  template <typename T>
+  T* get(size_t count) {
+    return reinterpret_cast<T*>(take(count * sizeof(T)));
+  }
+  void* take(size_t bytes);
+  std::vector<size_t> taken;
+};
+
+// timing brackets around one Dslash launch
+void timer_begin(dbq_ctx* c, int kind, hipEvent_t* ev_out);
+void timer_end(dbq_ctx* c, int kind, hipEvent_t ev_begin, double bytes);
+void timer_collect(dbq_ctx* c);
+
+}  // namespace dbq

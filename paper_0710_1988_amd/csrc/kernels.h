@@ -1,0 +1,187 @@
+// Host-side launchers of the dbq device kernels and the data structures they share.
+//
+// Internal storage (device, per right-hand side), sites in even-odd order:
+//   FP64 spinor : double2 [6][V][2]    element (k, s, j) = component c = 2k + j (c = 3*spin + colour)
+//   FP32 spinor : float4  [6][V]       element (j, s) = components 2j and 2j+1 at site s
+//   FP64 links  : double2 [4][9][V]    U_mu(s)[a][b] at ((mu*9 + 3a + b)*V + s)
+//   FP32 links  : float4  [4][3][V]    rows 0 and 1 of U_mu(s) (12 reals); row 2 = conj(row0 x row1)
+// Consecutive threads touch consecutive sites, so every load and store is coalesced; FP32 element
+// e of a vector holds the same two components as FP64 elements 2e and 2e+1, and the second half
+// of every vector holds spins 2 and 3 (gamma5 = -1) in both precisions.
+#pragma once
+
+#include "common.h"
+
+namespace dbq {
+
+// ----------------------------------------------------------------------------- per-rhs solver state
+enum : int {
+  F_CONV = 1,      // recursive residual below the stopping threshold
+  F_RELIABLE = 2,  // mixed precision: residual dropped by delta since the last FP64 update
+  F_BREAK = 4,     // rho or <rhat, v> vanished: restart with rhat <- r
+  F_OMEGA0 = 8,    // omega = 0 in this iteration (restart after the update)
+  F_NAN = 16,      // non-finite reduction
+};
+
+struct RhsScal {
+  zd rho, rho_prev, alpha, omega, beta;
+  zd dot;          // last <rhat, v>
+  double rr;       // recursive ||r||^2
+  double rr_true;  // last FP64 ||b - A x||^2
+  double rr_max;   // largest rr since the last reliable update
+  double bb;       // ||b||^2
+  double stop2;    // tol^2 * bb
+  double delta2;   // reliable-update threshold squared (0: none)
+  double rhat2;    // ||rhat||^2
+  int active;      // iterate this rhs
+  int sel;         // selected for a host-requested operation
+  int flags;
+  int iters;
+};
+
+// ----------------------------------------------------------------------------- batches
+constexpr int MAXLAT = 8;
+constexpr int DS_BS = 256;  // Dslash threads per block = sites per block
+
+struct DsLat {
+  Geom g;
+  const void* links;
+  const void* in;   // [nrhs][.][V]
+  void* out;
+  const void* aux;  // epilogue input with the layout of `in` (rhat, b) or null
+  int nrhs;
+  int rhs_base;     // global rhs index of this lattice's first rhs
+  int nsb;          // site blocks per rhs
+  int blk_begin;    // first logical block of this lattice
+  double kappa, mu;
+};
+
+struct DsBatch {
+  DsLat lat[MAXLAT];
+  int nlat;
+  int nblocks;
+  int nrhs_total;
+  int pstride;  // partial-sum slots per rhs
+};
+
+enum Epi : int { EPI_NONE = 0, EPI_RHAT = 1, EPI_TS = 2, EPI_RESID = 3 };
+
+// Vector-set description for BLAS-1 kernels over all right-hand sides of a batch.
+struct VecSet {
+  const long long* off;  // element offset of rhs j (device)
+  const int* nelem;      // elements of rhs j (device)
+  const int2* blk;       // per block: (rhs, chunk index) (device)
+  int nblocks;
+  int nrhs;
+  int pstride;           // partial slots per rhs (>= max chunks)
+};
+constexpr int BL_BS = 256;     // BLAS-1 threads per block
+constexpr int BL_EPT = 4;      // elements per thread
+constexpr int BL_CHUNK = BL_BS * BL_EPT;
+
+// ----------------------------------------------------------------------------- pack.hip
+void launch_geometry(hipStream_t s, const Geom& g, int32_t* lex_of_eo, int32_t* nbr);
+void pack_spinor_f64(hipStream_t s, const Geom& g, const void* canon, double2* out, int nrhs);
+void unpack_spinor_f64(hipStream_t s, const Geom& g, const double2* in, void* canon, int nrhs);
+void pack_spinor_f32(hipStream_t s, const Geom& g, const void* canon, float4* out, int nrhs);
+void unpack_spinor_f32(hipStream_t s, const Geom& g, const float4* in, void* canon, int nrhs);
+void pack_links_f64(hipStream_t s, const Geom& g, const void* canon, double2* out);
+void pack_links_f32(hipStream_t s, const Geom& g, const void* canon, float4* out);
+// gamma5 applied to packed FP64 vectors (count vectors of 12V elements), out may equal in
+void gamma5_f64(hipStream_t s, const double2* in, double2* out, long long V, int count);
+
+// ----------------------------------------------------------------------------- dslash.hip
+// Returns algorithmic HBM bytes of the launch (links once, input once, output once, plus
+// epilogue operands).
+double launch_dslash_f64(hipStream_t s, const DsBatch& b, int dagger, int epi, RhsScal* sc,
+                         double* partials, unsigned int* counter);
+double launch_dslash_f32(hipStream_t s, const DsBatch& b, int dagger, int epi, RhsScal* sc,
+                         double* partials, unsigned int* counter);
+
+// ----------------------------------------------------------------------------- bicg.hip
+enum BicgOp : int { BI_P = 0, BI_S = 1, BI_XR = 2 };
+// FP64 vectors (double2 elements) or FP32 vectors (float4 elements)
+void bicg_step_f64(hipStream_t s, int op, const VecSet& vs, double2* x, double2* r,
+                   const double2* rhat, double2* p, const double2* v, const double2* t,
+                   RhsScal* sc, double* partials, unsigned int* counter);
+void bicg_step_f32(hipStream_t s, int op, const VecSet& vs, float4* x, float4* r,
+                   const float4* rhat, float4* p, const float4* v, const float4* t,
+                   RhsScal* sc, double* partials, unsigned int* counter);
+// init: r (FP64) -> working r (copy or narrowed), rhat = r, p = v = 0, x32 = 0 (mixed),
+//       rho = ||r||^2 ... ; mode 0: all rhs with active != 0; uses `sel` when only_sel
+enum BicgAux : int { AX_INIT = 0, AX_RESTART = 1, AX_REPLACE = 2 };
+void bicg_aux_f64(hipStream_t s, int op, const VecSet& vs, const double2* r64, double2* r,
+                  double2* rhat, double2* p, double2* v, RhsScal* sc, double* partials,
+                  unsigned int* counter);
+void bicg_aux_f32(hipStream_t s, int op, const VecSet& vs32, const VecSet& vs64,
+                  const double2* r64, float4* r, float4* rhat, float4* p, float4* v, float4* x32,
+                  RhsScal* sc, double* partials, unsigned int* counter);
+// x64 += widen(x32), x32 = 0 for rhs with sel != 0
+void bicg_xacc(hipStream_t s, const VecSet& vs32, const VecSet& vs64, double2* x64, float4* x32,
+               const RhsScal* sc);
+
+// ----------------------------------------------------------------------------- blas.hip (FP64)
+// Tall-skinny products over vectors of n elements (double2):
+//   C[i + j*na] = sum_e conj(A_i[e]) * sg(e) * B_j[e]   (sg = -1 for components 6..11 when g5)
+// A_i at A + i*lda, B_j at B + j*ldb.  V = sites (for the gamma5 sign: element e of a vector is
+// component e / V).
+void gram_f64(hipStream_t s, const double2* A, long long lda, int na, const double2* B,
+              long long ldb, int nb, long long n, long long V, int g5, double2* C, double* work,
+              size_t work_elems);
+size_t gram_work_elems(long long n, int na, int nb);
+// Y_j (+)= sum_i A_i * (sg) * M[i + j*ldm] for j < nb; beta = 0 overwrites Y, 1 accumulates,
+// -1 subtracts (Y_j -= sum ...).  Y_j at Y + j*ldy.
+void combine_f64(hipStream_t s, const double2* A, long long lda, int na, const double2* M, int ldm,
+                 double2* Y, long long ldy, int nb, long long n, long long V, int g5, int beta);
+// y = alpha * x (complex scalar from device memory, optional reciprocal of a real norm)
+void scale_f64(hipStream_t s, const double2* x, double2* y, long long n, const double* inv_norm_of);
+// ||x||^2 per vector (count vectors of n elements, stride ld) into out[count] (device)
+void norm2_f64(hipStream_t s, const double2* x, long long ld, int count, long long n, double* out,
+               double* work, size_t work_elems);
+// y = x (count vectors)
+void copy_f64(hipStream_t s, const double2* x, double2* y, long long n);
+// y = a - b
+void sub_f64(hipStream_t s, const double2* a, const double2* b, double2* y, long long n);
+// M[0..count-1][col] = h1 + h2, M[diag_row][col] = sqrt(*nrm2)  (Arnoldi / Gram-Schmidt column)
+void write_col_f64(hipStream_t s, double2* M, int ld, int col, int count, const double2* h1,
+                   const double2* h2, const double* nrm2, int diag_row);
+// c = sqrt(*nrm2) e_1 (length len)
+void set_e1_f64(hipStream_t s, double2* c, int len, const double* nrm2);
+// deterministic pseudo-random vector (splitmix64 hash of the element index)
+void fill_hash_f64(hipStream_t s, double2* x, long long n, unsigned long long seed);
+// x = 0 with a kernel (safe inside captured graphs)
+void zero_f64(hipStream_t s, double2* x, long long n);
+
+// ----------------------------------------------------------------------------- dense.hip
+// Small dense FP64 linear algebra on one workgroup.
+// LU with partial pivoting of M (k x k, column-major) and solve M Y = C (k x nrhs); Y overwrites C.
+// Writes the 1-norm condition number to cond (device double).
+void dense_lu_solve(hipStream_t s, const double2* M, int k, double2* C, int nrhs, double2* work,
+                    double* cond);
+// GMRES-DR / Arnoldi cycle end, see dense.hip for the meaning of the modes.
+struct CycleArgs {
+  const double2* Hbar;  // (m+1) x m column-major, ld = m+1
+  const double2* c;     // m+1
+  int m, k;
+  int mode;             // 0: GMRES-DR restart, 1: GMRES-DR final vectors, 2: Ritz (largest Re)
+  double tol_abs;       // convergence threshold on ||rho|| (modes 0, 1)
+  double2* d;           // out: m least-squares coefficients (modes 0, 1)
+  double2* P;           // out: (m+1) x (k+1) column-major restart / output basis
+  double2* Hnew;        // out: (k+1) x k, ld = m+1 (written into the first k columns)
+  double2* cnew;        // out: m+1
+  double2* theta;       // out: m eigenvalues sorted
+  double* info;         // out: [0] ||rho||, [1] k_out, [2] converged flag, [3] ritz residual of
+                        //      theta[0] (mode 2), [4] eigen-solver failure flag
+  double2* work;        // scratch, dense_cycle_work(m) elements
+};
+size_t dense_cycle_work(int m);
+void dense_cycle(hipStream_t s, const CycleArgs& a);
+// small triangular solve / matvec helpers used by project_shifts
+void dense_trsolve_upper(hipStream_t s, const double2* R, int ldr, int n, double2* z, int nrhs,
+                         int ldz);
+
+// ----------------------------------------------------------------------------- force.hip
+void launch_link_force(hipStream_t s, const Geom& g, const void* links, double kappa,
+                       const void* lambda, const void* x, int nrhs, int kind, void* F);
+
+}  // namespace dbq

@@ -1,0 +1,878 @@
+// Host drivers of the solvers: D-BiCGStab(k) (Sec. 2), GMRES-DR(m,k) for the first right-hand side
+// (Sec. 1 and Sec. 3), kappa_c (Sec. 3), the minimal-residual projection over previous shifts'
+// solutions (Sec. 4), and the operator apply.  Every arithmetic step runs in the kernels; the
+// host decides control flow from a few scalars read back at check points.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "ctx.h"
+#include "kernels.h"
+#include "solvers.h"
+
+namespace dbq {
+
+namespace {
+
+enum : int { C_XR = 1, C_RHAT = 2, C_TS = 3, C_RESID = 4, C_AUX = 5 };
+
+struct Op {
+  Geom g;
+  double kappa = 0, mu = 0;
+  double2* l64 = nullptr;
+  float4* l32 = nullptr;
+  long long n() const { return 12LL * g.V; }
+};
+
+void check_op(const dbq_operator* o) {
+  DBQ_CHECK(o != nullptr, "null operator");
+  long long V = 1;
+  for (int i = 0; i < 4; ++i) {
+    DBQ_CHECK(o->L[i] >= 2 && o->L[i] % 2 == 0, "lattice extents must be even and >= 2");
+    V *= o->L[i];
+  }
+  DBQ_CHECK(V <= (1ll << 27), "lattice too large (V > 2^27)");
+  DBQ_CHECK(o->links != nullptr, "null links");
+  DBQ_CHECK(std::isfinite(o->kappa) && std::isfinite(o->mu), "non-finite kappa or mu");
+}
+
+Op make_op(dbq_ctx* c, WsScope& ws, const dbq_operator* o, bool f64, bool f32) {
+  Op op;
+  op.g = make_geom(o->L);
+  op.kappa = o->kappa;
+  op.mu = o->mu;
+  if (f64) {
+    op.l64 = ws.get<double2>(36LL * op.g.V);
+    pack_links_f64(c->stream, op.g, o->links, op.l64);
+  }
+  if (f32) {
+    op.l32 = ws.get<float4>(12LL * op.g.V);
+    pack_links_f32(c->stream, op.g, o->links, op.l32);
+  }
+  return op;
+}
+
+struct DsSpec {
+  const Op* op;
+  bool f32;
+  const void* in;
+  void* out;
+  const void* aux;
+  int nrhs;
+  int rhs_base;
+};
+
+DsBatch make_batch(const std::vector<DsSpec>& v) {
+  DBQ_CHECK(!v.empty() && v.size() <= size_t(MAXLAT), "batch: 1..8 lattices");
+  DsBatch b;
+  std::memset(&b, 0, sizeof(b));
+  b.nlat = int(v.size());
+  int blk = 0, nr = 0, ps = 1;
+  for (size_t i = 0; i < v.size(); ++i) {
+    DsLat& L = b.lat[i];
+    L.g = v[i].op->g;
+    L.links = v[i].f32 ? (const void*)v[i].op->l32 : (const void*)v[i].op->l64;
+    L.in = v[i].in;
+    L.out = v[i].out;
+    L.aux = v[i].aux;
+    L.nrhs = v[i].nrhs;
+    L.rhs_base = v[i].rhs_base;
+    L.nsb = (L.g.V + DS_BS - 1) / DS_BS;
+    L.blk_begin = blk;
+    L.kappa = v[i].op->kappa;
+    L.mu = v[i].op->mu;
+    blk += L.nsb * L.nrhs;
+    nr = std::max(nr, L.rhs_base + L.nrhs);
+    ps = std::max(ps, L.nsb);
+  }
+  b.nblocks = blk;
+  b.nrhs_total = nr;
+  b.pstride = ps;
+  return b;
+}
+
+void run_dslash(dbq_ctx* c, bool f32, const DsBatch& b, int dagger, int epi, RhsScal* sc,
+                double* partials, int ctr) {
+  hipEvent_t e0;
+  timer_begin(c, f32 ? 1 : 0, &e0);
+  const double bytes =
+      f32 ? launch_dslash_f32(c->stream, b, dagger, epi, sc, partials, counter(c, ctr))
+          : launch_dslash_f64(c->stream, b, dagger, epi, sc, partials, counter(c, ctr));
+  timer_end(c, f32 ? 1 : 0, e0, bytes);
+}
+
+template <typename T>
+T* upload(dbq_ctx* c, WsScope& ws, const std::vector<T>& h) {
+  T* d = ws.get<T>(std::max<size_t>(h.size(), 1));
+  if (!h.empty()) {
+    DBQ_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    DBQ_HIP(hipStreamSynchronize(c->stream));
+  }
+  return d;
+}
+
+VecSet make_vecset(dbq_ctx* c, WsScope& ws, const std::vector<int>& nelem) {
+  std::vector<long long> off(nelem.size());
+  std::vector<int2> blk;
+  long long o = 0;
+  int ps = 1;
+  for (size_t j = 0; j < nelem.size(); ++j) {
+    off[j] = o;
+    o += nelem[j];
+    const int nch = (nelem[j] + BL_CHUNK - 1) / BL_CHUNK;
+    ps = std::max(ps, nch);
+    for (int ch = 0; ch < nch; ++ch) blk.push_back(make_int2(int(j), ch));
+  }
+  DBQ_CHECK(blk.size() < (size_t(1) << 31), "vector set too large");
+  VecSet vs;
+  vs.off = upload(c, ws, off);
+  vs.nelem = upload(c, ws, nelem);
+  vs.blk = upload(c, ws, blk);
+  vs.nblocks = int(blk.size());
+  vs.nrhs = int(nelem.size());
+  vs.pstride = ps;
+  return vs;
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+size_t norm_work(long long n, int count) { return size_t((n + 2047) / 2048) * size_t(count) + 64; }
+
+}  // namespace
+
+// ============================================================================ operator apply
+void apply_operator(dbq_ctx* c, const dbq_operator* o, const void* in, void* out, int nrhs,
+                    int dagger, int prec) {
+  check_op(o);
+  DBQ_CHECK(in && out, "null vector");
+  DBQ_CHECK(in != out, "in and out must not alias");
+  DBQ_CHECK(nrhs >= 1, "nrhs must be >= 1");
+  DBQ_CHECK(prec == DBQ_FP64 || prec == DBQ_MIXED, "bad precision");
+  WsScope ws(c);
+  const bool f32 = prec == DBQ_MIXED;
+  Op op = make_op(c, ws, o, !f32, f32);
+  const long long V = op.g.V;
+  if (!f32) {
+    double2* a = ws.get<double2>(12LL * V * nrhs);
+    double2* b = ws.get<double2>(12LL * V * nrhs);
+    pack_spinor_f64(c->stream, op.g, in, a, nrhs);
+    DsBatch bt = make_batch({DsSpec{&op, false, a, b, nullptr, nrhs, 0}});
+    run_dslash(c, false, bt, dagger, EPI_NONE, nullptr, nullptr, 0);
+    unpack_spinor_f64(c->stream, op.g, b, out, nrhs);
+  } else {
+    float4* a = ws.get<float4>(6LL * V * nrhs);
+    float4* b = ws.get<float4>(6LL * V * nrhs);
+    pack_spinor_f32(c->stream, op.g, in, a, nrhs);
+    DsBatch bt = make_batch({DsSpec{&op, true, a, b, nullptr, nrhs, 0}});
+    run_dslash(c, true, bt, dagger, EPI_NONE, nullptr, nullptr, 0);
+    unpack_spinor_f32(c->stream, op.g, b, out, nrhs);
+  }
+}
+
+// ============================================================================ D-BiCGStab(k)
+int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* Vin,
+              const int32_t* kk, const void* const* B, void* const* X, const int32_t* nrhs,
+              double tol, int64_t max_mv, int prec, int dagger, dbq_stats* st) {
+  const double t0 = now_s();
+  DBQ_CHECK(nops >= 1 && nops <= MAXLAT, "nops must be in 1..8");
+  DBQ_CHECK(ops && kk && B && X && nrhs && st, "null argument");
+  DBQ_CHECK(tol > 0 && std::isfinite(tol), "tol must be positive");
+  DBQ_CHECK(max_mv >= 1, "max_mv must be >= 1");
+  DBQ_CHECK(prec == DBQ_FP64 || prec == DBQ_MIXED, "bad precision");
+  for (int i = 0; i < nops; ++i) {
+    check_op(&ops[i]);
+    DBQ_CHECK(nrhs[i] >= 1, "nrhs must be >= 1");
+    DBQ_CHECK(kk[i] >= 0 && kk[i] <= 128, "k must be in 0..128");
+    DBQ_CHECK(kk[i] == 0 || (Vin && Vin[i]), "null deflation vectors");
+    DBQ_CHECK(B[i] && X[i], "null right-hand side or solution");
+  }
+  hipStream_t s = c->stream;
+  const bool mixed = prec == DBQ_MIXED;
+  WsScope ws(c);
+  std::vector<Op> op(nops);
+  for (int i = 0; i < nops; ++i) op[i] = make_op(c, ws, &ops[i], true, mixed);
+
+  // ---- right-hand-side bookkeeping
+  std::vector<int> base(nops), lat_of;
+  std::vector<int> ne64, ne32;
+  std::vector<long long> off64, off32;
+  int NR = 0;
+  long long tot64 = 0, tot32 = 0;
+  for (int i = 0; i < nops; ++i) {
+    base[i] = NR;
+    for (int r = 0; r < nrhs[i]; ++r) {
+      lat_of.push_back(i);
+      ne64.push_back(int(op[i].n()));
+      ne32.push_back(int(op[i].n() / 2));
+      off64.push_back(tot64);
+      off32.push_back(tot32);
+      tot64 += op[i].n();
+      tot32 += op[i].n() / 2;
+      ++NR;
+    }
+  }
+  double2* b64 = ws.get<double2>(tot64);
+  double2* x64 = ws.get<double2>(tot64);
+  double2* r64 = ws.get<double2>(tot64);
+  for (int i = 0; i < nops; ++i) {
+    pack_spinor_f64(s, op[i].g, B[i], b64 + off64[base[i]], nrhs[i]);
+    pack_spinor_f64(s, op[i].g, X[i], x64 + off64[base[i]], nrhs[i]);
+  }
+  VecSet vs64 = make_vecset(c, ws, ne64);
+  VecSet vs32{};
+  if (mixed) vs32 = make_vecset(c, ws, ne32);
+
+  // ---- scratch for reductions
+  int pstride = std::max(vs64.pstride, mixed ? vs32.pstride : 1);
+  for (int i = 0; i < nops; ++i) pstride = std::max(pstride, (op[i].g.V + DS_BS - 1) / DS_BS);
+  double* partials = ws.get<double>(size_t(NR) * pstride * 3);
+  RhsScal* sc = ws.get<RhsScal>(NR);
+  // pinned host area: scalars | norms | cond
+  const size_t pin_bytes = sizeof(RhsScal) * NR + sizeof(double) * (2 * NR + MAXLAT) + 256;
+  char* pin = (char*)pinned_get(c, pin_bytes);
+  RhsScal* hs = (RhsScal*)pin;
+  double* hn = (double*)(pin + sizeof(RhsScal) * NR);
+  double* hcond = hn + 2 * NR;
+  auto pull = [&]() {
+    DBQ_HIP(hipMemcpyAsync(hs, sc, sizeof(RhsScal) * NR, hipMemcpyDeviceToHost, s));
+    DBQ_HIP(hipStreamSynchronize(s));
+  };
+  auto push = [&]() {
+    DBQ_HIP(hipMemcpyAsync(sc, hs, sizeof(RhsScal) * NR, hipMemcpyHostToDevice, s));
+  };
+
+  // ---- norms of b and x0
+  double* dn = ws.get<double>(2 * NR);
+  long long maxn = 0;
+  int maxr = 1;
+  for (int i = 0; i < nops; ++i) {
+    maxn = std::max(maxn, op[i].n());
+    maxr = std::max(maxr, nrhs[i]);
+  }
+  size_t nw = norm_work(maxn, maxr);
+  double* nwork = ws.get<double>(nw);
+  for (int i = 0; i < nops; ++i) {
+    norm2_f64(s, b64 + off64[base[i]], op[i].n(), nrhs[i], op[i].n(), dn + base[i], nwork, nw);
+    norm2_f64(s, x64 + off64[base[i]], op[i].n(), nrhs[i], op[i].n(), dn + NR + base[i], nwork, nw);
+  }
+  DBQ_HIP(hipMemcpyAsync(hn, dn, sizeof(double) * 2 * NR, hipMemcpyDeviceToHost, s));
+  DBQ_HIP(hipStreamSynchronize(s));
+
+  std::vector<long long> mvb(NR, 0);
+  std::vector<int> status(NR, DBQ_NOT_CONVERGED), restarts(NR, 0), relup(NR, 0);
+  std::vector<char> done(NR, 0), have_true(NR, 0);
+  std::vector<double> rrt(NR, 0.0);
+  std::memset(hs, 0, sizeof(RhsScal) * NR);
+  bool any_x0 = false;
+  for (int j = 0; j < NR; ++j) {
+    RhsScal& q = hs[j];
+    q.bb = hn[j];
+    q.stop2 = tol * tol * hn[j];
+    q.delta2 = mixed ? 0.01 : 0.0;  // reliable update when ||r|| drops by 10x
+    q.sel = hn[NR + j] > 0.0 ? 1 : 0;
+    if (q.sel) {
+      any_x0 = true;
+      mvb[j] += 1;
+    }
+    q.active = 0;
+    if (!std::isfinite(hn[j]) || !std::isfinite(hn[NR + j]))
+      throw Error(DBQ_EINVAL, "non-finite right-hand side or initial guess");
+  }
+  push();
+
+  // ---- r0 = b - A x0
+  double2* rt = mixed ? r64 : ws.get<double2>(tot64);  // FP64 true-residual target
+  std::vector<DsSpec> sres, sx0;
+  for (int i = 0; i < nops; ++i) {
+    const long long o = off64[base[i]];
+    sx0.push_back(DsSpec{&op[i], false, x64 + o, r64 + o, b64 + o, nrhs[i], base[i]});
+    sres.push_back(DsSpec{&op[i], false, x64 + o, rt + o, b64 + o, nrhs[i], base[i]});
+  }
+  const DsBatch bx0 = make_batch(sx0), bres = make_batch(sres);
+  copy_f64(s, b64, r64, tot64);
+  if (any_x0) run_dslash(c, false, bx0, dagger, EPI_RESID, sc, partials, C_RESID);
+
+  // ---- deflation: (U^H A V) y = U^H r0, x0 += V y with U = gamma5 V (roles swapped for A^H)
+  bool any_defl = false;
+  double* dcond = ws.get<double>(MAXLAT);
+  for (int i = 0; i < nops; ++i) {
+    const int k = kk[i];
+    if (k == 0) continue;
+    any_defl = true;
+    const long long n = op[i].n(), V = op[i].g.V;
+    const long long o = off64[base[i]];
+    double2* Vp = ws.get<double2>(k * n);
+    pack_spinor_f64(s, op[i].g, Vin[i], Vp, k);
+    const double2* right = Vp;
+    if (dagger) {
+      double2* R5 = ws.get<double2>(k * n);
+      gamma5_f64(s, Vp, R5, V, k);
+      right = R5;
+    }
+    double2* W = ws.get<double2>(k * n);
+    const DsBatch bw = make_batch({DsSpec{&op[i], false, right, W, nullptr, k, 0}});
+    run_dslash(c, false, bw, dagger, EPI_NONE, nullptr, nullptr, 0);
+    const size_t gw = gram_work_elems(n, k, std::max(k, nrhs[i]));
+    double* gwork = ws.get<double>(gw);
+    double2* M = ws.get<double2>(k * k);
+    double2* Cm = ws.get<double2>(k * nrhs[i]);
+    gram_f64(s, Vp, n, k, W, n, k, n, V, dagger ? 0 : 1, M, gwork, gw);
+    gram_f64(s, Vp, n, k, r64 + o, n, nrhs[i], n, V, dagger ? 0 : 1, Cm, gwork, gw);
+    double2* lw = ws.get<double2>(2 * k * k + k);
+    dense_lu_solve(s, M, k, Cm, nrhs[i], lw, dcond + i);
+    combine_f64(s, Vp, n, k, Cm, k, x64 + o, n, nrhs[i], n, V, dagger ? 1 : 0, 1);
+    DBQ_HIP(hipMemcpyAsync(hcond + i, dcond + i, sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  if (any_defl) {
+    DBQ_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < nops; ++i)
+      if (kk[i] > 0 && !(hcond[i] <= 1e12))
+        throw Error(DBQ_ESINGULAR, "projected matrix U^H A V is numerically singular (cond " +
+                                       std::to_string(hcond[i]) + ")");
+    // r = b - A x after the projection (one MVP per rhs)
+    pull();
+    for (int j = 0; j < NR; ++j) {
+      hs[j].sel = kk[lat_of[j]] > 0 ? 1 : 0;
+      if (hs[j].sel) mvb[j] += 1;
+    }
+    push();
+    run_dslash(c, false, bx0, dagger, EPI_RESID, sc, partials, C_RESID);
+  }
+
+  // ---- BiCGStab working vectors
+  double2 *rhat = nullptr, *p = nullptr, *v = nullptr, *t = nullptr;
+  float4 *x32 = nullptr, *r32 = nullptr, *rhat32 = nullptr, *p32 = nullptr, *v32 = nullptr,
+         *t32 = nullptr;
+  if (mixed) {
+    x32 = ws.get<float4>(tot32);
+    r32 = ws.get<float4>(tot32);
+    rhat32 = ws.get<float4>(tot32);
+    p32 = ws.get<float4>(tot32);
+    v32 = ws.get<float4>(tot32);
+    t32 = ws.get<float4>(tot32);
+  } else {
+    rhat = ws.get<double2>(tot64);
+    p = ws.get<double2>(tot64);
+    v = ws.get<double2>(tot64);
+    t = ws.get<double2>(tot64);
+  }
+  std::vector<DsSpec> sv, stt;
+  for (int i = 0; i < nops; ++i) {
+    if (mixed) {
+      const long long o = off32[base[i]];
+      sv.push_back(DsSpec{&op[i], true, p32 + o, v32 + o, rhat32 + o, nrhs[i], base[i]});
+      stt.push_back(DsSpec{&op[i], true, r32 + o, t32 + o, nullptr, nrhs[i], base[i]});
+    } else {
+      const long long o = off64[base[i]];
+      sv.push_back(DsSpec{&op[i], false, p + o, v + o, rhat + o, nrhs[i], base[i]});
+      stt.push_back(DsSpec{&op[i], false, r64 + o, t + o, nullptr, nrhs[i], base[i]});
+    }
+  }
+  const DsBatch bv = make_batch(sv), bt = make_batch(stt);
+
+  pull();
+  for (int j = 0; j < NR; ++j) {
+    hs[j].sel = 0;
+    if (hs[j].bb == 0.0) {
+      done[j] = 1;
+      status[j] = DBQ_OK;
+      have_true[j] = 1;
+      rrt[j] = 0.0;
+      hs[j].active = 0;
+      zero_f64(s, x64 + off64[j], ne64[j]);
+    } else {
+      hs[j].active = 1;
+    }
+  }
+  push();
+  if (mixed)
+    bicg_aux_f32(s, AX_INIT, vs32, vs64, r64, r32, rhat32, p32, v32, x32, sc, partials,
+                 counter(c, C_AUX));
+  else
+    bicg_aux_f64(s, AX_INIT, vs64, r64, r64, rhat, p, v, sc, partials, counter(c, C_AUX));
+
+  auto iterate = [&]() {
+    if (mixed) {
+      bicg_step_f32(s, BI_P, vs32, x32, r32, rhat32, p32, v32, t32, sc, partials, counter(c, C_XR));
+      run_dslash(c, true, bv, dagger, EPI_RHAT, sc, partials, C_RHAT);
+      bicg_step_f32(s, BI_S, vs32, x32, r32, rhat32, p32, v32, t32, sc, partials, counter(c, C_XR));
+      run_dslash(c, true, bt, dagger, EPI_TS, sc, partials, C_TS);
+      bicg_step_f32(s, BI_XR, vs32, x32, r32, rhat32, p32, v32, t32, sc, partials, counter(c, C_XR));
+    } else {
+      bicg_step_f64(s, BI_P, vs64, x64, r64, rhat, p, v, t, sc, partials, counter(c, C_XR));
+      run_dslash(c, false, bv, dagger, EPI_RHAT, sc, partials, C_RHAT);
+      bicg_step_f64(s, BI_S, vs64, x64, r64, rhat, p, v, t, sc, partials, counter(c, C_XR));
+      run_dslash(c, false, bt, dagger, EPI_TS, sc, partials, C_TS);
+      bicg_step_f64(s, BI_XR, vs64, x64, r64, rhat, p, v, t, sc, partials, counter(c, C_XR));
+    }
+  };
+
+  int nchk = 1;
+  bool first = true;
+  while (true) {
+    if (!first)
+      for (int it = 0; it < nchk; ++it) iterate();
+    first = false;
+    pull();
+    std::vector<int> A, Bk, Cc;
+    bool any_active = false;
+    for (int j = 0; j < NR; ++j) {
+      if (done[j]) continue;
+      const RhsScal& q = hs[j];
+      const long long mv = mvb[j] + 2LL * q.iters;
+      if (q.flags & F_NAN) {
+        done[j] = 1;
+        status[j] = DBQ_EBREAKDOWN;
+        Cc.push_back(j);
+      } else if (q.flags & (F_CONV | F_RELIABLE)) {
+        A.push_back(j);
+      } else if (q.flags & F_BREAK) {
+        Bk.push_back(j);
+      } else if (mv >= max_mv) {
+        Cc.push_back(j);
+      }
+      if (q.active) any_active = true;
+    }
+    if (A.empty() && Bk.empty() && Cc.empty()) {
+      if (!any_active) break;
+      nchk = std::min(nchk * 2, 16);
+      continue;
+    }
+    nchk = 1;
+    // (1) convergence claims and reliable updates: FP64 residual of the accumulated solution
+    if (!A.empty()) {
+      for (int j = 0; j < NR; ++j) hs[j].sel = 0;
+      for (int j : A) hs[j].sel = 1;
+      push();
+      if (mixed) bicg_xacc(s, vs32, vs64, x64, x32, sc);
+      run_dslash(c, false, bres, dagger, EPI_RESID, sc, partials, C_RESID);
+      pull();
+      bool any_rep = false;
+      for (int j : A) {
+        mvb[j] += 1;
+        if (mixed) relup[j] += 1;
+        rrt[j] = hs[j].rr_true;
+        have_true[j] = 1;
+        const long long mv = mvb[j] + 2LL * hs[j].iters;
+        if (hs[j].rr_true <= hs[j].stop2) {
+          done[j] = 1;
+          status[j] = DBQ_OK;
+          hs[j].sel = 0;
+          hs[j].active = 0;
+        } else if (mv >= max_mv || !std::isfinite(hs[j].rr_true)) {
+          done[j] = 1;
+          status[j] = std::isfinite(hs[j].rr_true) ? DBQ_NOT_CONVERGED : DBQ_EBREAKDOWN;
+          hs[j].sel = 0;
+          hs[j].active = 0;
+        } else {
+          any_rep = true;
+          have_true[j] = 0;
+        }
+      }
+      push();
+      if (any_rep) {
+        if (mixed)
+          bicg_aux_f32(s, AX_REPLACE, vs32, vs64, r64, r32, rhat32, p32, v32, x32, sc, partials,
+                       counter(c, C_AUX));
+        else
+          bicg_aux_f64(s, AX_REPLACE, vs64, rt, r64, rhat, p, v, sc, partials, counter(c, C_AUX));
+      }
+    }
+    // (2) breakdowns: restart with rhat <- r
+    if (!Bk.empty()) {
+      pull();
+      for (int j = 0; j < NR; ++j) hs[j].sel = 0;
+      bool any = false;
+      for (int j : Bk) {
+        if (done[j]) continue;
+        restarts[j] += 1;
+        if (restarts[j] > 10) {
+          done[j] = 1;
+          status[j] = DBQ_EBREAKDOWN;
+          hs[j].active = 0;
+        } else {
+          hs[j].sel = 1;
+          any = true;
+        }
+      }
+      push();
+      if (any) {
+        if (mixed)
+          bicg_aux_f32(s, AX_RESTART, vs32, vs64, r64, r32, rhat32, p32, v32, x32, sc, partials,
+                       counter(c, C_AUX));
+        else
+          bicg_aux_f64(s, AX_RESTART, vs64, r64, r64, rhat, p, v, sc, partials, counter(c, C_AUX));
+      }
+    }
+    // (3) out of matrix-vector products
+    if (!Cc.empty()) {
+      pull();
+      for (int j = 0; j < NR; ++j) hs[j].sel = 0;
+      for (int j : Cc) {
+        done[j] = 1;
+        if (status[j] != DBQ_EBREAKDOWN) status[j] = DBQ_NOT_CONVERGED;
+        hs[j].active = 0;
+      }
+      push();
+    }
+  }
+
+  // ---- final solution and residuals of the rhs that ended without one
+  pull();
+  bool need = false;
+  for (int j = 0; j < NR; ++j) {
+    hs[j].sel = 1;  // accumulate any FP32 correction that is left
+    hs[j].active = 0;
+  }
+  push();
+  if (mixed) bicg_xacc(s, vs32, vs64, x64, x32, sc);
+  pull();
+  for (int j = 0; j < NR; ++j) {
+    hs[j].sel = have_true[j] ? 0 : 1;
+    need = need || !have_true[j];
+  }
+  push();
+  if (need) {
+    run_dslash(c, false, bres, dagger, EPI_RESID, sc, partials, C_RESID);
+    pull();
+    for (int j = 0; j < NR; ++j)
+      if (!have_true[j]) rrt[j] = hs[j].rr_true;
+  }
+  for (int i = 0; i < nops; ++i)
+    unpack_spinor_f64(s, op[i].g, x64 + off64[base[i]], X[i], nrhs[i]);
+  DBQ_HIP(hipStreamSynchronize(s));
+  timer_collect(c);
+  const double secs = now_s() - t0;
+  int worst = DBQ_OK;
+  for (int j = 0; j < NR; ++j) {
+    dbq_stats& o = st[j];
+    o.matvecs = mvb[j] + 2LL * hs[j].iters;
+    o.iterations = hs[j].iters;
+    o.restarts = restarts[j];
+    o.reliable_updates = relup[j];
+    o.rel_true_resid = hs[j].bb > 0 ? std::sqrt(rrt[j] / hs[j].bb) : 0.0;
+    o.seconds = secs;
+    o.status = status[j];
+    o.pad = 0;
+    if (status[j] < 0) worst = std::min(worst, status[j]);
+    else if (worst >= 0) worst = std::max(worst, status[j]);
+  }
+  return worst;
+}
+
+// ============================================================================ Arnoldi machinery
+namespace {
+
+struct Arnoldi {
+  dbq_ctx* c;
+  const Op* op;
+  int m;
+  long long n, V;
+  double2 *Vb, *Vb2;  // (m+1) x n bases
+  double2 *Hbar, *Hnew, *cv, *cnew;
+  double2 *d, *P, *theta, *h1, *h2, *dwork;
+  double *info, *nrm, *gwork, *nwork;
+  size_t gw, nw;
+  int dagger = 0;
+  int64_t mv = 0;
+
+  Arnoldi(dbq_ctx* ctx, WsScope& ws, const Op* o, int mm, int k) : c(ctx), op(o), m(mm) {
+    n = o->n();
+    V = o->g.V;
+    const int m1 = m + 1;
+    Vb = ws.get<double2>(size_t(m1) * n);
+    Vb2 = ws.get<double2>(size_t(m1) * n);
+    Hbar = ws.get<double2>(size_t(m1) * m);
+    Hnew = ws.get<double2>(size_t(m1) * m);
+    cv = ws.get<double2>(m1);
+    cnew = ws.get<double2>(m1);
+    d = ws.get<double2>(m);
+    P = ws.get<double2>(size_t(m1) * (k + 1));
+    theta = ws.get<double2>(m);
+    h1 = ws.get<double2>(m1);
+    h2 = ws.get<double2>(m1);
+    dwork = ws.get<double2>(dense_cycle_work(m));
+    info = ws.get<double>(8);
+    nrm = ws.get<double>(4);
+    gw = gram_work_elems(n, m1, 1);
+    gwork = ws.get<double>(gw);
+    nw = norm_work(n, 1);
+    nwork = ws.get<double>(nw);
+    zero_f64(c->stream, Hbar, size_t(m1) * m);
+  }
+
+  double2* col(int j) { return Vb + size_t(j) * n; }
+
+  // extend the Arnoldi relation from column j0 to m with CGS2
+  void extend(int j0) {
+    hipStream_t s = c->stream;
+    for (int j = j0; j < m; ++j) {
+      const DsBatch b = make_batch({DsSpec{op, false, col(j), col(j + 1), nullptr, 1, 0}});
+      run_dslash(c, false, b, dagger, EPI_NONE, nullptr, nullptr, 0);
+      ++mv;
+      double2* w = col(j + 1);
+      gram_f64(s, Vb, n, j + 1, w, n, 1, n, V, 0, h1, gwork, gw);
+      combine_f64(s, Vb, n, j + 1, h1, j + 1, w, n, 1, n, V, 0, -1);
+      gram_f64(s, Vb, n, j + 1, w, n, 1, n, V, 0, h2, gwork, gw);
+      combine_f64(s, Vb, n, j + 1, h2, j + 1, w, n, 1, n, V, 0, -1);
+      norm2_f64(s, w, n, 1, n, nrm, nwork, nw);
+      write_col_f64(s, Hbar, m + 1, j, j + 1, h1, h2, nrm, j + 1);
+      scale_f64(s, w, w, n, nrm);
+    }
+  }
+
+  void cycle_end(int k, int mode, double tol_abs) {
+    CycleArgs a;
+    a.Hbar = Hbar;
+    a.c = cv;
+    a.m = m;
+    a.k = k;
+    a.mode = mode;
+    a.tol_abs = tol_abs;
+    a.d = d;
+    a.P = P;
+    a.Hnew = Hnew;
+    a.cnew = cnew;
+    a.theta = theta;
+    a.info = info;
+    a.work = dwork;
+    zero_f64(c->stream, Hnew, size_t(m + 1) * m);
+    dense_cycle(c->stream, a);
+  }
+
+  // V_{k+1} = V_{m+1} P_{k+1}; Hbar <- Hnew; c <- cnew
+  void restart(int k) {
+    combine_f64(c->stream, Vb, n, m + 1, P, m + 1, Vb2, n, k + 1, n, V, 0, 0);
+    std::swap(Vb, Vb2);
+    std::swap(Hbar, Hnew);
+    std::swap(cv, cnew);
+  }
+};
+
+}  // namespace
+
+// ============================================================================ GMRES-DR(m,k)
+int gmresdr(dbq_ctx* c, const dbq_operator* o, const void* b, void* x, int m, int k, double tol,
+            int64_t max_mv, void* Vout, double* theta, int32_t* k_out, dbq_stats* st) {
+  const double t0 = now_s();
+  check_op(o);
+  DBQ_CHECK(b && x && Vout && theta && k_out && st, "null argument");
+  DBQ_CHECK(k >= 2 && k < m && m <= 128, "need 2 <= k < m <= 128");
+  DBQ_CHECK(tol > 0 && std::isfinite(tol), "tol must be positive");
+  DBQ_CHECK(max_mv >= 1, "max_mv must be >= 1");
+  hipStream_t s = c->stream;
+  WsScope ws(c);
+  Op op = make_op(c, ws, o, true, false);
+  const long long n = op.n();
+  double2* b64 = ws.get<double2>(n);
+  double2* x64 = ws.get<double2>(n);
+  double2* tmp = ws.get<double2>(n);
+  pack_spinor_f64(s, op.g, b, b64, 1);
+  pack_spinor_f64(s, op.g, x, x64, 1);
+  Arnoldi ar(c, ws, &op, m, k);
+  double* dn = ws.get<double>(4);
+  double* hp = (double*)pinned_get(c, 64 * sizeof(double) + 2 * 128 * sizeof(double2));
+  norm2_f64(s, b64, n, 1, n, dn, ar.nwork, ar.nw);
+  norm2_f64(s, x64, n, 1, n, dn + 1, ar.nwork, ar.nw);
+  DBQ_HIP(hipMemcpyAsync(hp, dn, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  DBQ_HIP(hipStreamSynchronize(s));
+  const double bn = std::sqrt(hp[0]);
+  DBQ_CHECK(std::isfinite(hp[0]) && std::isfinite(hp[1]), "non-finite b or x0");
+  DBQ_CHECK(bn > 0, "b must be nonzero");
+  // r0 -> v_1, c = ||r0|| e_1
+  if (hp[1] > 0) {
+    const DsBatch bb = make_batch({DsSpec{&op, false, x64, tmp, nullptr, 1, 0}});
+    run_dslash(c, false, bb, 0, EPI_NONE, nullptr, nullptr, 0);
+    sub_f64(s, b64, tmp, ar.col(0), n);
+    ar.mv += 1;
+  } else {
+    copy_f64(s, b64, ar.col(0), n);
+  }
+  norm2_f64(s, ar.col(0), n, 1, n, ar.nrm, ar.nwork, ar.nw);
+  set_e1_f64(s, ar.cv, m + 1, ar.nrm);
+  scale_f64(s, ar.col(0), ar.col(0), n, ar.nrm);
+  int j0 = 0, cycles = 0;
+  bool conv = false;
+  while (true) {
+    ar.extend(j0);
+    ++cycles;
+    ar.cycle_end(k, 0, tol * bn);
+    combine_f64(s, ar.Vb, n, m, ar.d, m, x64, n, 1, n, op.g.V, 0, 1);
+    DBQ_HIP(hipMemcpyAsync(hp, ar.info, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+    DBQ_HIP(hipStreamSynchronize(s));
+    conv = hp[2] != 0.0;
+    if (!std::isfinite(hp[0])) throw Error(DBQ_EBREAKDOWN, "GMRES-DR residual is not finite");
+    if (conv || ar.mv >= max_mv) break;
+    if (hp[4] != 0.0) throw Error(DBQ_EBREAKDOWN, "harmonic Ritz eigensolver did not converge");
+    ar.restart(k);
+    j0 = k;
+  }
+  // eigenvector output of the last cycle (harmonic Ritz, conjugate-closed k)
+  ar.cycle_end(k, 1, tol * bn);
+  DBQ_HIP(hipMemcpyAsync(hp, ar.info, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+  double2* th_h = (double2*)(hp + 64);
+  DBQ_HIP(hipMemcpyAsync(th_h, ar.theta, sizeof(double2) * m, hipMemcpyDeviceToHost, s));
+  DBQ_HIP(hipStreamSynchronize(s));
+  const int kout = int(hp[1]);
+  double2* Vint = ws.get<double2>(size_t(kout) * n);
+  combine_f64(s, ar.Vb, n, m, ar.P, m + 1, Vint, n, kout, n, op.g.V, 0, 0);
+  unpack_spinor_f64(s, op.g, Vint, Vout, kout);
+  unpack_spinor_f64(s, op.g, x64, x, 1);
+  for (int i = 0; i < kout; ++i) {
+    theta[2 * i] = th_h[i].x;
+    theta[2 * i + 1] = th_h[i].y;
+  }
+  for (int i = kout; i < k; ++i) theta[2 * i] = theta[2 * i + 1] = 0.0;
+  *k_out = kout;
+  // true residual for the statistics (not charged as a matrix-vector product)
+  const DsBatch bb = make_batch({DsSpec{&op, false, x64, tmp, nullptr, 1, 0}});
+  run_dslash(c, false, bb, 0, EPI_NONE, nullptr, nullptr, 0);
+  sub_f64(s, b64, tmp, tmp, n);
+  norm2_f64(s, tmp, n, 1, n, dn + 2, ar.nwork, ar.nw);
+  DBQ_HIP(hipMemcpyAsync(hp, dn + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+  DBQ_HIP(hipStreamSynchronize(s));
+  timer_collect(c);
+  st->matvecs = ar.mv;
+  st->iterations = cycles;
+  st->restarts = cycles - 1;
+  st->reliable_updates = 0;
+  st->rel_true_resid = std::sqrt(hp[0]) / bn;
+  st->seconds = now_s() - t0;
+  st->status = conv ? DBQ_OK : DBQ_NOT_CONVERGED;
+  st->pad = 0;
+  return st->status;
+}
+
+// ============================================================================ kappa_c
+int kappa_crit(dbq_ctx* c, const int32_t L[4], const void* links, int m, int k, double tol,
+               int64_t max_mv, double* kappa_c, double* lambda, double* resid) {
+  DBQ_CHECK(L && links && kappa_c && lambda && resid, "null argument");
+  DBQ_CHECK(k >= 2 && k < m && m <= 128, "need 2 <= k < m <= 128");
+  dbq_operator o;
+  for (int i = 0; i < 4; ++i) o.L[i] = L[i];
+  o.links = links;
+  o.kappa = -1.0;  // apply I + H: same eigenvectors, eigenvalues shifted by one
+  o.mu = 0.0;
+  check_op(&o);
+  hipStream_t s = c->stream;
+  WsScope ws(c);
+  Op op = make_op(c, ws, &o, true, false);
+  const long long n = op.n();
+  Arnoldi ar(c, ws, &op, m, k);
+  double* hp = (double*)pinned_get(c, 64 * sizeof(double) + 2 * 128 * sizeof(double2));
+  fill_hash_f64(s, ar.col(0), n, 0x5DEECE66Dull);
+  norm2_f64(s, ar.col(0), n, 1, n, ar.nrm, ar.nwork, ar.nw);
+  scale_f64(s, ar.col(0), ar.col(0), n, ar.nrm);
+  int j0 = 0;
+  double lam_re = 0, lam_im = 0, res = INFINITY;
+  while (true) {
+    ar.extend(j0);
+    ar.cycle_end(k, 2, 0.0);
+    DBQ_HIP(hipMemcpyAsync(hp, ar.info, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+    double2* th_h = (double2*)(hp + 64);
+    DBQ_HIP(hipMemcpyAsync(th_h, ar.theta, sizeof(double2), hipMemcpyDeviceToHost, s));
+    DBQ_HIP(hipStreamSynchronize(s));
+    if (hp[4] != 0.0) throw Error(DBQ_EBREAKDOWN, "Ritz eigensolver did not converge");
+    lam_re = th_h[0].x - 1.0;
+    lam_im = th_h[0].y;
+    res = hp[3];
+    if (res <= tol * std::hypot(th_h[0].x, th_h[0].y) || ar.mv >= max_mv) break;
+    ar.restart(k);
+    j0 = k;
+  }
+  timer_collect(c);
+  lambda[0] = lam_re;
+  lambda[1] = lam_im;
+  *resid = res;
+  *kappa_c = 1.0 / lam_re;
+  return (res <= tol * std::hypot(lam_re + 1.0, lam_im)) ? DBQ_OK : DBQ_NOT_CONVERGED;
+}
+
+// ============================================================================ MR projection
+int mr_project(dbq_ctx* c, const dbq_operator* o, const void* Q, int nq, const void* B, void* X0,
+               int nrhs, double* rn) {
+  check_op(o);
+  DBQ_CHECK(Q && B && X0 && rn, "null argument");
+  DBQ_CHECK(nq >= 1 && nq <= 32, "nq must be in 1..32");
+  DBQ_CHECK(nrhs >= 1, "nrhs must be >= 1");
+  hipStream_t s = c->stream;
+  WsScope ws(c);
+  Op op = make_op(c, ws, o, true, false);
+  const long long n = op.n(), V = op.g.V;
+  double2* b64 = ws.get<double2>(size_t(nrhs) * n);
+  double2* x64 = ws.get<double2>(size_t(nrhs) * n);
+  double2* r64 = ws.get<double2>(size_t(nrhs) * n);
+  double2* Qp = ws.get<double2>(size_t(nrhs) * nq * n);
+  double2* W = ws.get<double2>(size_t(nrhs) * nq * n);
+  pack_spinor_f64(s, op.g, B, b64, nrhs);
+  pack_spinor_f64(s, op.g, X0, x64, nrhs);
+  pack_spinor_f64(s, op.g, Q, Qp, nrhs * nq);
+  // r0 = b - A x0, W = A Q
+  const DsBatch bx = make_batch({DsSpec{&op, false, x64, r64, nullptr, nrhs, 0}});
+  run_dslash(c, false, bx, 0, EPI_NONE, nullptr, nullptr, 0);
+  sub_f64(s, b64, r64, r64, size_t(nrhs) * n);
+  const DsBatch bq = make_batch({DsSpec{&op, false, Qp, W, nullptr, nrhs * nq, 0}});
+  run_dslash(c, false, bq, 0, EPI_NONE, nullptr, nullptr, 0);
+  const size_t gw = gram_work_elems(n, nq, 1);
+  double* gwork = ws.get<double>(gw);
+  const size_t nw = norm_work(n, nrhs);
+  double* nwork = ws.get<double>(nw);
+  double2* h1 = ws.get<double2>(nq);
+  double2* h2 = ws.get<double2>(nq);
+  double2* R = ws.get<double2>(size_t(nq) * nq);
+  double2* z = ws.get<double2>(nq);
+  double* nrm = ws.get<double>(2 * nrhs + 2);
+  norm2_f64(s, r64, n, nrhs, n, nrm, nwork, nw);
+  for (int j = 0; j < nrhs; ++j) {
+    double2* Wj = W + size_t(j) * nq * n;
+    const double2* Qj = Qp + size_t(j) * nq * n;
+    double2* rj = r64 + size_t(j) * n;
+    zero_f64(s, R, size_t(nq) * nq);
+    // W = Qw R (classical Gram-Schmidt twice)
+    for (int q = 0; q < nq; ++q) {
+      double2* w = Wj + size_t(q) * n;
+      if (q > 0) {
+        gram_f64(s, Wj, n, q, w, n, 1, n, V, 0, h1, gwork, gw);
+        combine_f64(s, Wj, n, q, h1, q, w, n, 1, n, V, 0, -1);
+        gram_f64(s, Wj, n, q, w, n, 1, n, V, 0, h2, gwork, gw);
+        combine_f64(s, Wj, n, q, h2, q, w, n, 1, n, V, 0, -1);
+      }
+      norm2_f64(s, w, n, 1, n, nrm + 2 * nrhs, nwork, nw);
+      write_col_f64(s, R, nq, q, q, h1, h2, nrm + 2 * nrhs, q);
+      scale_f64(s, w, w, n, nrm + 2 * nrhs);
+    }
+    // z = Qw^H r0, d = R^{-1} z, x += Q d, r = r0 - Qw z
+    gram_f64(s, Wj, n, nq, rj, n, 1, n, V, 0, z, gwork, gw);
+    combine_f64(s, Wj, n, nq, z, nq, rj, n, 1, n, V, 0, -1);
+    dense_trsolve_upper(s, R, nq, nq, z, 1, nq);
+    combine_f64(s, Qj, n, nq, z, nq, x64 + size_t(j) * n, n, 1, n, V, 0, 1);
+  }
+  norm2_f64(s, r64, n, nrhs, n, nrm + nrhs, nwork, nw);
+  unpack_spinor_f64(s, op.g, x64, X0, nrhs);
+  double* hp = (double*)pinned_get(c, sizeof(double) * 2 * nrhs);
+  DBQ_HIP(hipMemcpyAsync(hp, nrm, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, s));
+  DBQ_HIP(hipStreamSynchronize(s));
+  timer_collect(c);
+  for (int j = 0; j < nrhs; ++j) {
+    rn[2 * j] = std::sqrt(hp[j]);
+    rn[2 * j + 1] = std::sqrt(hp[nrhs + j]);
+  }
+  return DBQ_OK;
+}
+
+// ============================================================================ link force
+void force(dbq_ctx* c, const dbq_operator* o, const void* lambda, const void* x, int nrhs,
+           int kind, void* F) {
+  check_op(o);
+  DBQ_CHECK(lambda && x && F, "null argument");
+  DBQ_CHECK(nrhs >= 1, "nrhs must be >= 1");
+  DBQ_CHECK(kind == 0 || kind == 1, "kind must be 0 or 1");
+  const Geom g = make_geom(o->L);
+  launch_link_force(c->stream, g, o->links, o->kappa, lambda, x, nrhs, kind, F);
+}
+
+}  // namespace dbq

@@ -1,0 +1,298 @@
+"""GPU parity of GMRES-DR, D-BiCGStab (FP64, mixed, batched, uneven, adjoint), the shift
+projection, kappa_c and the link gradient against the oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import force as F
+from oracle import kappa as K
+from oracle import solvers as S
+from oracle import wilson as W
+from gpuhelp import dev, host, projector_distance, relerr
+
+pytestmark = pytest.mark.gpu
+
+C1 = dict(L=(4, 4, 4, 4), c=0.3, seed=101, kappa=0.15)
+
+
+def _c1():
+    L = C1["L"]
+    lat = W.Lattice(L)
+    U = synth.gauge_field(L, C1["c"], C1["seed"])
+    return L, lat, U
+
+
+def _true_rel(U, lat, kappa, mu, x, b, dagger=False):
+    r = b - W.apply_A(U, x, lat, kappa, mu, dagger)
+    return np.linalg.norm(r) / np.linalg.norm(b)
+
+
+# ----------------------------------------------------------------------------- GMRES-DR
+def test_gmresdr_c1_matches_oracle(gpu_lib):
+    """4^4, kappa 0.15, point source, GMRES-DR(20,6) to 1e-8: same cycle count as the oracle,
+    same solution to the tolerance, same harmonic Ritz values and the same deflation space."""
+    L, lat, U = _c1()
+    b = synth.point_source(L)
+    x, V, th, st = gpu_lib.gmresdr_first_rhs(L, dev(U), dev(b), 0.15, 20, 6, tol=1e-8)
+    A = W.operator(U, lat, 0.15)
+    xo, Vo, tho, io = S.gmresdr(A, b.reshape(-1), 20, 6, tol=1e-8)
+    assert st["status"] == 0 and io["status"] == 0
+    assert st["matvecs"] == 20 + 14 * (st["iterations"] - 1)
+    assert abs(st["iterations"] - io["cycles"]) <= 1
+    xg = host(x).reshape(-1)
+    assert _true_rel(U, lat, 0.15, 0.0, xg, b.reshape(-1)) <= 1.0001e-8
+    assert st["rel_true_resid"] <= 1.0001e-8
+    if st["iterations"] == io["cycles"]:
+        assert np.linalg.norm(xg - xo) <= 1e-9 * np.linalg.norm(xo)
+        assert len(th) == len(tho)
+        assert np.allclose(th, tho, rtol=1e-6, atol=1e-9)
+        Vg = host(V).reshape(len(th), -1).T
+        assert projector_distance(Vg, Vo) <= 1e-6
+    Vg = host(V).reshape(len(th), -1).T
+    assert np.allclose(Vg.conj().T @ Vg, np.eye(Vg.shape[1]), atol=1e-12)
+
+
+def test_gmresdr_free_field_closed_form(gpu_lib):
+    L = (4, 4, 4, 4)
+    k = 0.12
+    x, V, th, st = gpu_lib.gmresdr_first_rhs(L, dev(synth.unit_field(L)),
+                                             dev(synth.point_source(L)), k, 20, 6, tol=1e-12)
+    for e in [1 - 8 * k, 1 - 6 * k + 2j * k, 1 - 6 * k - 2j * k, 1 - 4 * k]:
+        assert np.min(np.abs(th - e)) <= 1e-8
+
+
+def test_gmresdr_max_mv_not_converged_still_returns_vectors(gpu_lib):
+    L, lat, U = _c1()
+    x, V, th, st = gpu_lib.gmresdr_first_rhs(L, dev(U), dev(synth.point_source(L)), 0.15, 20, 6,
+                                             tol=1e-12, max_mv=40)
+    assert st["status"] == 1 and st["matvecs"] >= 40
+    assert V.shape[0] in (5, 6) and np.all(np.isfinite(host(V)))
+
+
+# ----------------------------------------------------------------------------- D-BiCGStab
+@pytest.fixture(scope="module")
+def c1_vectors():
+    L, lat, U = _c1()
+    A = W.operator(U, lat, 0.15)
+    b = synth.point_source(L).reshape(-1)
+    _, Vo, tho, io = S.gmresdr(A, b, 20, 6, tol=1e-8)
+    return Vo
+
+
+def test_dbicgstab_fp64_matches_oracle(gpu_lib, c1_vectors):
+    L, lat, U = _c1()
+    A = W.operator(U, lat, 0.15)
+    g5 = lambda v: W.gamma5_flat(v, lat.V)
+    B = synth.z2_sources(L, 3, 1101)
+    Vt = dev(c1_vectors.T.reshape(-1, lat.V, 4, 3))
+    X, st, status = gpu_lib.dbicgstab_solve(
+        [dict(L=L, links=dev(U), kappa=0.15, B=dev(B), V=Vt)], tol=1e-8, prec="fp64")
+    assert status == 0
+    Xg = host(X[0])
+    for j in range(3):
+        xo, io = S.dbicgstab(A, B[j].reshape(-1), c1_vectors, g5, tol=1e-8)
+        rel = _true_rel(U, lat, 0.15, 0.0, Xg[j].reshape(-1), B[j].reshape(-1))
+        assert st[j]["status"] == 0 and rel <= 1.0001e-8
+        assert abs(st[j]["rel_true_resid"] - rel) <= 1e-3 * rel
+        # iteration counts are rounding-order dependent: report-level agreement only
+        assert abs(st[j]["matvecs"] - io["matvecs"]) <= 0.25 * io["matvecs"] + 20
+
+
+def test_dbicgstab_fp64_solution_error_against_dense_lu(gpu_lib, c1_vectors):
+    """At tol 1e-12 the relative solution error against a dense LU solve is <= 1e-10 on C1."""
+    L, lat, U = _c1()
+    B = synth.z2_sources(L, 1, 1101)
+    Vt = dev(c1_vectors.T.reshape(-1, lat.V, 4, 3))
+    X, st, status = gpu_lib.dbicgstab_solve(
+        [dict(L=L, links=dev(U), kappa=0.15, B=dev(B), V=Vt)], tol=1e-12, prec="fp64")
+    M = W.dense_matrix(U, lat, 0.15)
+    xe = np.linalg.solve(M, B[0].reshape(-1))
+    assert status == 0
+    assert np.linalg.norm(host(X[0]).reshape(-1) - xe) <= 1e-10 * np.linalg.norm(xe)
+
+
+def test_dbicgstab_mixed_reaches_fp64_residual(gpu_lib, c1_vectors):
+    L, lat, U = _c1()
+    B = synth.z2_sources(L, 3, 1101)
+    Vt = dev(c1_vectors.T.reshape(-1, lat.V, 4, 3))
+    X, st, status = gpu_lib.dbicgstab_solve(
+        [dict(L=L, links=dev(U), kappa=0.15, B=dev(B), V=Vt)], tol=1e-8, prec="mixed")
+    assert status == 0
+    Xg = host(X[0])
+    for j in range(3):
+        assert _true_rel(U, lat, 0.15, 0.0, Xg[j].reshape(-1), B[j].reshape(-1)) <= 1.0001e-8
+        assert st[j]["reliable_updates"] >= 1
+
+
+def test_batched_equals_separate_and_uneven_batch(gpu_lib):
+    """Three lattices of different size in one call give the same solutions (to the solve
+    tolerance) as separate calls; all true residuals meet the tolerance."""
+    probs = []
+    for i, L in enumerate([(4, 4, 4, 4), (6, 4, 4, 4), (4, 4, 2, 6)]):
+        U = synth.gauge_field(L, 0.5, 300 + i)
+        B = synth.z2_sources(L, 2 + i, 400 + i)
+        probs.append(dict(L=L, links=dev(U), kappa=0.12, mu=0.01 * i, B=dev(B), Uh=U, Bh=B))
+    Xb, stb, sb = gpu_lib.dbicgstab_solve([{k: v for k, v in p.items() if k not in ("Uh", "Bh")}
+                                           for p in probs], tol=1e-10, prec="mixed")
+    assert sb == 0
+    for p, Xi in zip(probs, Xb):
+        Xs, sts, ss = gpu_lib.dbicgstab_solve([{k: v for k, v in p.items()
+                                                if k not in ("Uh", "Bh")}], tol=1e-10, prec="mixed")
+        lat = W.Lattice(p["L"])
+        for j in range(p["Bh"].shape[0]):
+            xb = host(Xi)[j].reshape(-1)
+            xs = host(Xs[0])[j].reshape(-1)
+            assert _true_rel(p["Uh"], lat, 0.12, p["mu"], xb, p["Bh"][j].reshape(-1)) <= 1.0001e-10
+            assert np.linalg.norm(xb - xs) <= 1e-8 * np.linalg.norm(xs)
+
+
+def test_adjoint_solve_matches_oracle(gpu_lib, c1_vectors):
+    L, lat, U = _c1()
+    b = synth.gaussian_sources(L, 1, 77)
+    Vt = dev(c1_vectors.T.reshape(-1, lat.V, 4, 3))
+    X, st, status = gpu_lib.dbicgstab_solve(
+        [dict(L=L, links=dev(U), kappa=0.15, mu=0.02, B=dev(b), V=Vt)], tol=1e-10, prec="fp64",
+        dagger=True)
+    assert status == 0
+    rel = _true_rel(U, lat, 0.15, 0.02, host(X[0]).reshape(-1), b.reshape(-1), dagger=True)
+    assert rel <= 1.0001e-10
+
+
+def test_point_source_breakdown_restarts(gpu_lib):
+    """Plain BiCGStab (k = 0) on the point source: rho vanishes exactly after one iteration; the
+    solver restarts with rhat <- r and converges."""
+    L, lat, U = _c1()
+    b = synth.point_source(L)
+    X, st, status = gpu_lib.dbicgstab_solve([dict(L=L, links=dev(U), kappa=0.15, B=dev(b))],
+                                            tol=1e-8, prec="fp64")
+    assert status == 0 and st[0]["restarts"] >= 1
+    assert _true_rel(U, lat, 0.15, 0.0, host(X[0]).reshape(-1), b.reshape(-1)) <= 1.0001e-8
+
+
+def test_max_mv_reports_not_converged(gpu_lib):
+    L, lat, U = _c1()
+    X, st, status = gpu_lib.dbicgstab_solve(
+        [dict(L=L, links=dev(U), kappa=0.15, B=dev(synth.z2_sources(L, 2, 5)))], tol=1e-8,
+        max_mv=10, prec="mixed")
+    assert status == 1 and all(s["status"] == 1 for s in st)
+    assert all(np.isfinite(host(X[0])).ravel())
+
+
+def test_singular_projection_is_reported(gpu_lib, c1_vectors):
+    import paper_0710_1988_amd as dbq
+    L, lat, U = _c1()
+    Vd = np.concatenate([c1_vectors, c1_vectors[:, :1]], axis=1)  # duplicated column
+    with pytest.raises(dbq.DbqError) as e:
+        gpu_lib.dbicgstab_solve([dict(L=L, links=dev(U), kappa=0.15,
+                                      B=dev(synth.z2_sources(L, 1, 5)),
+                                      V=dev(Vd.T.reshape(-1, lat.V, 4, 3)))], tol=1e-8)
+    assert e.value.status == -3
+
+
+def test_zero_rhs_gives_zero_solution(gpu_lib):
+    L, lat, U = _c1()
+    B = np.zeros((1, lat.V, 4, 3), dtype=complex)
+    X, st, status = gpu_lib.dbicgstab_solve([dict(L=L, links=dev(U), kappa=0.15, B=dev(B))])
+    assert status == 0 and np.all(host(X[0]) == 0)
+
+
+# ----------------------------------------------------------------------------- shift projection
+def test_project_shifts_matches_oracle(gpu_lib):
+    L = (4, 4, 2, 4)
+    lat = W.Lattice(L)
+    U = synth.gauge_field(L, 0.6, 501)
+    B = synth.z2_sources(L, 2, 502)
+    mus = [0.05, 0.03, 0.02]
+    Q = np.zeros((2, 3, lat.V, 4, 3), dtype=complex)
+    for j in range(2):
+        for q, m in enumerate(mus):
+            x, _ = S.bicgstab(W.operator(U, lat, 0.15, m), B[j].reshape(-1), tol=1e-12)
+            Q[j, q] = x.reshape(lat.V, 4, 3)
+    X, r0, r1 = gpu_lib.project_shifts(L, dev(U), 0.15, 0.01, dev(Q), dev(B))
+    A = W.operator(U, lat, 0.15, 0.01)
+    for j in range(2):
+        xo, ro, io = S.mr_project(A, Q[j].reshape(3, -1).T, B[j].reshape(-1))
+        assert abs(r0[j] - io["rnorm_before"]) <= 1e-12 * io["rnorm_before"]
+        assert abs(r1[j] - io["rnorm_after"]) <= 1e-8 * io["rnorm_before"]
+        assert r1[j] <= r0[j]
+        rg = B[j].reshape(-1) - A(host(X)[j].reshape(-1))
+        assert abs(np.linalg.norm(rg) - io["rnorm_after"]) <= 1e-8 * io["rnorm_before"]
+
+
+# ----------------------------------------------------------------------------- kappa_c
+def test_kappa_critical_free_field(gpu_lib):
+    L = (4, 4, 4, 4)
+    kc, lam, res, st = gpu_lib.kappa_critical(L, dev(synth.unit_field(L)), m=24, k=8, tol=1e-12)
+    assert abs(kc - 0.125) <= 1e-12 and res <= 1e-10
+
+
+def test_kappa_critical_matches_oracle(gpu_lib):
+    L = (4, 4, 4, 4)
+    lat = W.Lattice(L)
+    U = synth.gauge_field(L, 0.3, 101)
+    kc, lam, res, st = gpu_lib.kappa_critical(L, dev(U), m=40, k=12, tol=1e-11)
+    ko, vals, reso = K.kappa_c(U, lat)
+    assert st == 0 and res <= 1e-9
+    assert abs(kc - ko) <= 1e-8 * ko
+
+
+# ----------------------------------------------------------------------------- gradient
+def test_link_force_matches_oracle(gpu_lib):
+    L = (4, 4, 2, 6)
+    lat = W.Lattice(L)
+    U = synth.gauge_field(L, 0.5, 601)
+    lam = synth.gaussian_sources(L, 2, 602)
+    x = synth.gaussian_sources(L, 2, 603)
+    G = F.link_gradient(U, lat, 0.13, lam, x)
+    Fo = F.su3_force(U, G)
+    Gg = host(gpu_lib.link_force(L, dev(U), 0.13, dev(lam), dev(x), kind="complex"))
+    Fg = host(gpu_lib.link_force(L, dev(U), 0.13, dev(lam), dev(x), kind="su3"))
+    assert relerr(Gg, G) <= 1e-13
+    assert relerr(Fg, Fo) <= 1e-12
+
+
+def test_autograd_matches_finite_differences(gpu_lib):
+    """C4 recipe on 4^4 (8^4 in the full check): L = Re(eta^H A^{-1} b); the autograd gradient
+    along random su(3) link directions and along b agrees with central differences of FP64
+    solves."""
+    import torch
+    L = (4, 4, 4, 4)
+    lat = W.Lattice(L)
+    U = synth.gauge_field(L, 0.5, 104)
+    kc, _, _ = K.kappa_c(U, lat)
+    kap = 0.9 * kc
+    b = synth.z2_sources(L, 1, 1104)
+    eta = synth.gaussian_sources(L, 1, 2104)
+    Ut = dev(U).requires_grad_(True)
+    bt = dev(b).requires_grad_(True)
+    x = gpu_lib.DeflatedSolve.apply(Ut, bt, L, kap, 0.0, None, 1e-13, "fp64", 100000)
+    loss = (dev(eta).conj() * x).sum().real
+    loss.backward()
+    gU = host(Ut.grad)
+    gb = host(bt.grad)
+
+    def Lval(Uh, bh):
+        X, _, st = gpu_lib.dbicgstab_solve([dict(L=L, links=dev(Uh), kappa=kap, B=dev(bh))],
+                                           tol=1e-14, prec="fp64", max_mv=100000)
+        return float(np.real(np.vdot(eta, host(X[0]))))
+
+    rng = np.random.default_rng(3104)
+    h = 1e-6
+    for _ in range(3):
+        mu_, y = rng.integers(0, 4), rng.integers(0, lat.V)
+        c = synth.su3_directions(1, int(rng.integers(1 << 30)))[0]
+        T = np.einsum("a,aij->ij", c, F.T_GEN)
+        q, Wv = np.linalg.eigh(T)
+        vals = []
+        for s in (+1, -1):
+            Up = U.copy()
+            Up[mu_, y] = (Wv * np.exp(1j * s * h * q)) @ Wv.conj().T @ U[mu_, y]
+            vals.append(Lval(Up, b))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        an = float(np.real(np.sum(np.conj(gU[mu_, y]) * (1j * T @ U[mu_, y]))))
+        assert abs(fd - an) <= 1e-4 * max(abs(fd), 1e-3)
+    # gradient with respect to b along a random direction
+    d = synth.gaussian_sources(L, 1, 9)
+    fd = (Lval(U, b + h * d) - Lval(U, b - h * d)) / (2 * h)
+    an = float(np.real(np.vdot(gb, d)))
+    assert abs(fd - an) <= 1e-5 * abs(fd)
