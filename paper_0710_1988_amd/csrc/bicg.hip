@@ -1,11 +1,12 @@
 // Fused BiCGStab vector updates and inner products for a batch of right-hand sides (Sec. 2 runs
 // BiCGStab after the deflation step; Sec. 1 motivates it as a non-restarted method).
 //
-// One iteration = 5 launches:  BI_P (p = r + beta (p - omega v)),  Dslash v = A p with <rhat, v>
-// -> alpha,  BI_S (r <- s = r - alpha v),  Dslash t = A s with <t, s>, <t, t> -> omega,
+// One iteration:  BI_P (p = r + beta (p - omega v)),  Dslash v = A p with <rhat, v> -> alpha,
+// BI_S (r <- s = r - alpha v),  Dslash t = A s with <t, s>, <t, t> -> omega,
 // BI_XR (x += alpha p + omega s; r = s - omega t; <rhat, r>, ||r||^2 -> rho, beta, tests).
-// The scalars live in RhsScal on the device; each reduction finishes in the last block to arrive
-// with a fixed summation order, so results do not depend on block scheduling.
+// The scalars live in RhsScal on the device.  Each streaming kernel stores one partial sum per
+// block; a small follow-up launch combines them per right-hand side in a fixed order, so the
+// results do not depend on block scheduling and no device-scope fence stalls the stream.
 #include "kernels.h"
 
 namespace dbq {
@@ -50,9 +51,11 @@ __device__ __forceinline__ bool fin(double v) { return isfinite(v); }
 // reduce the partials of every rhs (one wavefront per rhs) and apply `fn(rhs, a0, a1, a2)`
 template <typename Fn>
 __device__ void reduce_rhs(const VecSet& vs, const double* partials, Fn fn) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   constexpr int NW = BL_BS / 64;
-  for (int rhs = w; rhs < vs.nrhs; rhs += NW) {
+  const int w = blockIdx.x * NW + (threadIdx.x >> 6);
+  const int stride = gridDim.x * NW;
+  for (int rhs = w; rhs < vs.nrhs; rhs += stride) {
     const int nch = (vs.nelem[rhs] + BL_CHUNK - 1) / BL_CHUNK;
     const double* pp = partials + (long long)rhs * vs.pstride * 3;
     double a0 = 0, a1 = 0, a2 = 0;
@@ -171,15 +174,31 @@ __global__ __launch_bounds__(BL_BS) void k_bicg_step(VecSet vs, E* __restrict__ 
       }
     }
   }
-  if (OP == BI_XR) {
-    store_partial(vs, partials, rhs, ch, red);
-    if (last_block_arrive(counter, unsigned(vs.nblocks))) {
-      reduce_rhs(vs, partials, [&](int j, double a0, double a1, double a2) {
-        fin_xr(sc[j], a0, a1, a2);
-      });
-      last_block_reset(counter);
-    }
-  }
+  if (OP == BI_XR) store_partial(vs, partials, rhs, ch, red);
+}
+
+// Partial sums are combined in a separate launch (see the Dslash epilogue for why).
+__global__ __launch_bounds__(BL_BS) void k_fin_xr(VecSet vs, RhsScal* __restrict__ sc,
+                                                  const double* __restrict__ partials) {
+  reduce_rhs(vs, partials, [&](int j, double a0, double a1, double a2) { fin_xr(sc[j], a0, a1, a2); });
+}
+
+__device__ void fin_aux(int op, RhsScal& q, double a0, double a1, double a2);
+
+template <int OP>
+__global__ __launch_bounds__(BL_BS) void k_fin_aux(VecSet vs, RhsScal* __restrict__ sc,
+                                                   const double* __restrict__ partials) {
+  reduce_rhs(vs, partials, [&](int j, double a0, double a1, double a2) {
+    fin_aux(OP, sc[j], a0, a1, a2);
+  });
+}
+
+inline unsigned fin_blocks(const VecSet& vs) { return unsigned((vs.nrhs + BL_BS / 64 - 1) / (BL_BS / 64)); }
+
+template <int OP>
+void launch_fin_aux(hipStream_t s, const VecSet& vs, RhsScal* sc, const double* partials) {
+  hipLaunchKernelGGL((k_fin_aux<OP>), dim3(fin_blocks(vs)), dim3(BL_BS), 0, s, vs, sc, partials);
+  DBQ_HIP(hipGetLastError());
 }
 
 __device__ void fin_aux(int op, RhsScal& q, double a0, double a1, double a2) {
@@ -266,12 +285,6 @@ __global__ __launch_bounds__(BL_BS) void k_aux64(VecSet vs, const double2* __res
     }
   }
   store_partial(vs, partials, rhs, ch, red);
-  if (last_block_arrive(counter, unsigned(vs.nblocks))) {
-    reduce_rhs(vs, partials, [&](int j, double a0, double a1, double a2) {
-      fin_aux(OP, sc[j], a0, a1, a2);
-    });
-    last_block_reset(counter);
-  }
 }
 
 // FP32 working vectors fed from / narrowed from FP64 ones (element e <-> FP64 elements 2e, 2e+1)
@@ -323,12 +336,6 @@ __global__ __launch_bounds__(BL_BS) void k_aux32(VecSet vs, VecSet vs64,
     }
   }
   store_partial(vs, partials, rhs, ch, red);
-  if (last_block_arrive(counter, unsigned(vs.nblocks))) {
-    reduce_rhs(vs, partials, [&](int j, double a0, double a1, double a2) {
-      fin_aux(OP, sc[j], a0, a1, a2);
-    });
-    last_block_reset(counter);
-  }
 }
 
 __global__ __launch_bounds__(BL_BS) void k_xacc(VecSet vs, VecSet vs64, double2* __restrict__ x64,
@@ -374,6 +381,8 @@ void step(hipStream_t s, int op, const VecSet& vs, E* x, E* r, const E* rhat, E*
     default:
       hipLaunchKernelGGL((k_bicg_step<E, BI_XR>), g, b, 0, s, vs, x, r, rhat, p, v, t, sc,
                          partials, counter);
+      DBQ_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_fin_xr, dim3(fin_blocks(vs)), b, 0, s, vs, sc, partials);
       break;
   }
   DBQ_HIP(hipGetLastError());
@@ -405,6 +414,9 @@ void bicg_aux_f64(hipStream_t s, int op, const VecSet& vs, const double2* r64, d
     hipLaunchKernelGGL((k_aux64<AX_REPLACE>), g, b, 0, s, vs, r64, r, rhat, p, v, sc, partials,
                        counter);
   DBQ_HIP(hipGetLastError());
+  if (op == AX_INIT) launch_fin_aux<AX_INIT>(s, vs, sc, partials);
+  else if (op == AX_RESTART) launch_fin_aux<AX_RESTART>(s, vs, sc, partials);
+  else launch_fin_aux<AX_REPLACE>(s, vs, sc, partials);
 }
 
 void bicg_aux_f32(hipStream_t s, int op, const VecSet& vs32, const VecSet& vs64,
@@ -421,6 +433,9 @@ void bicg_aux_f32(hipStream_t s, int op, const VecSet& vs32, const VecSet& vs64,
     hipLaunchKernelGGL((k_aux32<AX_REPLACE>), g, b, 0, s, vs32, vs64, r64, r, rhat, p, v, x32,
                        sc, partials, counter);
   DBQ_HIP(hipGetLastError());
+  if (op == AX_INIT) launch_fin_aux<AX_INIT>(s, vs32, sc, partials);
+  else if (op == AX_RESTART) launch_fin_aux<AX_RESTART>(s, vs32, sc, partials);
+  else launch_fin_aux<AX_REPLACE>(s, vs32, sc, partials);
 }
 
 void bicg_xacc(hipStream_t s, const VecSet& vs32, const VecSet& vs64, double2* x64, float4* x32,

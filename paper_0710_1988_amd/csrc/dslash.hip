@@ -189,9 +189,11 @@ __device__ __forceinline__ bool finite_d(double v) { return isfinite(v); }
 // one wavefront over its per-block partials in a fixed order.
 template <int EPI>
 __device__ void finalize(const DsBatch& B, RhsScal* sc, const double* partials) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   constexpr int NW = DS_BS / 64;
-  for (int rhs = w; rhs < B.nrhs_total; rhs += NW) {
+  const int w = blockIdx.x * NW + (threadIdx.x >> 6);
+  const int stride = gridDim.x * NW;
+  for (int rhs = w; rhs < B.nrhs_total; rhs += stride) {
     int l = 0;
     for (int i = 1; i < B.nlat; ++i)
       if (rhs >= B.lat[i].rhs_base) l = i;
@@ -329,11 +331,16 @@ __global__ __launch_bounds__(DS_BS) void k_dslash(DsBatch B, RhsScal* __restrict
       pp[1] = red[1];
       pp[2] = red[2];
     }
-    if (last_block_arrive(counter, unsigned(B.nblocks))) {
-      finalize<EPI>(B, sc, partials);
-      last_block_reset(counter);
-    }
   }
+}
+
+// The per-block partial sums are combined by a separate small launch: the kernel boundary makes
+// every block's partials visible across XCDs without a device-scope fence in the streaming
+// kernel (on a multi-XCD part such a fence writes back the whole L2 of the issuing XCD).
+template <int EPI>
+__global__ __launch_bounds__(DS_BS) void k_ds_finalize(DsBatch B, RhsScal* __restrict__ sc,
+                                                       const double* __restrict__ partials) {
+  finalize<EPI>(B, sc, partials);
 }
 
 template <typename T>
@@ -362,6 +369,17 @@ double launch(hipStream_t s, const DsBatch& b, int dagger, int epi, RhsScal* sc,
   }
 #undef DBQ_DS
   DBQ_HIP(hipGetLastError());
+  if (epi != EPI_NONE) {
+    // one wavefront per right-hand side, four per block
+    const unsigned nb = unsigned((b.nrhs_total + DS_BS / 64 - 1) / (DS_BS / 64));
+    if (epi == EPI_RHAT)
+      hipLaunchKernelGGL((k_ds_finalize<EPI_RHAT>), dim3(nb), block, 0, s, b, sc, partials);
+    else if (epi == EPI_TS)
+      hipLaunchKernelGGL((k_ds_finalize<EPI_TS>), dim3(nb), block, 0, s, b, sc, partials);
+    else
+      hipLaunchKernelGGL((k_ds_finalize<EPI_RESID>), dim3(nb), block, 0, s, b, sc, partials);
+    DBQ_HIP(hipGetLastError());
+  }
   // algorithmic bytes: links once per lattice, each spinor read once and written once, plus
   // one epilogue operand per site (rhat or b)
   double bytes = 0;

@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -349,6 +351,8 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
          *t32 = nullptr;
   if (mixed) {
     x32 = ws.get<float4>(tot32);
+    // zeroed here so that right-hand sides which never start iterating (b = 0) add nothing
+    zero_f64(s, reinterpret_cast<double2*>(x32), tot32);
     r32 = ws.get<float4>(tot32);
     rhat32 = ws.get<float4>(tot32);
     p32 = ws.get<float4>(tot32);
@@ -413,11 +417,19 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
 
   int nchk = 1;
   bool first = true;
+  const bool debug = std::getenv("DBQ_DEBUG") != nullptr;
   while (true) {
     if (!first)
       for (int it = 0; it < nchk; ++it) iterate();
     first = false;
     pull();
+    if (debug) {
+      for (int j = 0; j < NR; ++j)
+        if (!done[j])
+          std::fprintf(stderr, "[dbq] rhs %d it %d flags %d act %d rr %.3e/%.3e rr_max %.3e mvb %lld\n",
+                       j, hs[j].iters, hs[j].flags, hs[j].active, hs[j].rr, hs[j].bb, hs[j].rr_max,
+                       (long long)mvb[j]);
+    }
     std::vector<int> A, Bk, Cc;
     bool any_active = false;
     for (int j = 0; j < NR; ++j) {
