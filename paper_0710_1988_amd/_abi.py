@@ -6,7 +6,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libdbq.so")
+# DBQ_LIBRARY selects another build of the same library (e.g. a variant compiled with different
+# kernel tuning flags); by default the in-tree libdbq.so next to this file is loaded.
+LIB_PATH = os.environ.get("DBQ_LIBRARY") or os.path.join(HERE, "libdbq.so")
 
 DBQ_OK, DBQ_NOT_CONVERGED = 0, 1
 DBQ_EINVAL, DBQ_EBREAKDOWN, DBQ_ESINGULAR, DBQ_EHIP, DBQ_ENOMEM = -1, -2, -3, -4, -5

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -34,8 +35,12 @@ struct dbq_ctx {
     double bytes = 0;
   } timers[2];
 
-  // ---- geometry-independent counters for the last-block reductions (one per kernel class)
+  // ---- geometry-independent counters (kept for kernels that need a device-wide count)
   unsigned int* counters = nullptr;  // device, NCOUNTERS entries, kept zero between launches
+
+  // ---- Dslash launch shape chosen by timing, keyed by (fp32, V, nrhs): (rhs per thread,
+  //      rhs groups per site sweep)
+  std::map<std::tuple<int, int, int>, std::pair<int, int>> ds_tune;
 };
 
 namespace dbq {

@@ -59,9 +59,11 @@ struct DsLat {
 struct DsBatch {
   DsLat lat[MAXLAT];
   int nlat;
-  int nblocks;
+  int nblocks;     // set by the launcher for the chosen rhs-per-thread
   int nrhs_total;
-  int pstride;  // partial-sum slots per rhs
+  int pstride;     // partial-sum slots per rhs
+  int nb;          // right-hand sides per thread (1, 2 or 4), set by the launcher
+  int rgroup;      // thread rhs-groups sharing a sweep over the site blocks, set by the launcher
 };
 
 enum Epi : int { EPI_NONE = 0, EPI_RHAT = 1, EPI_TS = 2, EPI_RESID = 3 };
@@ -91,12 +93,14 @@ void pack_links_f32(hipStream_t s, const Geom& g, const void* canon, float4* out
 void gamma5_f64(hipStream_t s, const double2* in, double2* out, long long V, int count);
 
 // ----------------------------------------------------------------------------- dslash.hip
-// Returns algorithmic HBM bytes of the launch (links once, input once, output once, plus
-// epilogue operands).
+// nb = right-hand sides per thread (1, 2, 4).  Returns the algorithmic HBM bytes of the launch
+// (links once, input once, output once, plus the epilogue operand).
+// rgroup = how many rhs groups of nb sweep the site blocks together (block order: rhs chunk,
+// then site block, then rhs within the chunk); 0 means all of them.
 double launch_dslash_f64(hipStream_t s, const DsBatch& b, int dagger, int epi, RhsScal* sc,
-                         double* partials, unsigned int* counter);
+                         double* partials, int nb, int rgroup);
 double launch_dslash_f32(hipStream_t s, const DsBatch& b, int dagger, int epi, RhsScal* sc,
-                         double* partials, unsigned int* counter);
+                         double* partials, int nb, int rgroup);
 
 // ----------------------------------------------------------------------------- bicg.hip
 enum BicgOp : int { BI_P = 0, BI_S = 1, BI_XR = 2 };

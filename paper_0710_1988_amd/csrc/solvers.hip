@@ -35,7 +35,8 @@ void check_op(const dbq_operator* o) {
     DBQ_CHECK(o->L[i] >= 2 && o->L[i] % 2 == 0, "lattice extents must be even and >= 2");
     V *= o->L[i];
   }
-  DBQ_CHECK(V <= (1ll << 27), "lattice too large (V > 2^27)");
+  // byte offsets within one component array are 32-bit in the kernels
+  DBQ_CHECK(V <= (1ll << 26), "lattice too large (V > 2^26)");
   DBQ_CHECK(o->links != nullptr, "null links");
   DBQ_CHECK(std::isfinite(o->kappa) && std::isfinite(o->mu), "non-finite kappa or mu");
 }
@@ -71,7 +72,7 @@ DsBatch make_batch(const std::vector<DsSpec>& v) {
   DsBatch b;
   std::memset(&b, 0, sizeof(b));
   b.nlat = int(v.size());
-  int blk = 0, nr = 0, ps = 1;
+  int nr = 0, ps = 1;
   for (size_t i = 0; i < v.size(); ++i) {
     DsLat& L = b.lat[i];
     L.g = v[i].op->g;
@@ -81,27 +82,99 @@ DsBatch make_batch(const std::vector<DsSpec>& v) {
     L.aux = v[i].aux;
     L.nrhs = v[i].nrhs;
     L.rhs_base = v[i].rhs_base;
-    L.nsb = (L.g.V + DS_BS - 1) / DS_BS;
-    L.blk_begin = blk;
+    // site blocks: each parity half is cut into blocks of DS_BS sites (the kernel interleaves
+    // the two halves block by block)
+    L.nsb = 2 * ((L.g.V / 2 + DS_BS - 1) / DS_BS);
+    L.blk_begin = 0;  // laid out by the launcher
     L.kappa = v[i].op->kappa;
     L.mu = v[i].op->mu;
-    blk += L.nsb * L.nrhs;
     nr = std::max(nr, L.rhs_base + L.nrhs);
     ps = std::max(ps, L.nsb);
   }
-  b.nblocks = blk;
+  b.nblocks = 0;
+  b.nb = 1;
   b.nrhs_total = nr;
   b.pstride = ps;
   return b;
 }
 
+// Launch shape of the Dslash for a batch: right-hand sides per thread (1, 2, 4) and how many of
+// those thread groups sweep the site blocks together (1, 2, 4 or all).  Timed once per
+// (precision, volume, batch size) in this context on a scratch output (the operator input is
+// only read).  DBQ_DS_NB / DBQ_DS_RG force the values.
+std::pair<int, int> choose_shape(dbq_ctx* c, bool f32, const DsBatch& b) {
+  int maxr = 1;
+  for (int i = 0; i < b.nlat; ++i) maxr = std::max(maxr, b.lat[i].nrhs);
+  const char* e_nb = std::getenv("DBQ_DS_NB");
+  const char* e_rg = std::getenv("DBQ_DS_RG");
+  if (e_nb || e_rg) {
+    int nb = e_nb ? std::atoi(e_nb) : 1;
+    if (nb != 1 && nb != 2 && nb != 4) nb = 1;
+    return {nb, e_rg ? std::max(0, std::atoi(e_rg)) : 0};
+  }
+  if (maxr == 1) return {1, 0};
+  int big = 0;
+  for (int i = 1; i < b.nlat; ++i)
+    if ((long long)b.lat[i].g.V * b.lat[i].nrhs > (long long)b.lat[big].g.V * b.lat[big].nrhs) big = i;
+  const auto key = std::make_tuple(f32 ? 1 : 0, b.lat[big].g.V, b.lat[big].nrhs);
+  auto it = c->ds_tune.find(key);
+  if (it != c->ds_tune.end()) return it->second;
+  WsScope ws(c);
+  DsBatch t;
+  std::memset(&t, 0, sizeof(t));
+  t.nlat = 1;
+  t.lat[0] = b.lat[big];
+  t.lat[0].rhs_base = 0;
+  t.lat[0].aux = nullptr;
+  t.nrhs_total = t.lat[0].nrhs;
+  t.pstride = t.lat[0].nsb;
+  const size_t bytes =
+      size_t(t.lat[0].nrhs) * t.lat[0].g.V * (f32 ? 6 * sizeof(float4) : 12 * sizeof(double2));
+  t.lat[0].out = ws.take(bytes);
+  hipEvent_t e0, e1;
+  DBQ_HIP(hipEventCreate(&e0));
+  DBQ_HIP(hipEventCreate(&e1));
+  std::pair<int, int> best{1, 0};
+  float best_ms = 1e30f;
+  for (int nb : {1, 2, 4}) {
+    if (nb > maxr || (!f32 && nb == 4)) continue;
+    const int ng = (maxr + nb - 1) / nb;
+    for (int rg : {1, 2, 4, 0}) {
+      if (rg >= ng) continue;  // 0 (all) covers it
+      for (int rep = 0; rep < 2; ++rep) {  // warm-up, then timed
+        DBQ_HIP(hipEventRecord(e0, c->stream));
+        for (int k = 0; k < 3; ++k) {
+          if (f32) launch_dslash_f32(c->stream, t, 0, EPI_NONE, nullptr, nullptr, nb, rg);
+          else launch_dslash_f64(c->stream, t, 0, EPI_NONE, nullptr, nullptr, nb, rg);
+        }
+        DBQ_HIP(hipEventRecord(e1, c->stream));
+      }
+      DBQ_HIP(hipEventSynchronize(e1));
+      float ms = 0;
+      DBQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (std::getenv("DBQ_DEBUG"))
+        std::fprintf(stderr, "[dbq] tune %s V=%d nrhs=%d nb=%d rg=%d: %.1f us\n", f32 ? "fp32" : "fp64",
+                     t.lat[0].g.V, maxr, nb, rg, ms * 1e3f / 3);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = {nb, rg};
+      }
+    }
+  }
+  DBQ_HIP(hipEventDestroy(e0));
+  DBQ_HIP(hipEventDestroy(e1));
+  c->ds_tune[key] = best;
+  return best;
+}
+
 void run_dslash(dbq_ctx* c, bool f32, const DsBatch& b, int dagger, int epi, RhsScal* sc,
-                double* partials, int ctr) {
+                double* partials, int) {
+  const auto shape = choose_shape(c, f32, b);
   hipEvent_t e0;
   timer_begin(c, f32 ? 1 : 0, &e0);
   const double bytes =
-      f32 ? launch_dslash_f32(c->stream, b, dagger, epi, sc, partials, counter(c, ctr))
-          : launch_dslash_f64(c->stream, b, dagger, epi, sc, partials, counter(c, ctr));
+      f32 ? launch_dslash_f32(c->stream, b, dagger, epi, sc, partials, shape.first, shape.second)
+          : launch_dslash_f64(c->stream, b, dagger, epi, sc, partials, shape.first, shape.second);
   timer_end(c, f32 ? 1 : 0, e0, bytes);
 }
 
