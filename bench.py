@@ -13,8 +13,10 @@ the CPU oracle on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -25,6 +27,35 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Dslash HBM GB/s; D-BiCGStab time-to-1e-8/source (mixed+batched vs FP64 plain)"
 HBM_PEAK_GBS = 8000.0
+# FETCH_SIZE / WRITE_SIZE summary of the FP32 batched Dslash on this workload, and the kernel
+# sources it was measured with: the traffic figure is reported only while they are unchanged.
+COUNTERS = os.path.join(ROOT, "profiles", "dslash_f32_batched_16x16x16x16_nrhs12_counters.md")
+KERNEL_SOURCES = ("paper_0710_1988_amd/csrc/dslash.hip", "paper_0710_1988_amd/csrc/kernels.h",
+                  "paper_0710_1988_amd/csrc/common.h")
+
+
+def kernel_digest():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic():
+    """Scaled FETCH_SIZE + WRITE_SIZE bytes per FP32 Dslash launch from the committed counter
+    summary, or None when the summary is missing or the kernel sources changed since."""
+    try:
+        txt = open(COUNTERS).read()
+    except OSError:
+        return None, "no counter summary"
+    m_t = re.search(r"^DSLASH_F32_TRAFFIC_BYTES_PER_LAUNCH = (\d+)", txt, re.M)
+    m_h = re.search(r"^KERNEL_SOURCE_SHA256 = ([0-9a-f]{64})", txt, re.M)
+    if not (m_t and m_h):
+        return None, "counter summary incomplete"
+    if m_h.group(1) != kernel_digest():
+        return None, "kernel sources changed since the counters were taken"
+    return float(m_t.group(1)), "profiles/" + os.path.basename(COUNTERS)
 
 
 def log(*a):
@@ -85,6 +116,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the FP64 comparisons and sweep")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 256 MiB with a plain device copy (a known-size reference "
+                         "for hardware byte counters)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the solve of "
@@ -100,6 +134,13 @@ def main():
         print("no GPU", file=sys.stderr)
         sys.exit(1)
     dev = "cuda:0"
+    if a.calibrate_copy:
+        src = torch.ones(1 << 26, dtype=torch.float32, device=dev)  # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 268435456 bytes read, 268435456 bytes written")
+        del src, dst
     L = (16, 16, 16, 16)
     Vol = int(np.prod(L))
     nrhs, m, k, tol = 12, 60, 20, 1e-8
@@ -148,6 +189,7 @@ def main():
         f"{worst:.2e}, all converged {ok}, MVPs/source {mv_mixed:.0f}")
     avg_us = ms32 / max(n32, 1) * 1e3
     ach = by32 / max(n32, 1) / (avg_us * 1e-6) / 1e9 if n32 else 0.0
+    traffic, traffic_src = counter_traffic()
     out = {
         "metric": METRIC,
         "value": round(ms_step / nrhs, 4),
@@ -171,8 +213,11 @@ def main():
         "all_converged": ok,
         "mvps_per_source": mv_mixed,
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_dslash<float> (FP32 12-real links, 12 rhs per launch)",
+                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic),
+                     "traffic_source": traffic_src,
+                     "kernel": "k_dslash<float> (FP32 12-real links, 12 rhs per launch; "
+                               "working set MALL-resident at 16^4)",
                      "avg_launch_us": round(avg_us, 2), "launches": n32,
                      "algorithmic_MB_per_launch": round(by32 / max(n32, 1) / 1e6, 2)},
         "fp64_dslash_in_step": {"launches": n64,

@@ -40,8 +40,12 @@ int dbq_create(dbq_ctx** out, void* stream) {
   c->stream = (hipStream_t)stream;
   if (hipGetDevice(&c->device) != hipSuccess ||
       hipMalloc(&c->counters, sizeof(unsigned int) * dbq::NCOUNTERS) != hipSuccess ||
-      hipMemset(c->counters, 0, sizeof(unsigned int) * dbq::NCOUNTERS) != hipSuccess) {
+      hipMemset(c->counters, 0, sizeof(unsigned int) * dbq::NCOUNTERS) != hipSuccess ||
+      hipMalloc(&c->acct, sizeof(unsigned long long) * 32) != hipSuccess ||
+      hipMemset(c->acct, 0, sizeof(unsigned long long) * 32) != hipSuccess) {
     (void)hipGetLastError();
+    if (c->counters) (void)hipFree(c->counters);
+    if (c->acct) (void)hipFree(c->acct);
     delete c;
     return DBQ_EHIP;
   }
@@ -55,6 +59,7 @@ int dbq_destroy(dbq_ctx* c) {
   for (auto& b : c->pool) (void)hipFree(b.p);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->counters) (void)hipFree(c->counters);
+  if (c->acct) (void)hipFree(c->acct);
   for (auto& t : c->timers) {
     for (auto& pr : t.ev) {
       (void)hipEventDestroy(pr.first);

@@ -112,6 +112,15 @@ void timer_collect(dbq_ctx* c) {
     }
     t.ev.clear();
   }
+  if (c->acct) {
+    unsigned long long v[2];
+    DBQ_HIP(hipMemcpyAsync(v, c->acct, sizeof(v), hipMemcpyDeviceToHost, c->stream));
+    DBQ_HIP(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < 2; ++k) {
+      c->timers[k].bytes += double(v[k] - c->acct_seen[k]);
+      c->acct_seen[k] = v[k];
+    }
+  }
 }
 
 }  // namespace dbq

@@ -38,6 +38,13 @@ struct dbq_ctx {
   // ---- geometry-independent counters (kept for kernels that need a device-wide count)
   unsigned int* counters = nullptr;  // device, NCOUNTERS entries, kept zero between launches
 
+  // ---- device accumulators for the algorithmic bytes of gated Dslash launches (timing only):
+  //      [kind] bytes so far, [8 + 8 * kind + lattice] id of the last launch that counted the
+  //      lattice's links.  acct_seen = the accumulator values already added to the timers.
+  unsigned long long* acct = nullptr;
+  unsigned long long acct_seq = 0;
+  unsigned long long acct_seen[2] = {0, 0};
+
   // ---- Dslash launch shape chosen by timing, keyed by (fp32, V, nrhs): (rhs per thread,
   //      rhs groups per site sweep)
   std::map<std::tuple<int, int, int>, std::pair<int, int>> ds_tune;

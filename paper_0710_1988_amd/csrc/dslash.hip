@@ -307,6 +307,17 @@ __device__ void finalize(const DsBatch& B, RhsScal* sc, const double* partials) 
     a2 = wave_sum(a2);
     if (lane == 0) {
       RhsScal& q = sc[rhs];
+      if (B.acct.bytes) {
+        // the flag the Dslash kernel was gated on, read before this launch changes it
+        const bool processed = (EPI == EPI_RESID) ? q.sel != 0 : q.active != 0;
+        if (processed) {
+          unsigned long long by = (unsigned long long)B.lat[l].g.V *
+                                  (unsigned long long)(B.acct.spinor_passes * B.acct.spinor_bytes);
+          if (atomicMax(B.acct.tags + l, B.acct.id) < B.acct.id)
+            by += (unsigned long long)B.lat[l].g.V * (unsigned long long)B.acct.link_bytes;
+          atomicAdd(B.acct.bytes, by);
+        }
+      }
       if (EPI == EPI_RHAT) {
         if (q.active) {
           const zd d{a0, a1};
@@ -551,18 +562,6 @@ double launch(hipStream_t s, const DsBatch& in, int dagger, int epi, RhsScal* sc
   if (dagger) launch_epi<T, true>(s, b, epi, sc, partials, gate);
   else launch_epi<T, false>(s, b, epi, sc, partials, gate);
   DBQ_HIP(hipGetLastError());
-  if (epi != EPI_NONE) {
-    // one wavefront per right-hand side, four per block
-    const unsigned nfb = unsigned((b.nrhs_total + DS_BS / 64 - 1) / (DS_BS / 64));
-    const dim3 block(DS_BS);
-    if (epi == EPI_RHAT)
-      hipLaunchKernelGGL((k_ds_finalize<EPI_RHAT>), dim3(nfb), block, 0, s, b, sc, partials);
-    else if (epi == EPI_TS)
-      hipLaunchKernelGGL((k_ds_finalize<EPI_TS>), dim3(nfb), block, 0, s, b, sc, partials);
-    else
-      hipLaunchKernelGGL((k_ds_finalize<EPI_RESID>), dim3(nfb), block, 0, s, b, sc, partials);
-    DBQ_HIP(hipGetLastError());
-  }
   // algorithmic bytes: links once per lattice, each spinor read once and written once, plus
   // one epilogue operand per site (rhat or b)
   double bytes = 0;
@@ -576,6 +575,22 @@ double launch(hipStream_t s, const DsBatch& in, int dagger, int epi, RhsScal* sc
 }
 
 }  // namespace
+
+void launch_ds_finalize(hipStream_t s, const DsBatch& b, int epi, RhsScal* sc,
+                        const double* partials) {
+  if (epi == EPI_NONE) return;
+  DBQ_CHECK(sc && partials, "dslash finalize: null scalars");
+  // one wavefront per right-hand side, four per block
+  const unsigned nfb = unsigned((b.nrhs_total + DS_BS / 64 - 1) / (DS_BS / 64));
+  const dim3 block(DS_BS);
+  if (epi == EPI_RHAT)
+    hipLaunchKernelGGL((k_ds_finalize<EPI_RHAT>), dim3(nfb), block, 0, s, b, sc, partials);
+  else if (epi == EPI_TS)
+    hipLaunchKernelGGL((k_ds_finalize<EPI_TS>), dim3(nfb), block, 0, s, b, sc, partials);
+  else
+    hipLaunchKernelGGL((k_ds_finalize<EPI_RESID>), dim3(nfb), block, 0, s, b, sc, partials);
+  DBQ_HIP(hipGetLastError());
+}
 
 double launch_dslash_f64(hipStream_t s, const DsBatch& b, int dagger, int epi, RhsScal* sc,
                          double* partials, int nb, int rgroup) {

@@ -56,6 +56,18 @@ struct DsLat {
   double kappa, mu;
 };
 
+// Optional accounting of the algorithmic bytes of a gated launch, done by its finalize launch
+// (which sees which right-hand sides the Dslash processed): each processed rhs adds its spinor
+// traffic, and the first processed rhs of each lattice adds the lattice's links.
+struct DsAcct {
+  unsigned long long* bytes;  // device accumulator, or null for no accounting
+  unsigned long long* tags;   // device, MAXLAT entries: id of the last launch that counted links
+  unsigned long long id;      // this launch's id, larger than every earlier one
+  int spinor_passes;          // spinor vectors read or written per processed rhs-site
+  int spinor_bytes;           // bytes of one spinor at one site
+  int link_bytes;             // bytes of the links of one site
+};
+
 struct DsBatch {
   DsLat lat[MAXLAT];
   int nlat;
@@ -64,6 +76,7 @@ struct DsBatch {
   int pstride;     // partial-sum slots per rhs
   int nb;          // right-hand sides per thread (1, 2 or 4), set by the launcher
   int rgroup;      // thread rhs-groups sharing a sweep over the site blocks, set by the launcher
+  DsAcct acct;     // zero unless the caller accounts bytes of a gated launch
 };
 
 enum Epi : int { EPI_NONE = 0, EPI_RHAT = 1, EPI_TS = 2, EPI_RESID = 3 };
@@ -93,14 +106,20 @@ void pack_links_f32(hipStream_t s, const Geom& g, const void* canon, float4* out
 void gamma5_f64(hipStream_t s, const double2* in, double2* out, long long V, int count);
 
 // ----------------------------------------------------------------------------- dslash.hip
+// Launches the Dslash kernel alone; a launch with an epilogue must be followed by
+// launch_ds_finalize, which turns the per-block partial sums into the rhs scalars.
 // nb = right-hand sides per thread (1, 2, 4).  Returns the algorithmic HBM bytes of the launch
-// (links once, input once, output once, plus the epilogue operand).
+// when every rhs is processed (links once, input once, output once, plus the epilogue operand).
 // rgroup = how many rhs groups of nb sweep the site blocks together (block order: rhs chunk,
 // then site block, then rhs within the chunk); 0 means all of them.
 double launch_dslash_f64(hipStream_t s, const DsBatch& b, int dagger, int epi, RhsScal* sc,
                          double* partials, int nb, int rgroup);
 double launch_dslash_f32(hipStream_t s, const DsBatch& b, int dagger, int epi, RhsScal* sc,
                          double* partials, int nb, int rgroup);
+void launch_ds_finalize(hipStream_t s, const DsBatch& b, int epi, RhsScal* sc,
+                        const double* partials);
+// spinor vectors moved per processed rhs-site for an epilogue (in, out, and the epilogue operand)
+inline int ds_spinor_passes(int epi) { return (epi == EPI_RHAT || epi == EPI_RESID) ? 3 : 2; }
 
 // ----------------------------------------------------------------------------- bicg.hip
 enum BicgOp : int { BI_P = 0, BI_S = 1, BI_XR = 2 };

@@ -167,15 +167,29 @@ std::pair<int, int> choose_shape(dbq_ctx* c, bool f32, const DsBatch& b) {
   return best;
 }
 
-void run_dslash(dbq_ctx* c, bool f32, const DsBatch& b, int dagger, int epi, RhsScal* sc,
+void run_dslash(dbq_ctx* c, bool f32, const DsBatch& b0, int dagger, int epi, RhsScal* sc,
                 double* partials, int) {
-  const auto shape = choose_shape(c, f32, b);
+  const auto shape = choose_shape(c, f32, b0);
+  const int kind = f32 ? 1 : 0;
+  DsBatch b = b0;
+  b.acct = DsAcct{};
+  // a gated launch (scalars given) skips inactive rhs: its bytes are counted on the device
+  const bool dev_acct = c->timing && sc != nullptr && epi != EPI_NONE;
+  if (dev_acct) {
+    b.acct.bytes = c->acct + kind;
+    b.acct.tags = c->acct + 8 + 8 * kind;
+    b.acct.id = ++c->acct_seq;
+    b.acct.spinor_passes = ds_spinor_passes(epi);
+    b.acct.spinor_bytes = f32 ? 24 * 4 : 12 * 16;
+    b.acct.link_bytes = f32 ? 4 * 12 * 4 : 4 * 9 * 16;
+  }
   hipEvent_t e0;
-  timer_begin(c, f32 ? 1 : 0, &e0);
+  timer_begin(c, kind, &e0);
   const double bytes =
       f32 ? launch_dslash_f32(c->stream, b, dagger, epi, sc, partials, shape.first, shape.second)
           : launch_dslash_f64(c->stream, b, dagger, epi, sc, partials, shape.first, shape.second);
-  timer_end(c, f32 ? 1 : 0, e0, bytes);
+  timer_end(c, kind, e0, dev_acct ? 0.0 : bytes);
+  launch_ds_finalize(c->stream, b, epi, sc, partials);
 }
 
 template <typename T>
