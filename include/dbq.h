@@ -83,14 +83,22 @@ const char* dbq_last_error(const dbq_ctx* ctx);
 /* Change the stream later calls are ordered on. */
 int dbq_set_stream(dbq_ctx* ctx, void* hip_stream);
 
-/* Geometry tables of the even-odd site order used inside the library (Sec. 3 solves the
- * even-odd preconditioned system; here even-odd is the storage order of the full operator):
- * eo = parity*V/2 + (lex >> 1), parity = (x+y+z+t) mod 2.
+/* Geometry tables of the site order used inside the library.  Sec. 3 solves the even-odd
+ * preconditioned system; here even-odd is the storage order of the full operator, blocked into
+ * 4-d tiles of T0 x T1 x T2 x T3 sites (powers of two dividing the extents, reported by
+ * dbq_site_tile):
+ *   eo = parity*V/2 + tile*(T0*T1*T2*T3/2) + (in-tile lex >> 1),   parity = (x+y+z+t) mod 2,
+ * tile = lexicographic index of (x/T0, y/T1, z/T2, t/T3) over the tile grid, in-tile lex =
+ * (x mod T0) + T0*((y mod T1) + T1*((z mod T2) + T2*(t mod T3))).
  * lex_of_eo: DEVICE int32 [V]; nbr: DEVICE int32 [8][V] with nbr[2*mu][eo] = eo index of x+mu and
  * nbr[2*mu+1][eo] = eo index of x-mu.  dbq_geometry_host fills HOST arrays with the same values
- * from the same index arithmetic on the CPU. */
+ * from the same index arithmetic on the CPU.  Extents must be even and >= 2 (DBQ_EINVAL). */
 int dbq_geometry(dbq_ctx* ctx, const int32_t L[4], int32_t* lex_of_eo, int32_t* nbr);
 int dbq_geometry_host(const int32_t L[4], int32_t* lex_of_eo, int32_t* nbr);
+/* Tile extents T[4] (host array) of the internal site order for extents L: per direction the
+ * largest power of two dividing L_mu, at most 4 (a tile holds at most 4^4 = 256 sites).  Host
+ * only; DBQ_EINVAL for odd or < 2 extents. */
+int dbq_site_tile(const int32_t L[4], int32_t* T);
 
 /* out = A(mu) in (dagger = 0) or A(mu)^dagger in (dagger = 1) for nrhs right-hand sides
  * (Sec. 1 operator; the matrix-vector product every solver in the paper is costed in).

@@ -50,13 +50,24 @@ class Lattice:
     * ``parity[lex]``     -- (x + y + z + t) mod 2
     * ``eo_of_lex[lex]``  -- even-odd index parity*V/2 + (lex >> 1)   (a bijection for even Lx)
     * ``lex_of_eo[eo]``   -- the inverse permutation
+
+    With ``tile`` = (T0, T1, T2, T3) (each even and dividing the extent) the even-odd order is
+    blocked into tiles: eo = parity*V/2 + tile_index*(T0*T1*T2*T3/2) + (in_tile_lex >> 1), where
+    tile_index is the lexicographic index of (x//T0, y//T1, z//T2, t//T3) over the tile grid and
+    in_tile_lex that of (x%T0, y%T1, z%T2, t%T3) inside the tile.  One tile covering the whole
+    lattice gives the plain order.  (A storage order only: the operator does not depend on it.)
     """
 
-    def __init__(self, L):
+    def __init__(self, L, tile=None):
         L = tuple(int(v) for v in L)
         if len(L) != 4 or any(v < 1 for v in L):
             raise ValueError("need four positive extents")
+        if tile is not None:
+            tile = tuple(int(v) for v in tile)
+            if len(tile) != 4 or any(t < 2 or t % 2 or l % t for t, l in zip(tile, L)):
+                raise ValueError("tile extents must be even and divide the lattice extents")
         self.L = L
+        self.tile = tile
         self.V = L[0] * L[1] * L[2] * L[3]
         lex = np.arange(self.V)
         x = lex % L[0]
@@ -74,7 +85,18 @@ class Lattice:
             cm[:, mu] = (cm[:, mu] - 1) % L[mu]
             self.bwd[mu] = self.lex(cm)
         self.parity = self.coords.sum(axis=1) % 2
-        if L[0] % 2 == 0:
+        if tile is not None:
+            T = np.array(tile)
+            NT = np.array(L) // T
+            tc = self.coords // T
+            ic = self.coords % T
+            tile_index = tc[:, 0] + NT[0] * (tc[:, 1] + NT[1] * (tc[:, 2] + NT[2] * tc[:, 3]))
+            in_tile_lex = ic[:, 0] + T[0] * (ic[:, 1] + T[1] * (ic[:, 2] + T[2] * ic[:, 3]))
+            half = int(np.prod(T)) // 2
+            self.eo_of_lex = self.parity * (self.V // 2) + tile_index * half + (in_tile_lex >> 1)
+            self.lex_of_eo = np.empty(self.V, dtype=np.int64)
+            self.lex_of_eo[self.eo_of_lex] = lex
+        elif L[0] % 2 == 0:
             self.eo_of_lex = self.parity * (self.V // 2) + (lex >> 1)
             self.lex_of_eo = np.empty(self.V, dtype=np.int64)
             self.lex_of_eo[self.eo_of_lex] = lex

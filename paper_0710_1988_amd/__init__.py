@@ -19,7 +19,7 @@ from . import _abi
 from ._abi import DBQ_FP64, DBQ_MIXED, Stats, Operator
 
 __all__ = ["DbqError", "wilson_apply", "gmresdr_first_rhs", "dbicgstab_solve", "project_shifts",
-           "link_force", "kappa_critical", "geometry", "geometry_host", "set_timing",
+           "link_force", "kappa_critical", "geometry", "geometry_host", "site_tile", "set_timing",
            "kernel_time", "reset_timing", "version", "library_path", "DeflatedSolve"]
 
 
@@ -321,6 +321,16 @@ def geometry_host(L):
     if st != 0:
         raise DbqError(st, "dbq_geometry_host failed")
     return lex, nbr
+
+
+def site_tile(L):
+    """Tile extents (T0, T1, T2, T3) of the library's internal site order for extents L."""
+    L, V = _lattice(L)
+    T = (ctypes.c_int32 * 4)()
+    st = _abi.load().dbq_site_tile((ctypes.c_int32 * 4)(*L), T)
+    if st != 0:
+        raise DbqError(st, "dbq_site_tile failed")
+    return tuple(int(v) for v in T)
 
 
 def set_timing(on, device=None):

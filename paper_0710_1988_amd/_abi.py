@@ -18,7 +18,7 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EBREAKDOWN", -3:
                 -4: "EHIP", -5: "ENOMEM"}
 
 EXPORTED = ["dbq_create", "dbq_destroy", "dbq_last_error", "dbq_set_stream", "dbq_geometry",
-            "dbq_geometry_host", "wilson_apply", "gmresdr_first_rhs", "dbicgstab_solve",
+            "dbq_geometry_host", "dbq_site_tile", "wilson_apply", "gmresdr_first_rhs", "dbicgstab_solve",
             "project_shifts", "link_force", "kappa_critical", "dbq_set_timing", "dbq_kernel_time",
             "dbq_reset_timing", "dbq_version"]
 
@@ -63,6 +63,7 @@ def load():
         "dbq_set_stream": ([P, P], ctypes.c_int),
         "dbq_geometry": ([P, PI32, P, P], ctypes.c_int),
         "dbq_geometry_host": ([PI32, PI32, PI32], ctypes.c_int),
+        "dbq_site_tile": ([PI32, PI32], ctypes.c_int),
         "wilson_apply": ([P, POP, P, P, I32, I32, I32], ctypes.c_int),
         "gmresdr_first_rhs": ([P, POP, P, P, I32, I32, D, I64, P, PD, PI32, PST], ctypes.c_int),
         "dbicgstab_solve": ([P, POP, I32, ctypes.POINTER(P), PI32, ctypes.POINTER(P),

@@ -90,6 +90,15 @@ int dbq_geometry(dbq_ctx* c, const int32_t L[4], int32_t* lex_of_eo, int32_t* nb
   });
 }
 
+int dbq_site_tile(const int32_t L[4], int32_t* T) {
+  if (!L || !T) return DBQ_EINVAL;
+  for (int i = 0; i < 4; ++i)
+    if (L[i] < 2 || L[i] % 2) return DBQ_EINVAL;
+  const dbq::Geom g = dbq::make_geom(L);
+  for (int i = 0; i < 4; ++i) T[i] = g.T[i];
+  return DBQ_OK;
+}
+
 int dbq_geometry_host(const int32_t L[4], int32_t* lex_of_eo, int32_t* nbr) {
   if (!L || !lex_of_eo || !nbr) return DBQ_EINVAL;
   for (int i = 0; i < 4; ++i)

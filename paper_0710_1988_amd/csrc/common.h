@@ -98,38 +98,80 @@ struct FastDiv {
 };
 
 // ----------------------------------------------------------------------------- lattice geometry
-// Even-odd order of the full lattice: eo = p*V/2 + (lex >> 1), p = (x+y+z+t) & 1.  Since Lx is
-// even, lex >> 1 = x/2 + (Lx/2)*(y + Ly*(z + Lz*t)) and each value is taken once per parity.
+// Internal site order: even-odd, blocked into 4-d tiles.  The lattice is cut into tiles of
+// T0 x T1 x T2 x T3 sites (powers of two dividing the extents, so every tile origin has an even
+// coordinate sum and each tile holds T/2 sites of either parity).  Site x of parity p gets
+//   eo = p * V/2 + tile(x) * T/2 + (in-tile lex(x) >> 1),
+// tile(x) = lexicographic index of floor(x_mu / T_mu) over the tile grid and in-tile lex the
+// lexicographic index of x_mu mod T_mu inside the tile.  Consecutive indices of one parity fill
+// one tile before the next, so a site's eight neighbours mostly lie in the same tile (or the
+// neighbouring one in x or y) and are served by the cache that already holds it.  With a single
+// tile covering the lattice this is the plain order p * V/2 + (lex >> 1).
 struct Geom {
   int L[4];
-  int V, Vh, Lxh;
-  FastDiv dLxh, dLy, dLz;
+  int V, Vh;
+  int T[4];   // tile extents
+  int lT[4];  // log2 of the tile extents
+  int NT[4];  // tiles per direction
+  int lTh;    // log2 of the half-sites per tile
+  FastDiv dNT0, dNT1, dNT2;
 };
+
+// Tile extents for a lattice: per direction the largest power of two that divides L_mu and
+// does not exceed 4 (all extents are even, so at least 2).  A tile holds at most 256 sites.
+constexpr int TILE_MAX = 4;
+inline void choose_tile(const int32_t L[4], int T[4]) {
+  for (int i = 0; i < 4; ++i) {
+    int t = 2;
+    while (t * 2 <= TILE_MAX && L[i] % (t * 2) == 0) t *= 2;
+    T[i] = t;
+  }
+}
+
+inline int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
 
 inline Geom make_geom(const int32_t L[4]) {
   Geom g;
   for (int i = 0; i < 4; ++i) g.L[i] = L[i];
   g.V = L[0] * L[1] * L[2] * L[3];
   g.Vh = g.V / 2;
-  g.Lxh = L[0] / 2;
-  g.dLxh = FastDiv(uint32_t(g.Lxh));
-  g.dLy = FastDiv(uint32_t(L[1]));
-  g.dLz = FastDiv(uint32_t(L[2]));
+  choose_tile(L, g.T);
+  for (int i = 0; i < 4; ++i) {
+    g.lT[i] = ilog2(g.T[i]);
+    g.NT[i] = L[i] / g.T[i];
+  }
+  g.lTh = g.lT[0] + g.lT[1] + g.lT[2] + g.lT[3] - 1;
+  g.dNT0 = FastDiv(uint32_t(g.NT[0]));
+  g.dNT1 = FastDiv(uint32_t(g.NT[1]));
+  g.dNT2 = FastDiv(uint32_t(g.NT[2]));
   return g;
 }
 
-// coordinates (x, y, z, t) and parity of even-odd index s
+// coordinates (x, y, z, t) and parity of internal index s
 __host__ __device__ __forceinline__ void eo_coords(const Geom& g, int s, int c[4], int& p) {
   p = s >= g.Vh ? 1 : 0;
-  uint32_t h = uint32_t(s - p * g.Vh);
-  uint32_t r = g.dLxh.div(h);
-  int xh = int(h - r * uint32_t(g.Lxh));
-  uint32_t r2 = g.dLy.div(r);
-  c[1] = int(r - r2 * uint32_t(g.L[1]));
-  uint32_t r3 = g.dLz.div(r2);
-  c[2] = int(r2 - r3 * uint32_t(g.L[2]));
-  c[3] = int(r3);
-  c[0] = 2 * xh + ((p + c[1] + c[2] + c[3]) & 1);
+  const uint32_t h = uint32_t(s - p * g.Vh);
+  const uint32_t tile = h >> g.lTh;
+  // in-tile lex of the even-x member of the pair that shares this half index
+  uint32_t r = (h & ((1u << g.lTh) - 1u)) << 1;
+  const int ix = int(r & uint32_t(g.T[0] - 1));
+  r >>= g.lT[0];
+  const int iy = int(r & uint32_t(g.T[1] - 1));
+  r >>= g.lT[1];
+  const int iz = int(r & uint32_t(g.T[2] - 1));
+  const int it = int(r >> g.lT[2]);
+  const uint32_t q1 = g.dNT0.div(tile);
+  const uint32_t q2 = g.dNT1.div(q1);
+  const uint32_t q3 = g.dNT2.div(q2);
+  c[1] = (int(q1 - q2 * uint32_t(g.NT[1])) << g.lT[1]) + iy;
+  c[2] = (int(q2 - q3 * uint32_t(g.NT[2])) << g.lT[2]) + iz;
+  c[3] = (int(q3) << g.lT[3]) + it;
+  // tile origins have even coordinate sums: the parity of x is that of its in-tile coordinates
+  c[0] = (int(tile - q1 * uint32_t(g.NT[0])) << g.lT[0]) + ix + ((p + iy + iz + it) & 1);
 }
 
 __host__ __device__ __forceinline__ int lex_index(const Geom& g, const int c[4]) {
@@ -137,11 +179,17 @@ __host__ __device__ __forceinline__ int lex_index(const Geom& g, const int c[4])
 }
 
 __host__ __device__ __forceinline__ int eo_of_coords(const Geom& g, const int c[4]) {
-  int p = (c[0] + c[1] + c[2] + c[3]) & 1;
-  return p * g.Vh + (lex_index(g, c) >> 1);
+  const int p = (c[0] + c[1] + c[2] + c[3]) & 1;
+  const int tile = (c[0] >> g.lT[0]) +
+                   g.NT[0] * ((c[1] >> g.lT[1]) + g.NT[1] * ((c[2] >> g.lT[2]) +
+                                                             g.NT[2] * (c[3] >> g.lT[3])));
+  const int il = (c[0] & (g.T[0] - 1)) | ((c[1] & (g.T[1] - 1)) << g.lT[0]) |
+                 ((c[2] & (g.T[2] - 1)) << (g.lT[0] + g.lT[1])) |
+                 ((c[3] & (g.T[3] - 1)) << (g.lT[0] + g.lT[1] + g.lT[2]));
+  return p * g.Vh + (tile << g.lTh) + (il >> 1);
 }
 
-// eo index of the neighbour x + dir*mu (dir = +1 or -1), periodic
+// internal index of the neighbour x + dir*mu (dir = +1 or -1), periodic
 template <int MU, int DIR>
 __host__ __device__ __forceinline__ int eo_neighbour(const Geom& g, const int c[4]) {
   int d[4] = {c[0], c[1], c[2], c[3]};

@@ -370,6 +370,53 @@ __device__ __forceinline__ void chain(int (&c)[4], int& s, cx<T> (&acc)[NB][12])
 #endif
 }
 
+// The site's result psi - kappa*acc + i*t*gamma5*psi (t = mu, or -mu for the dagger) and the
+// epilogue's contributions to the per-block sums: RESID replaces the result by aux - result and
+// adds its norm, RHAT adds <aux, result>, TS adds <result, psi> and |result|^2.
+template <typename T, int EPI>
+__device__ __forceinline__ void finish_site(const cx<T> (&psi)[12], const cx<T> (&acc)[12], T kap,
+                                            T tm, const typename IO<T>::SE* __restrict__ aux,
+                                            int V, int s, double& r0, double& r1, double& r2,
+                                            cx<T> (&o)[12]) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    // gamma5 = diag(1,1,-1,-1) over spins
+    const T t = k < 6 ? tm : -tm;
+    o[k].re = fma(-kap, acc[k].re, fma(-t, psi[k].im, psi[k].re));
+    o[k].im = fma(-kap, acc[k].im, fma(t, psi[k].re, psi[k].im));
+  }
+  if (EPI == EPI_RESID) {
+    cx<T> b[12];
+    IO<T>::load(aux, V, s, b);
+    T nn = T(0);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      o[k] = b[k] - o[k];
+      nn = fma(o[k].re, o[k].re, fma(o[k].im, o[k].im, nn));
+    }
+    r0 += double(nn);
+  } else if (EPI == EPI_RHAT) {
+    cx<T> rh[12];
+    IO<T>::load(aux, V, s, rh);
+    cx<T> d{T(0), T(0)};
+#pragma unroll
+    for (int k = 0; k < 12; ++k) cmacc(d, rh[k], o[k]);
+    r0 += double(d.re);
+    r1 += double(d.im);
+  } else if (EPI == EPI_TS) {
+    cx<T> d{T(0), T(0)};
+    T nn = T(0);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      cmacc(d, o[k], psi[k]);
+      nn = fma(o[k].re, o[k].re, fma(o[k].im, o[k].im, nn));
+    }
+    r0 += double(d.re);
+    r1 += double(d.im);
+    r2 += double(nn);
+  }
+}
+
 #if DBQ_OCC_F32 > 0
 // Minimum waves per SIMD the register allocation must leave room for.
 template <typename T, int NB>
@@ -458,43 +505,8 @@ void k_dslash(DsBatch B, RhsScal* __restrict__ sc, double* __restrict__ partials
       cx<T> psi[12];
       IO<T>::load(in + j * rstride, V, s, psi);
       cx<T> o[12];
-#pragma unroll
-      for (int k = 0; k < 12; ++k) {
-        // psi - kappa acc + i mu gamma5 psi, gamma5 = diag(1,1,-1,-1) over spins
-        const T t = k < 6 ? tm : -tm;
-        o[k].re = fma(-kap, acc[j][k].re, fma(-t, psi[k].im, psi[k].re));
-        o[k].im = fma(-kap, acc[j][k].im, fma(t, psi[k].re, psi[k].im));
-      }
-      if (EPI == EPI_RESID) {
-        cx<T> b[12];
-        IO<T>::load((const SE*)L.aux + (r0 + j) * rstride, V, s, b);
-        T nn = T(0);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-          o[k] = b[k] - o[k];
-          nn = fma(o[k].re, o[k].re, fma(o[k].im, o[k].im, nn));
-        }
-        red[3 * j] += double(nn);
-      } else if (EPI == EPI_RHAT) {
-        cx<T> rh[12];
-        IO<T>::load((const SE*)L.aux + (r0 + j) * rstride, V, s, rh);
-        cx<T> d{T(0), T(0)};
-#pragma unroll
-        for (int k = 0; k < 12; ++k) cmacc(d, rh[k], o[k]);
-        red[3 * j] += double(d.re);
-        red[3 * j + 1] += double(d.im);
-      } else if (EPI == EPI_TS) {
-        cx<T> d{T(0), T(0)};
-        T nn = T(0);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-          cmacc(d, o[k], psi[k]);
-          nn = fma(o[k].re, o[k].re, fma(o[k].im, o[k].im, nn));
-        }
-        red[3 * j] += double(d.re);
-        red[3 * j + 1] += double(d.im);
-        red[3 * j + 2] += double(nn);
-      }
+      finish_site<T, EPI>(psi, acc[j], kap, tm, (const SE*)L.aux + (r0 + j) * rstride, V, s,
+                          red[3 * j], red[3 * j + 1], red[3 * j + 2], o);
       IO<T>::store(out + j * rstride, V, s, o);
     }
   }
@@ -511,6 +523,297 @@ void k_dslash(DsBatch B, RhsScal* __restrict__ sc, double* __restrict__ partials
         pp[2] = red[3 * j + 2];
       }
     }
+  }
+}
+
+// ============================================================================ LDS-staged FP32
+// One block per (site tile, chunk of right-hand sides).  The block holds the 8 links of each of
+// its sites in registers for the whole chunk and, for one rhs after the other, copies the
+// tile's spinors and the eight neighbouring faces into LDS with LDS-direct loads (no registers
+// held while they are in flight), then every site reads its eight neighbours from LDS.  Each
+// spinor of the tile therefore passes through the vector memory unit once per rhs instead of
+// nine times (once as a centre, eight times as a neighbour), and each link once per chunk.
+//
+// LDS slots (per spinor component k = 0..5, float4 each, TL_SLOTS per component):
+//   [0, Vt)       the tile: parity p = slot >= Vt/2, the slot's half index in the tile
+//                 (the same order as in memory, so each parity half is one contiguous copy)
+//   [Vt, Vt + H)  faces (mu, +), (mu, -) for mu = 0..3: the Vt/T_mu sites of the tile beyond
+//                 this one in direction +-mu next to it, in lexicographic order of the three
+//                 other in-tile coordinates
+constexpr int TL_SLOTS = 768;  // 4^4 tile: 256 + 8 x 64
+
+struct TileGeo {
+  int vt, vh;        // sites per tile, per parity
+  int fbase[8];      // first slot of each face
+};
+
+__device__ __forceinline__ TileGeo tile_geo(const Geom& g) {
+  TileGeo t;
+  t.vh = 1 << g.lTh;
+  t.vt = 2 * t.vh;
+  int b = t.vt;
+#pragma unroll
+  for (int f = 0; f < 8; ++f) {
+    t.fbase[f] = b;
+    b += t.vt >> g.lT[f >> 1];
+  }
+  return t;
+}
+
+// in-tile coordinates of tile slot j < Vt (tile origins have even coordinate sums)
+__device__ __forceinline__ void tile_coords(const Geom& g, const TileGeo& t, int j, int (&ic)[4]) {
+  const int p = j >= t.vh ? 1 : 0;
+  uint32_t r = uint32_t(j - p * t.vh) << 1;
+  ic[0] = int(r & uint32_t(g.T[0] - 1));
+  r >>= g.lT[0];
+  ic[1] = int(r & uint32_t(g.T[1] - 1));
+  r >>= g.lT[1];
+  ic[2] = int(r & uint32_t(g.T[2] - 1));
+  ic[3] = int(r >> g.lT[2]);
+  ic[0] += (p + ic[1] + ic[2] + ic[3]) & 1;
+}
+
+__device__ __forceinline__ int in_tile_half(const Geom& g, const int (&ic)[4]) {
+  const int il = ic[0] | (ic[1] << g.lT[0]) | (ic[2] << (g.lT[0] + g.lT[1])) |
+                 (ic[3] << (g.lT[0] + g.lT[1] + g.lT[2]));
+  return il >> 1;
+}
+
+// position of in-tile coordinates on the face orthogonal to MU
+template <int MU>
+__device__ __forceinline__ int face_index(const Geom& g, const int (&ic)[4]) {
+  int q = 0, sh = 0;
+#pragma unroll
+  for (int nu = 0; nu < 4; ++nu) {
+    if (nu == MU) continue;
+    q |= ic[nu] << sh;
+    sh += g.lT[nu];
+  }
+  return q;
+}
+
+// LDS slot of the neighbour x + DIR*MU of the tile site with in-tile coordinates ic
+template <int MU, int DIR>
+__device__ __forceinline__ int nbr_slot(const Geom& g, const TileGeo& t, const int (&ic)[4]) {
+  const int v = ic[MU] + DIR;
+  if (v >= 0 && v < g.T[MU]) {
+    int d[4] = {ic[0], ic[1], ic[2], ic[3]};
+    d[MU] = v;
+    const int p = (d[0] + d[1] + d[2] + d[3]) & 1;
+    return p * t.vh + in_tile_half(g, d);
+  }
+  return t.fbase[2 * MU + (DIR > 0 ? 0 : 1)] + face_index<MU>(g, ic);
+}
+
+// memory index (internal order) of the site held in LDS slot j of tile tc; slots past the last
+// face repeat the tile's first site (their copies are never read)
+__device__ __forceinline__ int slot_site(const Geom& g, const TileGeo& t, const int (&tc)[4],
+                                         int tile, int j, int nslots) {
+  if (j < t.vt) {
+    const int p = j >= t.vh ? 1 : 0;
+    return p * g.Vh + (tile << g.lTh) + (j - p * t.vh);
+  }
+  if (j >= nslots) return tile << g.lTh;
+  int f = 0;
+#pragma unroll
+  for (int i = 1; i < 8; ++i)
+    if (j >= t.fbase[i]) f = i;
+  const int mu = f >> 1;
+  const int dir = (f & 1) ? -1 : +1;
+  uint32_t q = uint32_t(j - t.fbase[f]);
+  int ic[4];
+#pragma unroll
+  for (int nu = 0; nu < 4; ++nu) {
+    if (nu == mu) {
+      ic[nu] = dir > 0 ? 0 : g.T[nu] - 1;
+    } else {
+      ic[nu] = int(q & uint32_t(g.T[nu] - 1));
+      q >>= g.lT[nu];
+    }
+  }
+  int tn[4] = {tc[0], tc[1], tc[2], tc[3]};
+  int v = tn[mu] + dir;
+  v = v < 0 ? g.NT[mu] - 1 : (v == g.NT[mu] ? 0 : v);
+  tn[mu] = v;
+  const int tile_n = tn[0] + g.NT[0] * (tn[1] + g.NT[1] * (tn[2] + g.NT[2] * tn[3]));
+  const int p = (ic[0] + ic[1] + ic[2] + ic[3]) & 1;
+  return p * g.Vh + (tile_n << g.lTh) + in_tile_half(g, ic);
+}
+
+__device__ __forceinline__ void lds_spinor(const float4* lds, int slot, zf (&p)[12]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const float4 v = lds[k * TL_SLOTS + slot];
+    p[2 * k] = zf{v.x, v.y};
+    p[2 * k + 1] = zf{v.z, v.w};
+  }
+}
+
+__device__ __forceinline__ void rebuild(const float4 (&l)[3], zf (&u)[9]) {
+  u[0] = zf{l[0].x, l[0].y};
+  u[1] = zf{l[0].z, l[0].w};
+  u[2] = zf{l[1].x, l[1].y};
+  u[3] = zf{l[1].z, l[1].w};
+  u[4] = zf{l[2].x, l[2].y};
+  u[5] = zf{l[2].z, l[2].w};
+  u[6] = cross_conj(u[1], u[5], u[2], u[4]);
+  u[7] = cross_conj(u[2], u[3], u[0], u[5]);
+  u[8] = cross_conj(u[0], u[4], u[1], u[3]);
+}
+
+// one hop from LDS: BACK = false -> (1 + S gamma) U psi(slot); BACK = true -> U^dagger instead
+template <int MU, int S, bool BACK>
+__device__ __forceinline__ void hop_lds(const float4* lds, int slot, const float4 (&l)[3],
+                                        zf (&acc)[12]) {
+  zf u[9];
+  rebuild(l, u);
+  zf p[12];
+  lds_spinor(lds, slot, p);
+  zf h[6];
+  project<float, MU, S>(p, h);
+  zf chi[6];
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      zf z{0.f, 0.f};
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        if (!BACK) cmac(z, u[3 * a + b], h[3 * sp + b]);
+        else cmacc(z, u[3 * b + a], h[3 * sp + b]);
+      }
+      chi[3 * sp + a] = z;
+    }
+  }
+  spread<float, MU, S>(acc, chi);
+}
+
+template <bool DAG, int EPI>
+__global__ __launch_bounds__(DS_BS) void k_dslash_tile(DsBatch B, RhsScal* __restrict__ sc,
+                                                       double* __restrict__ partials, int gate) {
+  __shared__ float4 lds[6 * TL_SLOTS];
+  const int lb = xcd_block(blockIdx.x, B.nblocks);
+  int l = 0;
+#pragma unroll
+  for (int i = 1; i < MAXLAT; ++i)
+    if (i < B.nlat && lb >= B.lat[i].blk_begin) l = i;
+  const DsLat& L = B.lat[l];
+  const Geom& g = L.g;
+  const int G = (B.rgroup <= 0 || B.rgroup > L.nrhs) ? L.nrhs : B.rgroup;
+  const int nch = (L.nrhs + G - 1) / G;
+  const int loc = lb - L.blk_begin;
+  const int tile = loc / nch;  // chunks of one tile are adjacent blocks (they share the links)
+  const int r0 = (loc - tile * nch) * G;
+  const int Gc = min(G, L.nrhs - r0);
+  const int V = g.V;
+  const TileGeo tg = tile_geo(g);
+  const int nslots = tg.fbase[7] + (tg.vt >> g.lT[3]);
+  int tc[4];
+  {
+    const uint32_t q1 = g.dNT0.div(uint32_t(tile));
+    const uint32_t q2 = g.dNT1.div(q1);
+    const uint32_t q3 = g.dNT2.div(q2);
+    tc[0] = int(uint32_t(tile) - q1 * uint32_t(g.NT[0]));
+    tc[1] = int(q1 - q2 * uint32_t(g.NT[1]));
+    tc[2] = int(q2 - q3 * uint32_t(g.NT[2]));
+    tc[3] = int(q3);
+  }
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // LDS-direct copies: wave wv fills the 64-slot chunks wv, wv + 4, wv + 8 of every component
+  const int nck = (nslots + 63) >> 6;
+  int seo[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) seo[i] = slot_site(g, tg, tc, tile, (wv + 4 * i) * 64 + lane, nslots);
+
+  const bool own = tid < tg.vt;
+  int ic[4] = {0, 0, 0, 0}, s = 0;
+  int ns[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  float4 lf[4][3], lbk[4][3];
+  if (own) {
+    tile_coords(g, tg, tid, ic);
+    const int p = tid >= tg.vh ? 1 : 0;
+    s = p * g.Vh + (tile << g.lTh) + (tid - p * tg.vh);
+    int c[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) c[mu] = (tc[mu] << g.lT[mu]) + ic[mu];
+    ns[0] = nbr_slot<0, +1>(g, tg, ic);
+    ns[1] = nbr_slot<0, -1>(g, tg, ic);
+    ns[2] = nbr_slot<1, +1>(g, tg, ic);
+    ns[3] = nbr_slot<1, -1>(g, tg, ic);
+    ns[4] = nbr_slot<2, +1>(g, tg, ic);
+    ns[5] = nbr_slot<2, -1>(g, tg, ic);
+    ns[6] = nbr_slot<3, +1>(g, tg, ic);
+    ns[7] = nbr_slot<3, -1>(g, tg, ic);
+    int yb[4];
+    yb[0] = eo_neighbour<0, -1>(g, c);
+    yb[1] = eo_neighbour<1, -1>(g, c);
+    yb[2] = eo_neighbour<2, -1>(g, c);
+    yb[3] = eo_neighbour<3, -1>(g, c);
+    const float4* U = (const float4*)L.links;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        lf[mu][k] = ldo(U + (long long)(mu * 3 + k) * V, unsigned(s) * 16u);
+        lbk[mu][k] = ldo(U + (long long)(mu * 3 + k) * V, unsigned(yb[mu]) * 16u);
+      }
+  }
+  constexpr int SF = DAG ? +1 : -1;  // forward hop (1 - gamma), dagger (1 + gamma)
+  constexpr int SB = -SF;
+  const float kap = float(L.kappa);
+  const float tm = float(DAG ? -L.mu : L.mu);
+  for (int j = 0; j < Gc; ++j) {
+    const int r = r0 + j;
+    bool act = true;
+    if (gate == 1) act = sc[L.rhs_base + r].active != 0;
+    else if (gate == 2) act = sc[L.rhs_base + r].sel != 0;
+    if (!act) continue;  // uniform over the block
+    const float4* in = (const float4*)L.in + (long long)r * 6 * V;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int ck = wv + 4 * i;
+      if (ck < nck) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+          __builtin_amdgcn_global_load_lds(
+              (const void*)(in + (long long)k * V + seo[i]),
+              (__attribute__((address_space(3))) void*)(lds + k * TL_SLOTS + ck * 64), 16, 0, 0);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    double red[3] = {0.0, 0.0, 0.0};
+    if (own) {
+      zf acc[12];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) acc[k] = zf{0.f, 0.f};
+      hop_lds<0, SF, false>(lds, ns[0], lf[0], acc);
+      hop_lds<0, SB, true>(lds, ns[1], lbk[0], acc);
+      hop_lds<1, SF, false>(lds, ns[2], lf[1], acc);
+      hop_lds<1, SB, true>(lds, ns[3], lbk[1], acc);
+      hop_lds<2, SF, false>(lds, ns[4], lf[2], acc);
+      hop_lds<2, SB, true>(lds, ns[5], lbk[2], acc);
+      hop_lds<3, SF, false>(lds, ns[6], lf[3], acc);
+      hop_lds<3, SB, true>(lds, ns[7], lbk[3], acc);
+      zf psi[12];
+      lds_spinor(lds, tid, psi);
+      zf o[12];
+      finish_site<float, EPI>(psi, acc, kap, tm,
+                              (const float4*)L.aux + (long long)r * 6 * V, V, s, red[0], red[1],
+                              red[2], o);
+      IO<float>::store((float4*)L.out + (long long)r * 6 * V, V, s, o);
+    }
+    if (EPI != EPI_NONE) {
+      __shared__ double sh[3 * (DS_BS / 64)];
+      block_sum<3, DS_BS>(red, sh);
+      if (tid == 0) {
+        double* pp = partials + ((long long)(L.rhs_base + r) * B.pstride + tile) * 3;
+        pp[0] = red[0];
+        pp[1] = red[1];
+        pp[2] = red[2];
+      }
+    }
+    __syncthreads();  // the next rhs overwrites the LDS copy
   }
 }
 
@@ -540,27 +843,57 @@ void launch_epi(hipStream_t s, const DsBatch& b, int epi, RhsScal* sc, double* p
   }
 }
 
+template <bool DAG>
+void launch_tile_epi(hipStream_t s, const DsBatch& b, int epi, RhsScal* sc, double* partials,
+                     int gate) {
+  dim3 grid(b.nblocks), block(DS_BS);
+  switch (epi) {
+    case EPI_NONE: hipLaunchKernelGGL((k_dslash_tile<DAG, EPI_NONE>), grid, block, 0, s, b, sc, partials, gate); break;
+    case EPI_RHAT: hipLaunchKernelGGL((k_dslash_tile<DAG, EPI_RHAT>), grid, block, 0, s, b, sc, partials, gate); break;
+    case EPI_TS: hipLaunchKernelGGL((k_dslash_tile<DAG, EPI_TS>), grid, block, 0, s, b, sc, partials, gate); break;
+    default: hipLaunchKernelGGL((k_dslash_tile<DAG, EPI_RESID>), grid, block, 0, s, b, sc, partials, gate); break;
+  }
+}
+
 template <typename T>
-double launch(hipStream_t s, const DsBatch& in, int dagger, int epi, RhsScal* sc, double* partials,
+double launch(hipStream_t s, DsBatch& b, int dagger, int epi, RhsScal* sc, double* partials,
               int nb, int rgroup) {
-  DBQ_CHECK(in.nlat >= 1 && in.nlat <= MAXLAT, "dslash: bad lattice count");
+  DBQ_CHECK(b.nlat >= 1 && b.nlat <= MAXLAT, "dslash: bad lattice count");
   DBQ_CHECK(epi == EPI_NONE || (sc && partials), "dslash: epilogue needs scalars");
-  DBQ_CHECK(nb == 1 || nb == 2 || nb == 4, "dslash: rhs per thread must be 1, 2 or 4");
-  // block layout for nb right-hand sides per thread: per lattice nsb site blocks x rhs groups
-  DsBatch b = in;
-  b.nb = nb;
+  const bool tiled = nb == 0;
+  DBQ_CHECK(nb == 1 || nb == 2 || nb == 4 || (tiled && sizeof(T) == 4),
+            "dslash: rhs per thread must be 1, 2 or 4 (0: LDS-staged tiles, FP32)");
+  // block layout: per lattice nsb site blocks (tiles for the LDS-staged kernel) x rhs groups
+  b.nb = tiled ? 1 : nb;
   b.rgroup = rgroup;
   long long blk = 0;
   for (int i = 0; i < b.nlat; ++i) {
-    b.lat[i].blk_begin = int(blk);
-    blk += (long long)b.lat[i].nsb * ((b.lat[i].nrhs + nb - 1) / nb);
+    DsLat& L = b.lat[i];
+    L.blk_begin = int(blk);
+    if (tiled) {
+      DBQ_CHECK(L.g.T[0] <= 4 && L.g.T[1] <= 4 && L.g.T[2] <= 4 && L.g.T[3] <= 4,
+                "dslash: tile larger than 4^4");
+      L.nsb = L.g.V >> (L.g.lTh + 1);
+      const int G = (rgroup <= 0 || rgroup > L.nrhs) ? L.nrhs : rgroup;
+      blk += (long long)L.nsb * ((L.nrhs + G - 1) / G);
+    } else {
+      L.nsb = 2 * ((L.g.Vh + DS_BS - 1) / DS_BS);
+      blk += (long long)L.nsb * ((L.nrhs + nb - 1) / nb);
+    }
+    DBQ_CHECK(epi == EPI_NONE || L.nsb <= b.pstride, "dslash: partial-sum slots too few");
   }
   DBQ_CHECK(blk > 0 && blk < (1ll << 31), "dslash: grid size out of range");
   b.nblocks = int(blk);
   int gate = 0;
   if (sc) gate = (epi == EPI_RESID) ? 2 : 1;
-  if (dagger) launch_epi<T, true>(s, b, epi, sc, partials, gate);
-  else launch_epi<T, false>(s, b, epi, sc, partials, gate);
+  if (tiled) {
+    if (dagger) launch_tile_epi<true>(s, b, epi, sc, partials, gate);
+    else launch_tile_epi<false>(s, b, epi, sc, partials, gate);
+  } else if (dagger) {
+    launch_epi<T, true>(s, b, epi, sc, partials, gate);
+  } else {
+    launch_epi<T, false>(s, b, epi, sc, partials, gate);
+  }
   DBQ_HIP(hipGetLastError());
   // algorithmic bytes: links once per lattice, each spinor read once and written once, plus
   // one epilogue operand per site (rhat or b)
@@ -592,11 +925,11 @@ void launch_ds_finalize(hipStream_t s, const DsBatch& b, int epi, RhsScal* sc,
   DBQ_HIP(hipGetLastError());
 }
 
-double launch_dslash_f64(hipStream_t s, const DsBatch& b, int dagger, int epi, RhsScal* sc,
+double launch_dslash_f64(hipStream_t s, DsBatch& b, int dagger, int epi, RhsScal* sc,
                          double* partials, int nb, int rgroup) {
   return launch<double>(s, b, dagger, epi, sc, partials, nb, rgroup);
 }
-double launch_dslash_f32(hipStream_t s, const DsBatch& b, int dagger, int epi, RhsScal* sc,
+double launch_dslash_f32(hipStream_t s, DsBatch& b, int dagger, int epi, RhsScal* sc,
                          double* partials, int nb, int rgroup) {
   return launch<float>(s, b, dagger, epi, sc, partials, nb, rgroup);
 }

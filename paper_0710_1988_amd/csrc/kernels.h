@@ -10,6 +10,8 @@
 // of every vector holds spins 2 and 3 (gamma5 = -1) in both precisions.
 #pragma once
 
+#include <algorithm>
+
 #include "common.h"
 
 namespace dbq {
@@ -107,15 +109,21 @@ void gamma5_f64(hipStream_t s, const double2* in, double2* out, long long V, int
 
 // ----------------------------------------------------------------------------- dslash.hip
 // Launches the Dslash kernel alone; a launch with an epilogue must be followed by
-// launch_ds_finalize, which turns the per-block partial sums into the rhs scalars.
-// nb = right-hand sides per thread (1, 2, 4).  Returns the algorithmic HBM bytes of the launch
-// when every rhs is processed (links once, input once, output once, plus the epilogue operand).
-// rgroup = how many rhs groups of nb sweep the site blocks together (block order: rhs chunk,
-// then site block, then rhs within the chunk); 0 means all of them.
-double launch_dslash_f64(hipStream_t s, const DsBatch& b, int dagger, int epi, RhsScal* sc,
+// launch_ds_finalize on the batch as updated here (site-block counts and block layout).
+// nb = right-hand sides per thread (1, 2, 4), or 0 for the LDS-staged tile kernel (FP32 only).
+// rgroup = for nb > 0, how many rhs groups of nb sweep the site blocks together (block order:
+// rhs chunk, then site block, then rhs within the chunk); for nb = 0, the rhs one block applies
+// the operator to in turn with its links held in registers.  0 means all of them.
+// Returns the algorithmic HBM bytes of the launch when every rhs is processed (links once, input
+// once, output once, plus the epilogue operand).
+double launch_dslash_f64(hipStream_t s, DsBatch& b, int dagger, int epi, RhsScal* sc,
                          double* partials, int nb, int rgroup);
-double launch_dslash_f32(hipStream_t s, const DsBatch& b, int dagger, int epi, RhsScal* sc,
+double launch_dslash_f32(hipStream_t s, DsBatch& b, int dagger, int epi, RhsScal* sc,
                          double* partials, int nb, int rgroup);
+// partial-sum slots per rhs that every launch shape of the Dslash needs for a lattice
+inline int ds_partial_slots(const Geom& g) {
+  return std::max(2 * ((g.Vh + DS_BS - 1) / DS_BS), g.V >> (g.lTh + 1));
+}
 void launch_ds_finalize(hipStream_t s, const DsBatch& b, int epi, RhsScal* sc,
                         const double* partials);
 // spinor vectors moved per processed rhs-site for an epilogue (in, out, and the epilogue operand)

@@ -82,14 +82,13 @@ DsBatch make_batch(const std::vector<DsSpec>& v) {
     L.aux = v[i].aux;
     L.nrhs = v[i].nrhs;
     L.rhs_base = v[i].rhs_base;
-    // site blocks: each parity half is cut into blocks of DS_BS sites (the kernel interleaves
-    // the two halves block by block)
+    // site blocks (set again by the launcher for the launch shape it uses)
     L.nsb = 2 * ((L.g.V / 2 + DS_BS - 1) / DS_BS);
     L.blk_begin = 0;  // laid out by the launcher
     L.kappa = v[i].op->kappa;
     L.mu = v[i].op->mu;
     nr = std::max(nr, L.rhs_base + L.nrhs);
-    ps = std::max(ps, L.nsb);
+    ps = std::max(ps, ds_partial_slots(L.g));
   }
   b.nblocks = 0;
   b.nb = 1;
@@ -98,9 +97,10 @@ DsBatch make_batch(const std::vector<DsSpec>& v) {
   return b;
 }
 
-// Launch shape of the Dslash for a batch: right-hand sides per thread (1, 2, 4) and how many of
-// those thread groups sweep the site blocks together (1, 2, 4 or all).  Timed once per
-// (precision, volume, batch size) in this context on a scratch output (the operator input is
+// Launch shape of the Dslash for a batch: (nb, rg) = right-hand sides per thread (1, 2, 4) and
+// how many of those thread groups sweep the site blocks together (1, 2, 4 or all), or, in FP32,
+// nb = 0 for the LDS-staged tile kernel with rg rhs per block (1, 2, 3, 4, 6 or all).  Timed once
+// per (precision, volume, batch size) in this context on a scratch output (the operator input is
 // only read).  DBQ_DS_NB / DBQ_DS_RG force the values.
 std::pair<int, int> choose_shape(dbq_ctx* c, bool f32, const DsBatch& b) {
   int maxr = 1;
@@ -109,10 +109,21 @@ std::pair<int, int> choose_shape(dbq_ctx* c, bool f32, const DsBatch& b) {
   const char* e_rg = std::getenv("DBQ_DS_RG");
   if (e_nb || e_rg) {
     int nb = e_nb ? std::atoi(e_nb) : 1;
-    if (nb != 1 && nb != 2 && nb != 4) nb = 1;
+    if (nb != 0 && nb != 1 && nb != 2 && nb != 4) nb = 1;
+    if (nb == 0 && !f32) nb = 1;
     return {nb, e_rg ? std::max(0, std::atoi(e_rg)) : 0};
   }
-  if (maxr == 1) return {1, 0};
+  std::vector<std::pair<int, int>> cand;
+  for (int nb : {1, 2, 4}) {
+    if (nb > maxr || (!f32 && nb == 4)) continue;
+    const int ng = (maxr + nb - 1) / nb;
+    for (int rg : {1, 2, 4, 0})
+      if (rg < ng) cand.push_back({nb, rg});  // 0 (all) covers rg >= ng
+  }
+  if (f32)
+    for (int g : {1, 2, 3, 4, 6, 0})
+      if (g < maxr) cand.push_back({0, g});
+  if (cand.size() == 1) return cand[0];
   int big = 0;
   for (int i = 1; i < b.nlat; ++i)
     if ((long long)b.lat[i].g.V * b.lat[i].nrhs > (long long)b.lat[big].g.V * b.lat[big].nrhs) big = i;
@@ -127,38 +138,33 @@ std::pair<int, int> choose_shape(dbq_ctx* c, bool f32, const DsBatch& b) {
   t.lat[0].rhs_base = 0;
   t.lat[0].aux = nullptr;
   t.nrhs_total = t.lat[0].nrhs;
-  t.pstride = t.lat[0].nsb;
+  t.pstride = ds_partial_slots(t.lat[0].g);
   const size_t bytes =
       size_t(t.lat[0].nrhs) * t.lat[0].g.V * (f32 ? 6 * sizeof(float4) : 12 * sizeof(double2));
   t.lat[0].out = ws.take(bytes);
   hipEvent_t e0, e1;
   DBQ_HIP(hipEventCreate(&e0));
   DBQ_HIP(hipEventCreate(&e1));
-  std::pair<int, int> best{1, 0};
+  std::pair<int, int> best = cand[0];
   float best_ms = 1e30f;
-  for (int nb : {1, 2, 4}) {
-    if (nb > maxr || (!f32 && nb == 4)) continue;
-    const int ng = (maxr + nb - 1) / nb;
-    for (int rg : {1, 2, 4, 0}) {
-      if (rg >= ng) continue;  // 0 (all) covers it
-      for (int rep = 0; rep < 2; ++rep) {  // warm-up, then timed
-        DBQ_HIP(hipEventRecord(e0, c->stream));
-        for (int k = 0; k < 3; ++k) {
-          if (f32) launch_dslash_f32(c->stream, t, 0, EPI_NONE, nullptr, nullptr, nb, rg);
-          else launch_dslash_f64(c->stream, t, 0, EPI_NONE, nullptr, nullptr, nb, rg);
-        }
-        DBQ_HIP(hipEventRecord(e1, c->stream));
+  for (const auto& sh : cand) {
+    for (int rep = 0; rep < 2; ++rep) {  // warm-up, then timed
+      DBQ_HIP(hipEventRecord(e0, c->stream));
+      for (int k = 0; k < 3; ++k) {
+        if (f32) launch_dslash_f32(c->stream, t, 0, EPI_NONE, nullptr, nullptr, sh.first, sh.second);
+        else launch_dslash_f64(c->stream, t, 0, EPI_NONE, nullptr, nullptr, sh.first, sh.second);
       }
-      DBQ_HIP(hipEventSynchronize(e1));
-      float ms = 0;
-      DBQ_HIP(hipEventElapsedTime(&ms, e0, e1));
-      if (std::getenv("DBQ_DEBUG"))
-        std::fprintf(stderr, "[dbq] tune %s V=%d nrhs=%d nb=%d rg=%d: %.1f us\n", f32 ? "fp32" : "fp64",
-                     t.lat[0].g.V, maxr, nb, rg, ms * 1e3f / 3);
-      if (ms < best_ms) {
-        best_ms = ms;
-        best = {nb, rg};
-      }
+      DBQ_HIP(hipEventRecord(e1, c->stream));
+    }
+    DBQ_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    DBQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (std::getenv("DBQ_DEBUG"))
+      std::fprintf(stderr, "[dbq] tune %s V=%d nrhs=%d nb=%d rg=%d: %.1f us\n",
+                   f32 ? "fp32" : "fp64", t.lat[0].g.V, maxr, sh.first, sh.second, ms * 1e3f / 3);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = sh;
     }
   }
   DBQ_HIP(hipEventDestroy(e0));
@@ -317,7 +323,7 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
 
   // ---- scratch for reductions
   int pstride = std::max(vs64.pstride, mixed ? vs32.pstride : 1);
-  for (int i = 0; i < nops; ++i) pstride = std::max(pstride, (op[i].g.V + DS_BS - 1) / DS_BS);
+  for (int i = 0; i < nops; ++i) pstride = std::max(pstride, ds_partial_slots(op[i].g));
   double* partials = ws.get<double>(size_t(NR) * pstride * 3);
   RhsScal* sc = ws.get<RhsScal>(NR);
   // pinned host area: scalars | norms | cond

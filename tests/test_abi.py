@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 def test_host_geometry_is_bit_exact(L):
     import paper_0710_1988_amd as dbq
     lex, nbr = dbq.geometry_host(L)
-    lat = W.Lattice(L)
+    lat = W.Lattice(L, tile=dbq.site_tile(L))
     assert lex.dtype == np.int32
     assert np.array_equal(lex, lat.lex_of_eo)
     k = 0
@@ -49,6 +49,15 @@ def test_host_geometry_is_bit_exact(L):
         for tab in (lat.fwd[mu], lat.bwd[mu]):
             assert np.array_equal(nbr[k], lat.eo_of_lex[tab[lat.lex_of_eo]])
             k += 1
+
+
+@pytest.mark.parametrize("L,T", [((24, 24, 24, 48), (4, 4, 4, 4)), ((16, 16, 16, 16), (4, 4, 4, 4)),
+                                 ((20, 20, 20, 32), (4, 4, 4, 4)), ((6, 4, 2, 10), (2, 4, 2, 2)),
+                                 ((2, 2, 2, 2), (2, 2, 2, 2)), ((12, 6, 4, 8), (4, 2, 4, 4))])
+def test_site_tile_rule(L, T):
+    """Largest power of two dividing each extent, capped at 4."""
+    import paper_0710_1988_amd as dbq
+    assert dbq.site_tile(L) == T
 
 
 def test_host_geometry_rejects_odd_extents():

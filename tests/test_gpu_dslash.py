@@ -16,7 +16,7 @@ LATS = [(4, 4, 4, 4), (6, 4, 2, 10), (2, 2, 2, 2), (8, 6, 4, 6)]
 @pytest.mark.parametrize("L", [(4, 4, 4, 4), (6, 4, 2, 10), (24, 24, 24, 48)])
 def test_geometry_tables_bit_exact(gpu_lib, L):
     lex, nbr = gpu_lib.geometry(L)
-    lat = W.Lattice(L)
+    lat = W.Lattice(L, tile=gpu_lib.site_tile(L))
     assert np.array_equal(host(lex), lat.lex_of_eo)
     nb = host(nbr)
     k = 0
@@ -49,6 +49,23 @@ def test_apply_fp32_matches_oracle(gpu_lib, L, dagger):
     ref = W.apply_A_multi(U, psi, lat, 0.125, 0.02, dagger)
     # FP32 arithmetic with 12-real links: a few ulps of float per term
     assert relerr(out, ref) <= 2e-6
+
+
+@pytest.mark.parametrize("L", LATS + [(8, 8, 4, 12)])
+@pytest.mark.parametrize("shape", [("0", "1"), ("0", "2"), ("0", "0"), ("1", "1"), ("1", "0"),
+                                   ("2", "1"), ("4", "0")])
+def test_every_fp32_launch_shape_matches_oracle(gpu_lib, monkeypatch, L, shape):
+    """Each FP32 launch shape: rhs per thread 1/2/4 with rhs grouping, and the LDS-staged tile
+    kernel (nb 0) with 1, 2 or all rhs per block; 5 rhs leave a ragged last chunk."""
+    monkeypatch.setenv("DBQ_DS_NB", shape[0])
+    monkeypatch.setenv("DBQ_DS_RG", shape[1])
+    lat = W.Lattice(L)
+    U = synth.gauge_field(L, 0.6, 208)
+    psi = synth.gaussian_sources(L, 5, 209)
+    for dagger, mu in ((False, 0.0), (True, 0.031)):
+        out = host(gpu_lib.wilson_apply(L, dev(U), dev(psi), 0.127, mu, dagger, "mixed"))
+        ref = W.apply_A_multi(U, psi, lat, 0.127, mu, dagger)
+        assert relerr(out, ref) <= 2e-6
 
 
 def test_gpu_output_is_gamma5_hermitian_and_gauge_covariant(gpu_lib):

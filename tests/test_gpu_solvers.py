@@ -158,9 +158,15 @@ def test_dbicgstab_mixed_reaches_fp64_residual(gpu_lib):
         assert err <= 1e-6
 
 
-def test_batched_equals_separate_and_uneven_batch(gpu_lib):
+@pytest.mark.parametrize("shape", [None, ("0", "1"), ("0", "0"), ("1", "0")])
+def test_batched_equals_separate_and_uneven_batch(gpu_lib, monkeypatch, shape):
     """Three lattices of different size in one call give the same solutions (to the solve
-    tolerance) as separate calls; all true residuals meet the tolerance."""
+    tolerance) as separate calls; all true residuals meet the tolerance.  Run with the tuned
+    Dslash launch shape and with forced ones (LDS-staged tiles with 1 or all rhs per block, one
+    rhs per thread), which exercises every fused epilogue of each."""
+    if shape is not None:
+        monkeypatch.setenv("DBQ_DS_NB", shape[0])
+        monkeypatch.setenv("DBQ_DS_RG", shape[1])
     probs = []
     for i, L in enumerate([(4, 4, 4, 4), (6, 4, 4, 4), (4, 4, 2, 6)]):
         U = synth.gauge_field(L, 0.5, 300 + i)

@@ -50,6 +50,34 @@ def test_geometry_tables(L):
             assert np.all(lat.parity[lat.fwd[mu]] != lat.parity)
 
 
+@pytest.mark.parametrize("L,T", [((8, 4, 4, 8), (4, 2, 2, 4)), ((24, 12, 4, 8), (8, 4, 4, 4)),
+                                 ((6, 4, 2, 10), (2, 2, 2, 2)), ((6, 10, 4, 2), (6, 10, 4, 2))])
+def test_blocked_even_odd_order(L, T):
+    """The tiled even-odd storage order: a bijection that keeps the parity halves, fills each
+    tile's half-range with exactly that tile's sites of that parity in in-tile lex order, and
+    reduces to parity*V/2 + (lex >> 1) when one tile covers the lattice."""
+    lat = W.Lattice(L, tile=T)
+    V = lat.V
+    h = int(np.prod(T)) // 2
+    assert np.array_equal(np.sort(lat.eo_of_lex), np.arange(V))
+    assert np.array_equal(lat.eo_of_lex[lat.lex_of_eo], np.arange(V))
+    even = lat.parity == 0
+    assert np.all(lat.eo_of_lex[even] < V // 2) and np.all(lat.eo_of_lex[~even] >= V // 2)
+    # the sites stored in one tile's half-range: same parity, same tile, a box of extents T
+    c = lat.coords[lat.lex_of_eo]
+    for start in range(0, V, h):
+        box = c[start:start + h]
+        assert np.all(box // np.array(T) == box[0] // np.array(T))
+        assert len(np.unique(lat.parity[lat.lex_of_eo[start:start + h]])) == 1
+        lexs = lat.lex_of_eo[start:start + h]
+        assert np.all(np.diff(lexs) > 0)  # in-tile lex order is lattice lex order within a box
+    plain = W.Lattice(L)
+    single = W.Lattice(L, tile=L)
+    assert np.array_equal(single.eo_of_lex, plain.eo_of_lex)
+    with pytest.raises(ValueError):
+        W.Lattice(L, tile=(3, 2, 2, 2))
+
+
 def _free_symbol(p, kappa):
     g = W.GAMMA
     return (np.eye(4) * (1 - 2 * kappa * np.cos(p).sum())
