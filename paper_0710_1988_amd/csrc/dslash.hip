@@ -372,12 +372,12 @@ __device__ __forceinline__ void chain(int (&c)[4], int& s, cx<T> (&acc)[NB][12])
 
 // The site's result psi - kappa*acc + i*t*gamma5*psi (t = mu, or -mu for the dagger) and the
 // epilogue's contributions to the per-block sums: RESID replaces the result by aux - result and
-// adds its norm, RHAT adds <aux, result>, TS adds <result, psi> and |result|^2.
+// adds its norm, RHAT adds <aux, result>, TS adds <result, psi> and |result|^2 (aux, the
+// epilogue operand at the site, is read only by RESID and RHAT).
 template <typename T, int EPI>
 __device__ __forceinline__ void finish_site(const cx<T> (&psi)[12], const cx<T> (&acc)[12], T kap,
-                                            T tm, const typename IO<T>::SE* __restrict__ aux,
-                                            int V, int s, double& r0, double& r1, double& r2,
-                                            cx<T> (&o)[12]) {
+                                            T tm, const cx<T> (&aux)[12], double& r0,
+                                            double& r1, double& r2, cx<T> (&o)[12]) {
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
     // gamma5 = diag(1,1,-1,-1) over spins
@@ -386,21 +386,17 @@ __device__ __forceinline__ void finish_site(const cx<T> (&psi)[12], const cx<T> 
     o[k].im = fma(-kap, acc[k].im, fma(t, psi[k].re, psi[k].im));
   }
   if (EPI == EPI_RESID) {
-    cx<T> b[12];
-    IO<T>::load(aux, V, s, b);
     T nn = T(0);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-      o[k] = b[k] - o[k];
+      o[k] = aux[k] - o[k];
       nn = fma(o[k].re, o[k].re, fma(o[k].im, o[k].im, nn));
     }
     r0 += double(nn);
   } else if (EPI == EPI_RHAT) {
-    cx<T> rh[12];
-    IO<T>::load(aux, V, s, rh);
     cx<T> d{T(0), T(0)};
 #pragma unroll
-    for (int k = 0; k < 12; ++k) cmacc(d, rh[k], o[k]);
+    for (int k = 0; k < 12; ++k) cmacc(d, aux[k], o[k]);
     r0 += double(d.re);
     r1 += double(d.im);
   } else if (EPI == EPI_TS) {
@@ -504,9 +500,12 @@ void k_dslash(DsBatch B, RhsScal* __restrict__ sc, double* __restrict__ partials
       if (!act[j]) continue;
       cx<T> psi[12];
       IO<T>::load(in + j * rstride, V, s, psi);
+      cx<T> ax[12];
+      if (EPI == EPI_RHAT || EPI == EPI_RESID)
+        IO<T>::load((const SE*)L.aux + (r0 + j) * rstride, V, s, ax);
       cx<T> o[12];
-      finish_site<T, EPI>(psi, acc[j], kap, tm, (const SE*)L.aux + (r0 + j) * rstride, V, s,
-                          red[3 * j], red[3 * j + 1], red[3 * j + 2], o);
+      finish_site<T, EPI>(psi, acc[j], kap, tm, ax, red[3 * j], red[3 * j + 1], red[3 * j + 2],
+                          o);
       IO<T>::store(out + j * rstride, V, s, o);
     }
   }
@@ -541,6 +540,11 @@ void k_dslash(DsBatch B, RhsScal* __restrict__ sc, double* __restrict__ partials
 //                 this one in direction +-mu next to it, in lexicographic order of the three
 //                 other in-tile coordinates
 constexpr int TL_SLOTS = 768;  // 4^4 tile: 256 + 8 x 64
+
+// rhs per block of the tile kernel: rgroup, 0 = all
+__host__ __device__ __forceinline__ int tile_chunk(int rgroup, int nrhs) {
+  return (rgroup <= 0 || rgroup > nrhs) ? nrhs : rgroup;
+}
 
 struct TileGeo {
   int vt, vh;        // sites per tile, per parity
@@ -699,7 +703,7 @@ __global__ __launch_bounds__(DS_BS) void k_dslash_tile(DsBatch B, RhsScal* __res
     if (i < B.nlat && lb >= B.lat[i].blk_begin) l = i;
   const DsLat& L = B.lat[l];
   const Geom& g = L.g;
-  const int G = (B.rgroup <= 0 || B.rgroup > L.nrhs) ? L.nrhs : B.rgroup;
+  const int G = tile_chunk(B.rgroup, L.nrhs);
   const int nch = (L.nrhs + G - 1) / G;
   const int loc = lb - L.blk_begin;
   const int tile = loc / nch;  // chunks of one tile are adjacent blocks (they share the links)
@@ -762,13 +766,17 @@ __global__ __launch_bounds__(DS_BS) void k_dslash_tile(DsBatch B, RhsScal* __res
   constexpr int SB = -SF;
   const float kap = float(L.kappa);
   const float tm = float(DAG ? -L.mu : L.mu);
-  for (int j = 0; j < Gc; ++j) {
-    const int r = r0 + j;
-    bool act = true;
-    if (gate == 1) act = sc[L.rhs_base + r].active != 0;
-    else if (gate == 2) act = sc[L.rhs_base + r].sel != 0;
-    if (!act) continue;  // uniform over the block
-    const float4* in = (const float4*)L.in + (long long)r * 6 * V;
+  auto active = [&](int j) {
+    if (gate == 1) return sc[L.rhs_base + r0 + j].active != 0;
+    if (gate == 2) return sc[L.rhs_base + r0 + j].sel != 0;
+    return true;
+  };
+  auto next = [&](int j) {
+    while (j < Gc && !active(j)) ++j;  // uniform over the block
+    return j;
+  };
+  auto stage = [&](int j, float4* buf) {
+    const float4* in = (const float4*)L.in + (long long)(r0 + j) * 6 * V;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const int ck = wv + 4 * i;
@@ -777,30 +785,40 @@ __global__ __launch_bounds__(DS_BS) void k_dslash_tile(DsBatch B, RhsScal* __res
         for (int k = 0; k < 6; ++k)
           __builtin_amdgcn_global_load_lds(
               (const void*)(in + (long long)k * V + seo[i]),
-              (__attribute__((address_space(3))) void*)(lds + k * TL_SLOTS + ck * 64), 16, 0, 0);
+              (__attribute__((address_space(3))) void*)(buf + k * TL_SLOTS + ck * 64), 16, 0, 0);
       }
     }
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+  };
+  // (A second LDS buffer to overlap the next copy with this rhs's arithmetic leaves room for
+  // one block per CU instead of two; measured slower.)
+  int j = next(0);
+  if (j < Gc) stage(j, lds);
+  while (j < Gc) {
+    const int r = r0 + j;
+    const float4* buf = lds;
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's LDS-direct copies have landed
+    __syncthreads();                // and everyone else's
+    const int jn = next(j + 1);
+    zf ax[12];
+    if (own && (EPI == EPI_RHAT || EPI == EPI_RESID))
+      IO<float>::load((const float4*)L.aux + (long long)r * 6 * V, V, s, ax);
     double red[3] = {0.0, 0.0, 0.0};
     if (own) {
       zf acc[12];
 #pragma unroll
       for (int k = 0; k < 12; ++k) acc[k] = zf{0.f, 0.f};
-      hop_lds<0, SF, false>(lds, ns[0], lf[0], acc);
-      hop_lds<0, SB, true>(lds, ns[1], lbk[0], acc);
-      hop_lds<1, SF, false>(lds, ns[2], lf[1], acc);
-      hop_lds<1, SB, true>(lds, ns[3], lbk[1], acc);
-      hop_lds<2, SF, false>(lds, ns[4], lf[2], acc);
-      hop_lds<2, SB, true>(lds, ns[5], lbk[2], acc);
-      hop_lds<3, SF, false>(lds, ns[6], lf[3], acc);
-      hop_lds<3, SB, true>(lds, ns[7], lbk[3], acc);
+      hop_lds<0, SF, false>(buf, ns[0], lf[0], acc);
+      hop_lds<0, SB, true>(buf, ns[1], lbk[0], acc);
+      hop_lds<1, SF, false>(buf, ns[2], lf[1], acc);
+      hop_lds<1, SB, true>(buf, ns[3], lbk[1], acc);
+      hop_lds<2, SF, false>(buf, ns[4], lf[2], acc);
+      hop_lds<2, SB, true>(buf, ns[5], lbk[2], acc);
+      hop_lds<3, SF, false>(buf, ns[6], lf[3], acc);
+      hop_lds<3, SB, true>(buf, ns[7], lbk[3], acc);
       zf psi[12];
-      lds_spinor(lds, tid, psi);
+      lds_spinor(buf, tid, psi);
       zf o[12];
-      finish_site<float, EPI>(psi, acc, kap, tm,
-                              (const float4*)L.aux + (long long)r * 6 * V, V, s, red[0], red[1],
-                              red[2], o);
+      finish_site<float, EPI>(psi, acc, kap, tm, ax, red[0], red[1], red[2], o);
       IO<float>::store((float4*)L.out + (long long)r * 6 * V, V, s, o);
     }
     if (EPI != EPI_NONE) {
@@ -813,7 +831,11 @@ __global__ __launch_bounds__(DS_BS) void k_dslash_tile(DsBatch B, RhsScal* __res
         pp[2] = red[2];
       }
     }
-    __syncthreads();  // the next rhs overwrites the LDS copy
+    if (jn < Gc) {
+      __syncthreads();  // every thread is done with the copy that is overwritten next
+      stage(jn, lds);
+    }
+    j = jn;
   }
 }
 
@@ -874,7 +896,7 @@ double launch(hipStream_t s, DsBatch& b, int dagger, int epi, RhsScal* sc, doubl
       DBQ_CHECK(L.g.T[0] <= 4 && L.g.T[1] <= 4 && L.g.T[2] <= 4 && L.g.T[3] <= 4,
                 "dslash: tile larger than 4^4");
       L.nsb = L.g.V >> (L.g.lTh + 1);
-      const int G = (rgroup <= 0 || rgroup > L.nrhs) ? L.nrhs : rgroup;
+      const int G = tile_chunk(rgroup, L.nrhs);
       blk += (long long)L.nsb * ((L.nrhs + G - 1) / G);
     } else {
       L.nsb = 2 * ((L.g.Vh + DS_BS - 1) / DS_BS);

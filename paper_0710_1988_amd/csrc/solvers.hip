@@ -120,9 +120,10 @@ std::pair<int, int> choose_shape(dbq_ctx* c, bool f32, const DsBatch& b) {
     for (int rg : {1, 2, 4, 0})
       if (rg < ng) cand.push_back({nb, rg});  // 0 (all) covers rg >= ng
   }
-  if (f32)
+  if (f32) {
     for (int g : {1, 2, 3, 4, 6, 0})
       if (g < maxr) cand.push_back({0, g});
+  }
   if (cand.size() == 1) return cand[0];
   int big = 0;
   for (int i = 1; i < b.nlat; ++i)

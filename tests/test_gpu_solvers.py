@@ -158,12 +158,12 @@ def test_dbicgstab_mixed_reaches_fp64_residual(gpu_lib):
         assert err <= 1e-6
 
 
-@pytest.mark.parametrize("shape", [None, ("0", "1"), ("0", "0"), ("1", "0")])
+@pytest.mark.parametrize("shape", [None, ("0", "1"), ("0", "0"), ("0", "3"), ("1", "0")])
 def test_batched_equals_separate_and_uneven_batch(gpu_lib, monkeypatch, shape):
     """Three lattices of different size in one call give the same solutions (to the solve
     tolerance) as separate calls; all true residuals meet the tolerance.  Run with the tuned
-    Dslash launch shape and with forced ones (LDS-staged tiles with 1 or all rhs per block, one
-    rhs per thread), which exercises every fused epilogue of each."""
+    Dslash launch shape and with forced ones (LDS-staged tiles with 1, 3 or all rhs per block;
+    one rhs per thread), which exercises every fused epilogue."""
     if shape is not None:
         monkeypatch.setenv("DBQ_DS_NB", shape[0])
         monkeypatch.setenv("DBQ_DS_RG", shape[1])
