@@ -108,6 +108,8 @@ __device__ void fin_xr(RhsScal& q, double a0, double a1, double a2) {
   q.rho_prev = q.rho;
   q.rho = rn;
   if (q.flags & (F_CONV | F_RELIABLE | F_BREAK | F_NAN)) q.active = 0;
+  // a convergence claim or a reliable update asks for the FP64 residual of this rhs
+  if (q.flags & (F_CONV | F_RELIABLE)) q.sel = 1;
 }
 
 template <typename E, int OP>
@@ -218,6 +220,7 @@ __device__ void fin_aux(int op, RhsScal& q, double a0, double a1, double a2) {
     } else if (a2 <= q.stop2) {
       q.flags = F_CONV;
       q.active = 0;
+      q.sel = 1;
     }
   } else if (op == AX_RESTART) {
     if (!q.sel) return;
@@ -228,6 +231,7 @@ __device__ void fin_aux(int op, RhsScal& q, double a0, double a1, double a2) {
     q.beta = zd{0.0, 0.0};
     q.flags = 0;
     q.active = 1;
+    q.sel = 0;
   } else {  // AX_REPLACE
     if (!q.sel) return;
     const zd rn{a0, a1};
@@ -240,6 +244,7 @@ __device__ void fin_aux(int op, RhsScal& q, double a0, double a1, double a2) {
     q.rr_max = a2;
     q.flags = 0;
     q.active = 1;
+    q.sel = 0;
     if (norm2(rn) <= 1e-28 * q.rhat2 * a2) {
       q.flags = F_BREAK;
       q.active = 0;

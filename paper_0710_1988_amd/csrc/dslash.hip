@@ -346,7 +346,23 @@ __device__ void finalize(const DsBatch& B, RhsScal* sc, const double* partials) 
           }
         }
       } else if (EPI == EPI_RESID) {
-        if (q.sel) q.rr_true = a0;
+        if (q.sel) {
+          q.rr_true = a0;
+          if (B.decide) {
+            // reliable update on the device: converged rhs stop, the others keep sel for the
+            // residual replacement that follows
+            q.nrel += 1;
+            if (a0 <= q.stop2) {
+              q.flags = F_DONE;
+              q.active = 0;
+              q.sel = 0;
+            } else if (!finite_d(a0)) {
+              q.flags = F_NAN;
+              q.active = 0;
+              q.sel = 0;
+            }
+          }
+        }
       }
     }
   }

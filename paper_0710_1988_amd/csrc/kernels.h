@@ -23,6 +23,7 @@ enum : int {
   F_BREAK = 4,     // rho or <rhat, v> vanished: restart with rhat <- r
   F_OMEGA0 = 8,    // omega = 0 in this iteration (restart after the update)
   F_NAN = 16,      // non-finite reduction
+  F_DONE = 32,     // FP64 true residual below the stopping threshold (decided on the device)
 };
 
 struct RhsScal {
@@ -39,6 +40,8 @@ struct RhsScal {
   int sel;         // selected for a host-requested operation
   int flags;
   int iters;
+  int nrel;        // FP64 residual replacements decided on the device (each one FP64 MVP)
+  int pad;
 };
 
 // ----------------------------------------------------------------------------- batches
@@ -79,6 +82,7 @@ struct DsBatch {
   int nb;          // right-hand sides per thread (1, 2 or 4), set by the launcher
   int rgroup;      // thread rhs-groups sharing a sweep over the site blocks, set by the launcher
   DsAcct acct;     // zero unless the caller accounts bytes of a gated launch
+  int decide;      // RESID finalize also decides convergence / replacement (device loop)
 };
 
 enum Epi : int { EPI_NONE = 0, EPI_RHAT = 1, EPI_TS = 2, EPI_RESID = 3 };

@@ -509,121 +509,220 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
     }
   };
 
-  int nchk = 1;
-  bool first = true;
   const bool debug = std::getenv("DBQ_DEBUG") != nullptr;
-  while (true) {
-    if (!first)
-      for (int it = 0; it < nchk; ++it) iterate();
-    first = false;
-    pull();
-    if (debug) {
-      for (int j = 0; j < NR; ++j)
-        if (!done[j])
-          std::fprintf(stderr, "[dbq] rhs %d it %d flags %d act %d rr %.3e/%.3e rr_max %.3e mvb %lld\n",
-                       j, hs[j].iters, hs[j].flags, hs[j].active, hs[j].rr, hs[j].bb, hs[j].rr_max,
-                       (long long)mvb[j]);
-    }
-    std::vector<int> A, Bk, Cc;
-    bool any_active = false;
-    for (int j = 0; j < NR; ++j) {
+  auto trace = [&]() {
+    if (!debug) return;
+    for (int j = 0; j < NR; ++j)
+      if (!done[j])
+        std::fprintf(stderr, "[dbq] rhs %d it %d flags %d act %d sel %d rr %.3e/%.3e rr_max %.3e nrel %d\n",
+                     j, hs[j].iters, hs[j].flags, hs[j].active, hs[j].sel, hs[j].rr, hs[j].bb,
+                     hs[j].rr_max, hs[j].nrel);
+  };
+  // breakdowns: restart with rhat <- r (the selection is pushed with the host scalars)
+  auto restart = [&](const std::vector<int>& Bk) {
+    for (int j = 0; j < NR; ++j) hs[j].sel = 0;
+    bool any = false;
+    for (int j : Bk) {
       if (done[j]) continue;
-      const RhsScal& q = hs[j];
-      const long long mv = mvb[j] + 2LL * q.iters;
-      if (q.flags & F_NAN) {
+      restarts[j] += 1;
+      if (restarts[j] > 10) {
         done[j] = 1;
         status[j] = DBQ_EBREAKDOWN;
-        Cc.push_back(j);
-      } else if (q.flags & (F_CONV | F_RELIABLE)) {
-        A.push_back(j);
-      } else if (q.flags & F_BREAK) {
-        Bk.push_back(j);
-      } else if (mv >= max_mv) {
-        Cc.push_back(j);
+        hs[j].active = 0;
+      } else {
+        hs[j].sel = 1;
+        any = true;
       }
-      if (q.active) any_active = true;
     }
-    if (A.empty() && Bk.empty() && Cc.empty()) {
-      if (!any_active) break;
-      nchk = std::min(nchk * 2, 16);
-      continue;
+    push();
+    if (any) {
+      if (mixed)
+        bicg_aux_f32(s, AX_RESTART, vs32, vs64, r64, r32, rhat32, p32, v32, x32, sc, partials,
+                     counter(c, C_AUX));
+      else
+        bicg_aux_f64(s, AX_RESTART, vs64, r64, r64, rhat, p, v, sc, partials, counter(c, C_AUX));
     }
-    nchk = 1;
-    // (1) convergence claims and reliable updates: FP64 residual of the accumulated solution
-    if (!A.empty()) {
-      for (int j = 0; j < NR; ++j) hs[j].sel = 0;
-      for (int j : A) hs[j].sel = 1;
-      push();
-      if (mixed) bicg_xacc(s, vs32, vs64, x64, x32, sc);
-      run_dslash(c, false, bres, dagger, EPI_RESID, sc, partials, C_RESID);
+  };
+  if (mixed) {
+    // Reliable updates on the device: every `every` iterations the rhs that claimed convergence
+    // or dropped by the reliable-update factor (selected by the iteration's finalize) get
+    // x64 += x32 and the FP64 residual; the residual's finalize stops the converged ones and the
+    // others continue from the replaced residual.  The host only polls for rhs that finished,
+    // broke down or ran out of MVPs, at intervals that double up to 32 iterations.
+    int every = 4;
+    if (const char* e = std::getenv("DBQ_RELUP_EVERY")) every = std::max(1, std::atoi(e));
+    DsBatch bres_dec = bres;
+    bres_dec.decide = 1;
+    auto relup_dev = [&]() {
+      bicg_xacc(s, vs32, vs64, x64, x32, sc);
+      run_dslash(c, false, bres_dec, dagger, EPI_RESID, sc, partials, C_RESID);
+      bicg_aux_f32(s, AX_REPLACE, vs32, vs64, r64, r32, rhat32, p32, v32, x32, sc, partials,
+                   counter(c, C_AUX));
+    };
+    relup_dev();  // rhs whose starting residual already meets the tolerance
+    int nchk = every;
+    while (true) {
       pull();
-      bool any_rep = false;
-      for (int j : A) {
-        mvb[j] += 1;
-        if (mixed) relup[j] += 1;
-        rrt[j] = hs[j].rr_true;
-        have_true[j] = 1;
-        const long long mv = mvb[j] + 2LL * hs[j].iters;
-        if (hs[j].rr_true <= hs[j].stop2) {
+      trace();
+      std::vector<int> Bk, Cc;
+      bool live = false;
+      for (int j = 0; j < NR; ++j) {
+        if (done[j]) continue;
+        const RhsScal& q = hs[j];
+        const long long mv = mvb[j] + q.nrel + 2LL * q.iters;
+        if (q.flags & F_DONE) {
           done[j] = 1;
           status[j] = DBQ_OK;
-          hs[j].sel = 0;
-          hs[j].active = 0;
-        } else if (mv >= max_mv || !std::isfinite(hs[j].rr_true)) {
-          done[j] = 1;
-          status[j] = std::isfinite(hs[j].rr_true) ? DBQ_NOT_CONVERGED : DBQ_EBREAKDOWN;
-          hs[j].sel = 0;
-          hs[j].active = 0;
-        } else {
-          any_rep = true;
-          have_true[j] = 0;
-        }
-      }
-      push();
-      if (any_rep) {
-        if (mixed)
-          bicg_aux_f32(s, AX_REPLACE, vs32, vs64, r64, r32, rhat32, p32, v32, x32, sc, partials,
-                       counter(c, C_AUX));
-        else
-          bicg_aux_f64(s, AX_REPLACE, vs64, rt, r64, rhat, p, v, sc, partials, counter(c, C_AUX));
-      }
-    }
-    // (2) breakdowns: restart with rhat <- r
-    if (!Bk.empty()) {
-      pull();
-      for (int j = 0; j < NR; ++j) hs[j].sel = 0;
-      bool any = false;
-      for (int j : Bk) {
-        if (done[j]) continue;
-        restarts[j] += 1;
-        if (restarts[j] > 10) {
+          rrt[j] = q.rr_true;
+          have_true[j] = 1;
+        } else if (q.flags & F_NAN) {
           done[j] = 1;
           status[j] = DBQ_EBREAKDOWN;
-          hs[j].active = 0;
-        } else {
-          hs[j].sel = 1;
-          any = true;
+          Cc.push_back(j);
+        } else if (q.flags & F_BREAK) {
+          Bk.push_back(j);
+        } else if (mv >= max_mv) {
+          Cc.push_back(j);
+        } else if (q.active || q.sel) {
+          live = true;
         }
       }
-      push();
-      if (any) {
-        if (mixed)
-          bicg_aux_f32(s, AX_RESTART, vs32, vs64, r64, r32, rhat32, p32, v32, x32, sc, partials,
-                       counter(c, C_AUX));
-        else
-          bicg_aux_f64(s, AX_RESTART, vs64, r64, r64, rhat, p, v, sc, partials, counter(c, C_AUX));
+      if (!Cc.empty()) {
+        for (int j : Cc) {
+          done[j] = 1;
+          if (status[j] != DBQ_EBREAKDOWN) status[j] = DBQ_NOT_CONVERGED;
+          hs[j].active = 0;
+          hs[j].sel = 0;
+        }
+        if (Bk.empty()) push();
+      }
+      if (!Bk.empty()) {
+        restart(Bk);
+        live = true;
+      }
+      if (!live) break;
+      nchk = (Bk.empty() && Cc.empty()) ? std::min(nchk * 2, std::max(32, every)) : every;
+      for (int it = 1; it <= nchk; ++it) {
+        iterate();
+        if (it % every == 0) relup_dev();
       }
     }
-    // (3) out of matrix-vector products
-    if (!Cc.empty()) {
+  } else {
+    int nchk = 1;
+    bool first = true;
+    while (true) {
+      if (!first)
+        for (int it = 0; it < nchk; ++it) iterate();
+      first = false;
       pull();
-      for (int j = 0; j < NR; ++j) hs[j].sel = 0;
-      for (int j : Cc) {
-        done[j] = 1;
-        if (status[j] != DBQ_EBREAKDOWN) status[j] = DBQ_NOT_CONVERGED;
-        hs[j].active = 0;
+      if (debug) {
+        for (int j = 0; j < NR; ++j)
+          if (!done[j])
+            std::fprintf(stderr, "[dbq] rhs %d it %d flags %d act %d rr %.3e/%.3e rr_max %.3e mvb %lld\n",
+                         j, hs[j].iters, hs[j].flags, hs[j].active, hs[j].rr, hs[j].bb, hs[j].rr_max,
+                         (long long)mvb[j]);
       }
-      push();
+      std::vector<int> A, Bk, Cc;
+      bool any_active = false;
+      for (int j = 0; j < NR; ++j) {
+        if (done[j]) continue;
+        const RhsScal& q = hs[j];
+        const long long mv = mvb[j] + 2LL * q.iters;
+        if (q.flags & F_NAN) {
+          done[j] = 1;
+          status[j] = DBQ_EBREAKDOWN;
+          Cc.push_back(j);
+        } else if (q.flags & (F_CONV | F_RELIABLE)) {
+          A.push_back(j);
+        } else if (q.flags & F_BREAK) {
+          Bk.push_back(j);
+        } else if (mv >= max_mv) {
+          Cc.push_back(j);
+        }
+        if (q.active) any_active = true;
+      }
+      if (A.empty() && Bk.empty() && Cc.empty()) {
+        if (!any_active) break;
+        nchk = std::min(nchk * 2, 16);
+        continue;
+      }
+      nchk = 1;
+      // (1) convergence claims and reliable updates: FP64 residual of the accumulated solution
+      if (!A.empty()) {
+        for (int j = 0; j < NR; ++j) hs[j].sel = 0;
+        for (int j : A) hs[j].sel = 1;
+        push();
+        if (mixed) bicg_xacc(s, vs32, vs64, x64, x32, sc);
+        run_dslash(c, false, bres, dagger, EPI_RESID, sc, partials, C_RESID);
+        pull();
+        bool any_rep = false;
+        for (int j : A) {
+          mvb[j] += 1;
+          if (mixed) relup[j] += 1;
+          rrt[j] = hs[j].rr_true;
+          have_true[j] = 1;
+          const long long mv = mvb[j] + 2LL * hs[j].iters;
+          if (hs[j].rr_true <= hs[j].stop2) {
+            done[j] = 1;
+            status[j] = DBQ_OK;
+            hs[j].sel = 0;
+            hs[j].active = 0;
+          } else if (mv >= max_mv || !std::isfinite(hs[j].rr_true)) {
+            done[j] = 1;
+            status[j] = std::isfinite(hs[j].rr_true) ? DBQ_NOT_CONVERGED : DBQ_EBREAKDOWN;
+            hs[j].sel = 0;
+            hs[j].active = 0;
+          } else {
+            any_rep = true;
+            have_true[j] = 0;
+          }
+        }
+        push();
+        if (any_rep) {
+          if (mixed)
+            bicg_aux_f32(s, AX_REPLACE, vs32, vs64, r64, r32, rhat32, p32, v32, x32, sc, partials,
+                         counter(c, C_AUX));
+          else
+            bicg_aux_f64(s, AX_REPLACE, vs64, rt, r64, rhat, p, v, sc, partials, counter(c, C_AUX));
+        }
+      }
+      // (2) breakdowns: restart with rhat <- r
+      if (!Bk.empty()) {
+        pull();
+        for (int j = 0; j < NR; ++j) hs[j].sel = 0;
+        bool any = false;
+        for (int j : Bk) {
+          if (done[j]) continue;
+          restarts[j] += 1;
+          if (restarts[j] > 10) {
+            done[j] = 1;
+            status[j] = DBQ_EBREAKDOWN;
+            hs[j].active = 0;
+          } else {
+            hs[j].sel = 1;
+            any = true;
+          }
+        }
+        push();
+        if (any) {
+          if (mixed)
+            bicg_aux_f32(s, AX_RESTART, vs32, vs64, r64, r32, rhat32, p32, v32, x32, sc, partials,
+                         counter(c, C_AUX));
+          else
+            bicg_aux_f64(s, AX_RESTART, vs64, r64, r64, rhat, p, v, sc, partials, counter(c, C_AUX));
+        }
+      }
+      // (3) out of matrix-vector products
+      if (!Cc.empty()) {
+        pull();
+        for (int j = 0; j < NR; ++j) hs[j].sel = 0;
+        for (int j : Cc) {
+          done[j] = 1;
+          if (status[j] != DBQ_EBREAKDOWN) status[j] = DBQ_NOT_CONVERGED;
+          hs[j].active = 0;
+        }
+        push();
+      }
     }
   }
 
@@ -656,10 +755,10 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
   int worst = DBQ_OK;
   for (int j = 0; j < NR; ++j) {
     dbq_stats& o = st[j];
-    o.matvecs = mvb[j] + 2LL * hs[j].iters;
+    o.matvecs = mvb[j] + hs[j].nrel + 2LL * hs[j].iters;
     o.iterations = hs[j].iters;
     o.restarts = restarts[j];
-    o.reliable_updates = relup[j];
+    o.reliable_updates = relup[j] + hs[j].nrel;
     o.rel_true_resid = hs[j].bb > 0 ? std::sqrt(rrt[j] / hs[j].bb) : 0.0;
     o.seconds = secs;
     o.status = status[j];
