@@ -190,11 +190,14 @@ void run_dslash(dbq_ctx* c, bool f32, const DsBatch& b0, int dagger, int epi, Rh
     b.acct.spinor_bytes = f32 ? 24 * 4 : 12 * 16;
     b.acct.link_bytes = f32 ? 4 * 12 * 4 : 4 * 9 * 16;
   }
+  // residual launches select few rhs: with all rhs groups of a site block adjacent, the selected
+  // ones still cover every XCD (chunks of rhs groups would put one rhs on one or two XCDs)
+  const int rg = (epi == EPI_RESID && shape.first > 0) ? 0 : shape.second;
   hipEvent_t e0;
   timer_begin(c, kind, &e0);
   const double bytes =
-      f32 ? launch_dslash_f32(c->stream, b, dagger, epi, sc, partials, shape.first, shape.second)
-          : launch_dslash_f64(c->stream, b, dagger, epi, sc, partials, shape.first, shape.second);
+      f32 ? launch_dslash_f32(c->stream, b, dagger, epi, sc, partials, shape.first, rg)
+          : launch_dslash_f64(c->stream, b, dagger, epi, sc, partials, shape.first, rg);
   timer_end(c, kind, e0, dev_acct ? 0.0 : bytes);
   launch_ds_finalize(c->stream, b, epi, sc, partials);
 }
@@ -211,16 +214,21 @@ T* upload(dbq_ctx* c, WsScope& ws, const std::vector<T>& h) {
 
 VecSet make_vecset(dbq_ctx* c, WsScope& ws, const std::vector<int>& nelem) {
   std::vector<long long> off(nelem.size());
-  std::vector<int2> blk;
+  std::vector<int> nch(nelem.size());
   long long o = 0;
   int ps = 1;
   for (size_t j = 0; j < nelem.size(); ++j) {
     off[j] = o;
     o += nelem[j];
-    const int nch = (nelem[j] + BL_CHUNK - 1) / BL_CHUNK;
-    ps = std::max(ps, nch);
-    for (int ch = 0; ch < nch; ++ch) blk.push_back(make_int2(int(j), ch));
+    nch[j] = (nelem[j] + BL_CHUNK - 1) / BL_CHUNK;
+    ps = std::max(ps, nch[j]);
   }
+  // chunk-major block order: the right-hand sides alternate, so that a launch in which only a
+  // few of them are selected still spreads their chunks over every XCD
+  std::vector<int2> blk;
+  for (int ch = 0; ch < ps; ++ch)
+    for (size_t j = 0; j < nelem.size(); ++j)
+      if (ch < nch[j]) blk.push_back(make_int2(int(j), ch));
   DBQ_CHECK(blk.size() < (size_t(1) << 31), "vector set too large");
   VecSet vs;
   vs.off = upload(c, ws, off);
