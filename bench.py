@@ -109,6 +109,121 @@ def dslash_sweep(dbq, torch):
     return out
 
 
+def _timed(torch, fn):
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return r, time.perf_counter() - t
+
+
+def _setup(dbq, torch, synth, L, c, seed, kappa_frac, m, k, mu_defl=0.0, kc_mu=None):
+    """Field, kappa_c (GPU), kappa and the GMRES-DR(m,k) deflation space of a point source."""
+    U = torch.from_numpy(synth.gauge_field(L, c, seed)).cuda()
+    (kc, lam, res, st), t_kc = _timed(torch, lambda: dbq.kappa_critical(L, U, m=48, k=16,
+                                                                         tol=1e-10))
+    kap = kappa_frac * kc
+    b0 = torch.from_numpy(synth.point_source(L)).cuda()
+    (x0, V, th, gst), t_gd = _timed(torch, lambda: dbq.gmresdr_first_rhs(L, U, b0, kap, m, k,
+                                                                         mu=mu_defl, tol=1e-8))
+    info = dict(lattice=list(L), c=c, seed=seed, kappa_c=kc, kappa=kap, kappa_c_s=round(t_kc, 2),
+                gmresdr=f"({m},{k})", gmresdr_mu=mu_defl, gmresdr_s=round(t_gd, 2),
+                gmresdr_mvps=gst["matvecs"], gmresdr_status=gst["status_name"], k_out=int(V.shape[0]))
+    return U, kap, V, info
+
+
+def leg_c3(dbq, torch, synth):
+    """20^3 x 32 with 24 Z2 sources, and the uneven batch 8^4 / 12^4 / 16^4 (8 sources each, own
+    kappa_c and deflation space) in one call; kappa = 0.99 kappa_c, GMRES-DR(50,30), mixed."""
+    out = {}
+    L = (20, 20, 20, 32)
+    U, kap, V, info = _setup(dbq, torch, synth, L, 0.6, 103, 0.99, 50, 30)
+    B = torch.from_numpy(synth.z2_sources(L, 24, 1103)).cuda()
+    prob = dict(L=L, links=U, kappa=kap, B=B, V=V)
+    dbq.dbicgstab_solve([prob], tol=1e-8, prec="mixed")  # warm-up (tunes the launch shape)
+    (X, st, status), t = _timed(torch, lambda: dbq.dbicgstab_solve([prob], tol=1e-8,
+                                                                   prec="mixed"))
+    info.update(nrhs=24, ms_per_source=round(t * 1e3 / 24, 3), all_converged=status == 0,
+                worst_rel_true_resid=max(x["rel_true_resid"] for x in st),
+                mvps_per_source=float(np.mean([x["matvecs"] for x in st])))
+    out["20x20x20x32_nrhs24"] = info
+    del X, B, V, U, prob
+    probs, infos = [], []
+    for Lb, seed in (((8, 8, 8, 8), 1031), ((12, 12, 12, 12), 1032), ((16, 16, 16, 16), 1033)):
+        U, kap, V, info = _setup(dbq, torch, synth, Lb, 0.6, seed, 0.99, 50, 30)
+        B = torch.from_numpy(synth.z2_sources(Lb, 8, 1000 + seed)).cuda()
+        probs.append(dict(L=Lb, links=U, kappa=kap, B=B, V=V))
+        infos.append(info)
+    dbq.dbicgstab_solve(probs, tol=1e-8, prec="mixed")
+    (X, st, status), t = _timed(torch, lambda: dbq.dbicgstab_solve(probs, tol=1e-8,
+                                                                   prec="mixed"))
+    out["uneven_8^4_12^4_16^4_nrhs8x3"] = dict(
+        lattices=infos, ms_per_source=round(t * 1e3 / 24, 3), all_converged=status == 0,
+        worst_rel_true_resid=max(x["rel_true_resid"] for x in st),
+        mvps_per_source=[float(np.mean([x["matvecs"] for x in st[i * 8:(i + 1) * 8]]))
+                         for i in range(3)])
+    return out
+
+
+def leg_c4(dbq, torch, synth):
+    """Gradient of Re(eta^H A^{-1} b) on 16^4 (links exp(0.5 iQ), seed 1041), kappa = 0.97 kappa_c,
+    8 sources: mixed deflated forward solve, deflated adjoint solve and link force, per source."""
+    L = (16, 16, 16, 16)
+    U, kap, V, info = _setup(dbq, torch, synth, L, 0.5, 1041, 0.97, 40, 20)
+    B = torch.from_numpy(synth.z2_sources(L, 8, 2041)).cuda()
+    eta = torch.from_numpy(synth.gaussian_sources(L, 8, 2104)).cuda()
+
+    def grad():
+        X, st, s1 = dbq.dbicgstab_solve([dict(L=L, links=U, kappa=kap, B=B, V=V)], tol=1e-8,
+                                        prec="mixed")
+        Lam, st2, s2 = dbq.dbicgstab_solve([dict(L=L, links=U, kappa=kap, B=eta, V=V)],
+                                           tol=1e-8, prec="mixed", dagger=True)
+        Fo = dbq.link_force(L, U, kap, Lam[0], X[0], kind="su3")
+        return st, st2, s1, s2, Fo
+
+    grad()
+    (st, st2, s1, s2, Fo), t = _timed(torch, grad)
+    info.update(nrhs=8, ms_per_source=round(t * 1e3 / 8, 3), status=[s1, s2],
+                forward_mvps=float(np.mean([x["matvecs"] for x in st])),
+                adjoint_mvps=float(np.mean([x["matvecs"] for x in st2])))
+    return {"16x16x16x16_gradient_nrhs8": info}
+
+
+def leg_c5(dbq, torch, synth):
+    """Twisted-mass shifts on 24^3 x 48 at kappa_c: 8 masses mu = 0.001 * 20^(j/7) from the
+    heaviest, each started from the minimal-residual combination of the previous solutions and
+    deflated with GMRES-DR(60,40) of A(mu = 0.02); 12 Z2 sources, mixed precision."""
+    L = (24, 24, 24, 48)
+    mus = [0.001 * 20 ** (j / 7) for j in range(8)][::-1]
+    U, kap, V, info = _setup(dbq, torch, synth, L, 0.6, 105, 1.0, 60, 40, mu_defl=mus[0])
+    B = torch.from_numpy(synth.z2_sources(L, 12, 1105)).cuda()
+    sols, shifts = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for m in mus:
+        X0, r0, r1 = None, None, None
+        if sols:
+            Q = torch.stack(sols, dim=1)
+            X0, r0, r1 = dbq.project_shifts(L, U, kap, m, Q, B)
+            del Q
+        (X, st, status), t = _timed(torch, lambda: dbq.dbicgstab_solve(
+            [dict(L=L, links=U, kappa=kap, mu=m, B=B, V=V, X0=X0)], tol=1e-8, prec="mixed",
+            max_mv=40000))
+        shifts.append(dict(mu=m, solve_s=round(t, 3), status=status,
+                           mvps_per_source=float(np.mean([x["matvecs"] for x in st])),
+                           worst_rel_true_resid=max(x["rel_true_resid"] for x in st),
+                           mr_resid_before_after=None if r0 is None else
+                           [float(np.mean(r0)), float(np.mean(r1))]))
+        sols.append(X[0])
+        log(f"C5 mu={m:.5f}: {shifts[-1]}")
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    info.update(nrhs=12, shifts=shifts, total_s=round(total, 3),
+                ms_per_source_all_shifts=round(total * 1e3 / 12, 2),
+                total_mvps_per_source=float(sum(x["mvps_per_source"] for x in shifts)))
+    return {"24x24x24x48_twisted_shifts_nrhs12": info}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +231,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the FP64 comparisons and sweep")
+    ap.add_argument("--extra", default="",
+                    help="comma-separated extra workload legs, outside the timed steps: c3 "
+                         "(20^3x32 and the uneven batch), c4 (16^4 gradient), c5 (24^3x48 "
+                         "twisted-mass shifts)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB with a plain device copy (a known-size reference "
                          "for hardware byte counters)")
@@ -258,6 +377,13 @@ def main():
         del X
         out["dslash_24x24x24x48"] = dslash_sweep(dbq, torch)
         log(f"dslash sweep: {out['dslash_24x24x24x48']}")
+    legs = {"c3": leg_c3, "c4": leg_c4, "c5": leg_c5}
+    for name in [x for x in a.extra.split(",") if x]:
+        if name not in legs:
+            raise SystemExit(f"unknown leg {name}")
+        log(f"leg {name} ...")
+        out.setdefault("extra", {}).update(legs[name](dbq, torch, synth))
+        log(f"leg {name}: {out['extra']}")
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Uh, L, kappa, Bh[0], mv64 or mv_mixed)
         log(f"cpu baseline: {out['cpu_baseline']}")
