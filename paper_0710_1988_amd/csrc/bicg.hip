@@ -87,6 +87,7 @@ __device__ __forceinline__ void store_partial(const VecSet& vs, double* partials
 __device__ void fin_xr(RhsScal& q, double a0, double a1, double a2) {
   if (!q.active) return;
   q.iters += 1;
+  q.since += 1;
   q.rr = a2;
   if (!fin(a0) || !fin(a1) || !fin(a2)) {
     q.flags |= F_NAN;
@@ -97,7 +98,9 @@ __device__ void fin_xr(RhsScal& q, double a0, double a1, double a2) {
   if (a2 <= q.stop2) q.flags |= F_CONV;
   if (q.delta2 > 0.0) {
     if (a2 > q.rr_max) q.rr_max = a2;
-    if (a2 < q.delta2 * q.rr_max) q.flags |= F_RELIABLE;
+    // a drop by the reliable-update factor, or a long stretch without one (checked for a
+    // stall by the FP64 residual that follows)
+    if (a2 < q.delta2 * q.rr_max || q.since >= STALL_ITERS) q.flags |= F_RELIABLE;
   }
   if (norm2(rn) <= 1e-28 * q.rhat2 * a2) q.flags |= F_BREAK;
   if (q.flags & F_OMEGA0) q.flags |= F_BREAK;
@@ -214,6 +217,9 @@ __device__ void fin_aux(int op, RhsScal& q, double a0, double a1, double a2) {
     q.beta = zd{0.0, 0.0};
     q.iters = 0;
     q.flags = 0;
+    q.since = 0;
+    q.stalls = 0;
+    q.rr_prev = a2;
     if (!fin(a2)) {
       q.flags = F_NAN;
       q.active = 0;
@@ -232,6 +238,7 @@ __device__ void fin_aux(int op, RhsScal& q, double a0, double a1, double a2) {
     q.flags = 0;
     q.active = 1;
     q.sel = 0;
+    q.since = 0;
   } else {  // AX_REPLACE
     if (!q.sel) return;
     const zd rn{a0, a1};
@@ -245,6 +252,7 @@ __device__ void fin_aux(int op, RhsScal& q, double a0, double a1, double a2) {
     q.flags = 0;
     q.active = 1;
     q.sel = 0;
+    q.since = 0;
     if (norm2(rn) <= 1e-28 * q.rhat2 * a2) {
       q.flags = F_BREAK;
       q.active = 0;

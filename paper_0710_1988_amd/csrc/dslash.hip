@@ -360,6 +360,14 @@ __device__ void finalize(const DsBatch& B, RhsScal* sc, const double* partials) 
               q.flags = F_NAN;
               q.active = 0;
               q.sel = 0;
+            } else {
+              q.stalls = a0 > 0.25 * q.rr_prev ? q.stalls + 1 : 0;
+              q.rr_prev = a0;
+              if (q.stalls >= 2) {
+                q.flags = F_STALL;
+                q.active = 0;
+                q.sel = 0;
+              }
             }
           }
         }

@@ -24,6 +24,7 @@ enum : int {
   F_OMEGA0 = 8,    // omega = 0 in this iteration (restart after the update)
   F_NAN = 16,      // non-finite reduction
   F_DONE = 32,     // FP64 true residual below the stopping threshold (decided on the device)
+  F_STALL = 64,    // FP32 iteration no longer reduces the FP64 residual (decided on the device)
 };
 
 struct RhsScal {
@@ -41,8 +42,16 @@ struct RhsScal {
   int flags;
   int iters;
   int nrel;        // FP64 residual replacements decided on the device (each one FP64 MVP)
+  int since;       // iterations since the last residual replacement (mixed precision)
+  int stalls;      // consecutive FP64 checks that found too little progress (mixed precision)
   int pad;
+  double rr_prev;  // FP64 ||r||^2 at the previous check (mixed precision)
 };
+
+// Mixed precision gives up on an rhs (F_STALL; the solve continues it in FP64 from its current
+// solution) when two FP64 checks in a row find the true residual reduced by less than 2x; an
+// FP64 check is also forced after STALL_ITERS iterations without a residual replacement.
+constexpr int STALL_ITERS = 250;
 
 // ----------------------------------------------------------------------------- batches
 constexpr int MAXLAT = 8;

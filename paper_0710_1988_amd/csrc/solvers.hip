@@ -368,7 +368,7 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
 
   std::vector<long long> mvb(NR, 0);
   std::vector<int> status(NR, DBQ_NOT_CONVERGED), restarts(NR, 0), relup(NR, 0);
-  std::vector<char> done(NR, 0), have_true(NR, 0);
+  std::vector<char> done(NR, 0), have_true(NR, 0), stalled(NR, 0);
   std::vector<double> rrt(NR, 0.0);
   std::memset(hs, 0, sizeof(RhsScal) * NR);
   bool any_x0 = false;
@@ -583,6 +583,11 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
           status[j] = DBQ_OK;
           rrt[j] = q.rr_true;
           have_true[j] = 1;
+        } else if (q.flags & F_STALL) {
+          done[j] = 1;
+          stalled[j] = 1;
+          rrt[j] = q.rr_true;
+          have_true[j] = 1;
         } else if (q.flags & F_NAN) {
           done[j] = 1;
           status[j] = DBQ_EBREAKDOWN;
@@ -758,9 +763,6 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
   for (int i = 0; i < nops; ++i)
     unpack_spinor_f64(s, op[i].g, x64 + off64[base[i]], X[i], nrhs[i]);
   DBQ_HIP(hipStreamSynchronize(s));
-  timer_collect(c);
-  const double secs = now_s() - t0;
-  int worst = DBQ_OK;
   for (int j = 0; j < NR; ++j) {
     dbq_stats& o = st[j];
     o.matvecs = mvb[j] + hs[j].nrel + 2LL * hs[j].iters;
@@ -768,11 +770,75 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
     o.restarts = restarts[j];
     o.reliable_updates = relup[j] + hs[j].nrel;
     o.rel_true_resid = hs[j].bb > 0 ? std::sqrt(rrt[j] / hs[j].bb) : 0.0;
-    o.seconds = secs;
     o.status = status[j];
     o.pad = 0;
-    if (status[j] < 0) worst = std::min(worst, status[j]);
-    else if (worst >= 0) worst = std::max(worst, status[j]);
+  }
+
+  // ---- rhs whose FP32 iteration stalled: continue them in FP64 from their current solution
+  // (same deflation space, remaining MVP budget), gathered per lattice into contiguous buffers
+  if (std::any_of(stalled.begin(), stalled.end(), [](char v) { return v != 0; })) {
+    std::vector<dbq_operator> ops2;
+    std::vector<const void*> V2, B2;
+    std::vector<void*> X2;
+    std::vector<int32_t> k2, n2;
+    std::vector<std::vector<int>> rows;  // global rhs index of each rescued rhs, per lattice
+    std::vector<int> lat;                // lattice of each entry of rows
+    int64_t used = 0;
+    for (int i = 0; i < nops; ++i) {
+      std::vector<int> js;
+      for (int jl = 0; jl < nrhs[i]; ++jl)
+        if (stalled[base[i] + jl]) js.push_back(base[i] + jl);
+      if (js.empty()) continue;
+      const size_t vb = size_t(op[i].n()) * sizeof(double2);
+      char* bs = (char*)ws.take(vb * js.size());
+      char* xs = (char*)ws.take(vb * js.size());
+      for (size_t q = 0; q < js.size(); ++q) {
+        const size_t jl = size_t(js[q] - base[i]);
+        DBQ_HIP(hipMemcpyAsync(bs + q * vb, (const char*)B[i] + jl * vb, vb,
+                               hipMemcpyDeviceToDevice, s));
+        DBQ_HIP(hipMemcpyAsync(xs + q * vb, (const char*)X[i] + jl * vb, vb,
+                               hipMemcpyDeviceToDevice, s));
+        used = std::max<int64_t>(used, st[js[q]].matvecs);
+      }
+      ops2.push_back(ops[i]);
+      V2.push_back(Vin ? Vin[i] : nullptr);
+      k2.push_back(kk[i]);
+      B2.push_back(bs);
+      X2.push_back(xs);
+      n2.push_back(int32_t(js.size()));
+      rows.push_back(js);
+      lat.push_back(i);
+    }
+    std::vector<dbq_stats> st2(stalled.size());
+    dbicgstab(c, ops2.data(), int(ops2.size()), V2.data(), k2.data(), B2.data(), X2.data(),
+              n2.data(), tol, std::max<int64_t>(1, max_mv - used), DBQ_FP64, dagger, st2.data());
+    size_t q2 = 0;
+    for (size_t l = 0; l < rows.size(); ++l) {
+      const int li = lat[l];
+      const size_t vb = size_t(op[li].n()) * sizeof(double2);
+      for (size_t q = 0; q < rows[l].size(); ++q, ++q2) {
+        const int j = rows[l][q];
+        DBQ_HIP(hipMemcpyAsync((char*)X[li] + size_t(j - base[li]) * vb,
+                               (const char*)X2[l] + q * vb, vb, hipMemcpyDeviceToDevice, s));
+        dbq_stats& o = st[j];
+        const dbq_stats& r = st2[q2];
+        o.matvecs += r.matvecs;
+        o.iterations += r.iterations;
+        o.restarts += r.restarts;
+        o.rel_true_resid = r.rel_true_resid;
+        o.status = r.status;
+      }
+    }
+    DBQ_HIP(hipStreamSynchronize(s));
+  }
+  timer_collect(c);
+  const double secs = now_s() - t0;
+  int worst = DBQ_OK;
+  for (int j = 0; j < NR; ++j) {
+    st[j].seconds = secs;
+    const int sj = st[j].status;
+    if (sj < 0) worst = std::min(worst, sj);
+    else if (worst >= 0) worst = std::max(worst, sj);
   }
   return worst;
 }
