@@ -78,22 +78,36 @@ __global__ __launch_bounds__(G_BS) void k_gram(const double2* __restrict__ A, lo
   }
 }
 
-// C[i + j*na] = sum over chunks of the tile partials, in chunk order
+// C[i + j*na] = sum over chunks of the tile partials.  One block per tile: thread t adds the
+// chunks t, t + G_BS, ... of every entry of the tile, then a fixed-order block reduction
+// (deterministic, and not latency-bound on thousands of chunks).
 template <int TA, int TB>
-__global__ void k_gram_final(const double* __restrict__ work, int nchunks, int ntA, int ntB, int na,
-                             int nb, double2* __restrict__ C) {
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= na * nb) return;
-  const int i = id % na, j = id / na;
-  const int ta = i / TA, a = i - ta * TA, tb = j / TB, b = j - tb * TB;
-  const int tile = ta * ntB + tb, ntiles = ntA * ntB;
-  double re = 0, im = 0;
-  for (int c = 0; c < nchunks; ++c) {
-    const double* p = work + ((long long)c * ntiles + tile) * (TA * TB * 2) + (a * TB + b) * 2;
-    re += p[0];
-    im += p[1];
+__global__ __launch_bounds__(G_BS) void k_gram_final(const double* __restrict__ work, int nchunks,
+                                                     int ntA, int ntB, int na, int nb,
+                                                     double2* __restrict__ C) {
+  constexpr int NV = TA * TB * 2;
+  const int tile = blockIdx.x, ntiles = ntA * ntB;
+  const int ta = tile / ntB, tb = tile - ta * ntB;
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  for (int c = threadIdx.x; c < nchunks; c += G_BS) {
+    const double* p = work + ((long long)c * ntiles + tile) * NV;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] += p[v];
   }
-  C[i + (long long)j * na] = make_double2(re, im);
+  __shared__ double sh[NV * (G_BS / 64)];
+  block_sum<NV, G_BS>(acc, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int a = 0; a < TA; ++a)
+#pragma unroll
+      for (int b = 0; b < TB; ++b) {
+        const int i = ta * TA + a, j = tb * TB + b;
+        if (i < na && j < nb)
+          C[i + (long long)j * na] = make_double2(acc[(a * TB + b) * 2], acc[(a * TB + b) * 2 + 1]);
+      }
+  }
 }
 
 template <int TA, int TB>
@@ -108,8 +122,7 @@ void gram_impl(hipStream_t s, const double2* A, long long lda, int na, const dou
   hipLaunchKernelGGL((k_gram<TA, TB>), dim3(unsigned(nblocks)), dim3(G_BS), 0, s, A, lda, na, B,
                      ldb, nb, n, V, g5, ntA, ntB, int(nblocks), work);
   DBQ_HIP(hipGetLastError());
-  const int tot = na * nb;
-  hipLaunchKernelGGL((k_gram_final<TA, TB>), dim3((tot + 127) / 128), dim3(128), 0, s, work,
+  hipLaunchKernelGGL((k_gram_final<TA, TB>), dim3(unsigned(ntA * ntB)), dim3(G_BS), 0, s, work,
                      nchunks, ntA, ntB, na, nb, C);
   DBQ_HIP(hipGetLastError());
 }
@@ -183,13 +196,15 @@ __global__ __launch_bounds__(256) void k_norm2(const double2* __restrict__ x, lo
   if (threadIdx.x == 0) work[(long long)vec * nchunks + chunk] = s[0];
 }
 
-__global__ void k_norm2_final(const double* __restrict__ work, int nchunks, int count,
-                              double* __restrict__ out) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= count) return;
-  double s = 0;
-  for (int c = 0; c < nchunks; ++c) s += work[(long long)v * nchunks + c];
-  out[v] = s;
+// one block per vector: strided partial sums, then a fixed-order block reduction
+__global__ __launch_bounds__(G_BS) void k_norm2_final(const double* __restrict__ work, int nchunks,
+                                                      double* __restrict__ out) {
+  const int v = blockIdx.x;
+  double s[1] = {0.0};
+  for (int c = threadIdx.x; c < nchunks; c += G_BS) s[0] += work[(long long)v * nchunks + c];
+  __shared__ double sh[G_BS / 64];
+  block_sum<1, G_BS>(s, sh);
+  if (threadIdx.x == 0) out[v] = s[0];
 }
 
 __global__ void k_copy(const double2* __restrict__ x, double2* __restrict__ y, long long n) {
@@ -307,8 +322,7 @@ void norm2_f64(hipStream_t s, const double2* x, long long ld, int count, long lo
   DBQ_CHECK(size_t(nchunks) * count <= work_elems, "norm2: workspace too small");
   hipLaunchKernelGGL(k_norm2, dim3(nchunks, count), dim3(G_BS), 0, s, x, ld, n, nchunks, work);
   DBQ_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_norm2_final, dim3((count + 63) / 64), dim3(64), 0, s, work, nchunks, count,
-                     out);
+  hipLaunchKernelGGL(k_norm2_final, dim3(count), dim3(G_BS), 0, s, work, nchunks, out);
   DBQ_HIP(hipGetLastError());
 }
 

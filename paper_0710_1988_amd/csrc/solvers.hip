@@ -1048,6 +1048,7 @@ int kappa_crit(dbq_ctx* c, const int32_t L[4], const void* links, int m, int k, 
   scale_f64(s, ar.col(0), ar.col(0), n, ar.nrm);
   int j0 = 0;
   double lam_re = 0, lam_im = 0, res = INFINITY;
+  const bool debug = std::getenv("DBQ_DEBUG") != nullptr;
   while (true) {
     ar.extend(j0);
     ar.cycle_end(k, 2, 0.0);
@@ -1059,6 +1060,9 @@ int kappa_crit(dbq_ctx* c, const int32_t L[4], const void* links, int m, int k, 
     lam_re = th_h[0].x - 1.0;
     lam_im = th_h[0].y;
     res = hp[3];
+    if (debug)
+      std::fprintf(stderr, "[dbq] kappa_c cycle: mv %lld lambda %.10f%+.10fi resid %.3e\n",
+                   (long long)ar.mv, lam_re, lam_im, res);
     if (res <= tol * std::hypot(th_h[0].x, th_h[0].y) || ar.mv >= max_mv) break;
     ar.restart(k);
     j0 = k;
