@@ -361,7 +361,12 @@ __device__ void finalize(const DsBatch& B, RhsScal* sc, const double* partials) 
               q.active = 0;
               q.sel = 0;
             } else {
-              q.stalls = a0 > 0.25 * q.rr_prev ? q.stalls + 1 : 0;
+              // a stall: the FP32 recursion claimed a 10x drop (or ran STALL_ITERS iterations
+              // without one) but the FP64 residual fell by less than 2x since the last check;
+              // convergence claims just above the tolerance are not counted
+              const bool slow = a0 > 0.25 * q.rr_prev;
+              if (!slow) q.stalls = 0;
+              else if (q.rr <= 0.01 * q.rr_prev || q.since >= STALL_ITERS) q.stalls += 1;
               q.rr_prev = a0;
               if (q.stalls >= 2) {
                 q.flags = F_STALL;

@@ -49,8 +49,9 @@ struct RhsScal {
 };
 
 // Mixed precision gives up on an rhs (F_STALL; the solve continues it in FP64 from its current
-// solution) when two FP64 checks in a row find the true residual reduced by less than 2x; an
-// FP64 check is also forced after STALL_ITERS iterations without a residual replacement.
+// solution) after two FP64 checks at which the FP32 recursion claimed a 10x drop, or had run
+// STALL_ITERS iterations without a replacement (which forces a check), while the true residual
+// fell by less than 2x.
 constexpr int STALL_ITERS = 250;
 
 // ----------------------------------------------------------------------------- batches
