@@ -282,6 +282,17 @@ __device__ __forceinline__ void hops_mu(const typename IO<T>::SE* __restrict__ i
 
 __device__ __forceinline__ bool finite_d(double v) { return isfinite(v); }
 
+// Byte accounting of a gated launch (timing only), done by the blocks of the first site block or
+// tile of a lattice: each rhs they process adds its spinor traffic, the first one of the lattice
+// in this launch (launch-id tag) also the links.
+__device__ __forceinline__ void account(const DsBatch& B, int l) {
+  unsigned long long by = (unsigned long long)B.lat[l].g.V *
+                          (unsigned long long)(B.acct.spinor_passes * B.acct.spinor_bytes);
+  if (atomicMax(B.acct.tags + l, B.acct.id) < B.acct.id)
+    by += (unsigned long long)B.lat[l].g.V * (unsigned long long)B.acct.link_bytes;
+  atomicAdd(B.acct.bytes, by);
+}
+
 // Combine the per-block partials of one epilogue: every right-hand side of the batch is reduced
 // by one wavefront over its site blocks in a fixed order.
 template <int EPI>
@@ -307,17 +318,6 @@ __device__ void finalize(const DsBatch& B, RhsScal* sc, const double* partials) 
     a2 = wave_sum(a2);
     if (lane == 0) {
       RhsScal& q = sc[rhs];
-      if (B.acct.bytes) {
-        // the flag the Dslash kernel was gated on, read before this launch changes it
-        const bool processed = (EPI == EPI_RESID) ? q.sel != 0 : q.active != 0;
-        if (processed) {
-          unsigned long long by = (unsigned long long)B.lat[l].g.V *
-                                  (unsigned long long)(B.acct.spinor_passes * B.acct.spinor_bytes);
-          if (atomicMax(B.acct.tags + l, B.acct.id) < B.acct.id)
-            by += (unsigned long long)B.lat[l].g.V * (unsigned long long)B.acct.link_bytes;
-          atomicAdd(B.acct.bytes, by);
-        }
-      }
       if (EPI == EPI_RHAT) {
         if (q.active) {
           const zd d{a0, a1};
@@ -487,6 +487,11 @@ void k_dslash(DsBatch B, RhsScal* __restrict__ sc, double* __restrict__ partials
     else if (a && gate == 2) a = sc[L.rhs_base + r0 + j].sel != 0;
     act[j] = a;
     any = any || a;
+  }
+  if (B.acct.bytes && sb == 0 && threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+      if (act[j]) account(B, l);
   }
 #if DBQ_DS_PARITY_INTERLEAVE
   // consecutive site blocks alternate between the two parities of the same spatial range, so
@@ -825,6 +830,7 @@ __global__ __launch_bounds__(DS_BS) void k_dslash_tile(DsBatch B, RhsScal* __res
   while (j < Gc) {
     const int r = r0 + j;
     const float4* buf = lds;
+    if (B.acct.bytes && tile == 0 && tid == 0) account(B, l);
     __builtin_amdgcn_s_waitcnt(0);  // this wave's LDS-direct copies have landed
     __syncthreads();                // and everyone else's
     const int jn = next(j + 1);

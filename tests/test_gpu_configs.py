@@ -34,6 +34,34 @@ def _golden(name):
     raise KeyError(name)
 
 
+# ----------------------------------------------------------------------------- C2
+def test_c2_full_size_batched_mixed_solve_sampled_residual(gpu_lib):
+    """The benchmark's solve at full size: 16^4, kappa = 0.995 kappa_c, GMRES-DR(60,20)
+    deflation, 12 Z2 sources in one mixed-precision call.  Every source reports an FP64 true
+    residual below 1e-8; the oracle recomputes b - A x at 512 sampled sites of each solution,
+    whose norm must be of the size that a residual below 1e-8 allows there."""
+    L = (16, 16, 16, 16)
+    lat = W.Lattice(L)
+    U = synth.gauge_field(L, 0.6, 102)
+    kc, _, res, st = gpu_lib.kappa_critical(L, dev(U), m=96, k=32, tol=1e-8)
+    assert st == 0
+    kap = 0.995 * kc
+    _, V, _, gst = gpu_lib.gmresdr_first_rhs(L, dev(U), dev(synth.point_source(L)), kap, 60, 20,
+                                             tol=1e-8)
+    assert gst["status"] == 0
+    B = synth.z2_sources(L, 12, 1102)
+    X, stats, status = gpu_lib.dbicgstab_solve([dict(L=L, links=dev(U), kappa=kap, B=dev(B), V=V)],
+                                               tol=1e-8, prec="mixed")
+    assert status == 0 and all(s["rel_true_resid"] <= 1e-8 for s in stats)
+    Xh = host(X[0])
+    sites = np.random.default_rng(7).choice(lat.V, 512, replace=False)
+    frac = len(sites) / lat.V
+    for j in range(12):
+        r = B[j][sites] - W.apply_A_sites(U, Xh[j], lat, kap, sites)
+        # a uniformly spread residual of relative size 1e-8 puts ~frac of its square here
+        assert np.linalg.norm(r) <= 10 * 1e-8 * np.linalg.norm(B[j]) * np.sqrt(frac)
+
+
 # ----------------------------------------------------------------------------- C3
 def test_c3_uneven_batch_with_own_kappa_and_deflation(gpu_lib):
     probs = []

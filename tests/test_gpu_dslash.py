@@ -115,6 +115,21 @@ def test_full_size_24x48_sampled_sites(gpu_lib, prec, tol):
     assert relerr(out[sites], ref) <= tol
 
 
+@pytest.mark.parametrize("dagger", [False, True])
+def test_full_size_16x16x16x16_batch_of_12_sampled_sites(gpu_lib, dagger):
+    """The benchmark's operator launch: 16^4, 12 Z2 sources in one FP32 call in the tuned launch
+    shape; 256 sampled sites of every source recomputed by the oracle."""
+    L = (16, 16, 16, 16)
+    lat = W.Lattice(L)
+    U = synth.gauge_field(L, 0.6, 102)
+    psi = synth.z2_sources(L, 12, 1102)
+    out = host(gpu_lib.wilson_apply(L, dev(U), dev(psi), 0.2074870, 0.0, dagger, "mixed"))
+    sites = np.random.default_rng(6).choice(lat.V, 256, replace=False)
+    for j in range(12):
+        ref = W.apply_A_sites(U, psi[j], lat, 0.2074870, sites, 0.0, dagger)
+        assert relerr(out[j][sites], ref) <= 2e-6
+
+
 def test_rejects_bad_shapes_before_launch(gpu_lib):
     import torch
     L = (4, 4, 4, 4)
