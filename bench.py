@@ -234,6 +234,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the FP64 comparisons and sweep")
+    ap.add_argument("--dslash-only", action="store_true",
+                    help="only the 24^3 x 48 Dslash bandwidth sweep (one JSON line)")
     ap.add_argument("--extra", default="",
                     help="comma-separated extra workload legs, outside the timed steps: c3 "
                          "(20^3x32 and the uneven batch), c4 (16^4 gradient), c5 (24^3x48 "
@@ -263,6 +265,12 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: 268435456 bytes read, 268435456 bytes written")
         del src, dst
+    if a.dslash_only:
+        sweep = dslash_sweep(dbq, torch)
+        print(json.dumps({"metric": "Dslash HBM GB/s (algorithmic bytes / kernel time)",
+                          "unit": "GB/s", "data": "synthetic", "dslash_24x24x24x48": sweep}),
+              flush=True)
+        return
     L = (16, 16, 16, 16)
     Vol = int(np.prod(L))
     nrhs, m, k, tol = 12, 60, 20, 1e-8

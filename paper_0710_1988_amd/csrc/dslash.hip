@@ -17,7 +17,7 @@
 #define DBQ_OCC_F32 0
 #endif
 #ifndef DBQ_OCC_F64
-#define DBQ_OCC_F64 2
+#define DBQ_OCC_F64 0
 #endif
 #ifndef DBQ_DS_CHAIN
 #define DBQ_DS_CHAIN 0
@@ -442,16 +442,13 @@ __device__ __forceinline__ void finish_site(const cx<T> (&psi)[12], const cx<T> 
   }
 }
 
-#if DBQ_OCC_F32 > 0
-// Minimum waves per SIMD the register allocation must leave room for.
+// Minimum waves per SIMD the register allocation must leave room for (1: no constraint).
 template <typename T, int NB>
 struct Occ {
-  static constexpr int value = sizeof(T) == 4 ? (NB <= 2 ? DBQ_OCC_F32 : 2) : DBQ_OCC_F64;
+  static constexpr int value = sizeof(T) == 4 ? (DBQ_OCC_F32 > 0 ? DBQ_OCC_F32 : 1)
+                                              : (DBQ_OCC_F64 > 0 ? DBQ_OCC_F64 : 1);
 };
 #define DBQ_DS_ATTR __attribute__((amdgpu_waves_per_eu(Occ<T, NB>::value)))
-#else
-#define DBQ_DS_ATTR
-#endif
 
 template <typename T, bool DAG, int EPI, int NB>
 __global__ __launch_bounds__(DS_BS) DBQ_DS_ATTR
@@ -652,27 +649,31 @@ __device__ __forceinline__ int slot_site(const Geom& g, const TileGeo& t, const 
     return p * g.Vh + (tile << g.lTh) + (j - p * t.vh);
   }
   if (j >= nslots) return tile << g.lTh;
-  int f = 0;
+  // face f and its first slot, selected without indexing a local array by a runtime value
+  // (which would place the array in scratch memory)
+  int f = 0, fb = t.fbase[0];
 #pragma unroll
   for (int i = 1; i < 8; ++i)
-    if (j >= t.fbase[i]) f = i;
+    if (j >= t.fbase[i]) {
+      f = i;
+      fb = t.fbase[i];
+    }
   const int mu = f >> 1;
   const int dir = (f & 1) ? -1 : +1;
-  uint32_t q = uint32_t(j - t.fbase[f]);
-  int ic[4];
+  uint32_t q = uint32_t(j - fb);
+  int ic[4], tn[4];
 #pragma unroll
   for (int nu = 0; nu < 4; ++nu) {
     if (nu == mu) {
       ic[nu] = dir > 0 ? 0 : g.T[nu] - 1;
+      int v = tc[nu] + dir;
+      tn[nu] = v < 0 ? g.NT[nu] - 1 : (v == g.NT[nu] ? 0 : v);
     } else {
       ic[nu] = int(q & uint32_t(g.T[nu] - 1));
       q >>= g.lT[nu];
+      tn[nu] = tc[nu];
     }
   }
-  int tn[4] = {tc[0], tc[1], tc[2], tc[3]};
-  int v = tn[mu] + dir;
-  v = v < 0 ? g.NT[mu] - 1 : (v == g.NT[mu] ? 0 : v);
-  tn[mu] = v;
   const int tile_n = tn[0] + g.NT[0] * (tn[1] + g.NT[1] * (tn[2] + g.NT[2] * tn[3]));
   const int p = (ic[0] + ic[1] + ic[2] + ic[3]) & 1;
   return p * g.Vh + (tile_n << g.lTh) + in_tile_half(g, ic);
