@@ -346,8 +346,8 @@ def main():
                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic),
                      "traffic_source": traffic_src,
-                     "kernel": "k_dslash<float> (FP32 12-real links, 12 rhs per launch; "
-                               "working set MALL-resident at 16^4)",
+                     "kernel": "FP32 Dslash k_dslash_tile (LDS-staged 4^4 tiles, 12-real links, "
+                               "12 rhs per launch; working set MALL-resident at 16^4)",
                      "avg_launch_us": round(avg_us, 2), "launches": n32,
                      "algorithmic_MB_per_launch": round(by32 / max(n32, 1) / 1e6, 2)},
         "fp64_dslash_in_step": {"launches": n64,
