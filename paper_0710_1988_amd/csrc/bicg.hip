@@ -122,8 +122,7 @@ __global__ __launch_bounds__(BL_BS) void k_bicg_step(VecSet vs, E* __restrict__ 
                                                      E* __restrict__ p, const E* __restrict__ v,
                                                      const E* __restrict__ t,
                                                      RhsScal* __restrict__ sc,
-                                                     double* __restrict__ partials,
-                                                     unsigned int* __restrict__ counter) {
+                                                     double* __restrict__ partials) {
   typedef typename ET<E>::R R;
   constexpr int NC = ET<E>::NC;
   const int lb = xcd_block(blockIdx.x, vs.nblocks);
@@ -267,8 +266,7 @@ __global__ __launch_bounds__(BL_BS) void k_aux64(VecSet vs, const double2* __res
                                                  double2* __restrict__ rhat,
                                                  double2* __restrict__ p, double2* __restrict__ v,
                                                  RhsScal* __restrict__ sc,
-                                                 double* __restrict__ partials,
-                                                 unsigned int* __restrict__ counter) {
+                                                 double* __restrict__ partials) {
   const int lb = xcd_block(blockIdx.x, vs.nblocks);
   const int2 bm = vs.blk[lb];
   const int rhs = bm.x, ch = bm.y;
@@ -308,8 +306,7 @@ __global__ __launch_bounds__(BL_BS) void k_aux32(VecSet vs, VecSet vs64,
                                                  float4* __restrict__ p, float4* __restrict__ v,
                                                  float4* __restrict__ x32,
                                                  RhsScal* __restrict__ sc,
-                                                 double* __restrict__ partials,
-                                                 unsigned int* __restrict__ counter) {
+                                                 double* __restrict__ partials) {
   const int lb = xcd_block(blockIdx.x, vs.nblocks);
   const int2 bm = vs.blk[lb];
   const int rhs = bm.x, ch = bm.y;
@@ -380,20 +377,20 @@ __global__ __launch_bounds__(BL_BS) void k_xacc(VecSet vs, VecSet vs64, double2*
 
 template <typename E>
 void step(hipStream_t s, int op, const VecSet& vs, E* x, E* r, const E* rhat, E* p, const E* v,
-          const E* t, RhsScal* sc, double* partials, unsigned int* counter) {
+          const E* t, RhsScal* sc, double* partials) {
   dim3 g(vs.nblocks), b(BL_BS);
   switch (op) {
     case BI_P:
       hipLaunchKernelGGL((k_bicg_step<E, BI_P>), g, b, 0, s, vs, x, r, rhat, p, v, t, sc,
-                         partials, counter);
+                         partials);
       break;
     case BI_S:
       hipLaunchKernelGGL((k_bicg_step<E, BI_S>), g, b, 0, s, vs, x, r, rhat, p, v, t, sc,
-                         partials, counter);
+                         partials);
       break;
     default:
       hipLaunchKernelGGL((k_bicg_step<E, BI_XR>), g, b, 0, s, vs, x, r, rhat, p, v, t, sc,
-                         partials, counter);
+                         partials);
       DBQ_HIP(hipGetLastError());
       hipLaunchKernelGGL(k_fin_xr, dim3(fin_blocks(vs)), b, 0, s, vs, sc, partials);
       break;
@@ -405,27 +402,24 @@ void step(hipStream_t s, int op, const VecSet& vs, E* x, E* r, const E* rhat, E*
 
 void bicg_step_f64(hipStream_t s, int op, const VecSet& vs, double2* x, double2* r,
                    const double2* rhat, double2* p, const double2* v, const double2* t,
-                   RhsScal* sc, double* partials, unsigned int* counter) {
-  step<double2>(s, op, vs, x, r, rhat, p, v, t, sc, partials, counter);
+                   RhsScal* sc, double* partials) {
+  step<double2>(s, op, vs, x, r, rhat, p, v, t, sc, partials);
 }
 void bicg_step_f32(hipStream_t s, int op, const VecSet& vs, float4* x, float4* r,
                    const float4* rhat, float4* p, const float4* v, const float4* t,
-                   RhsScal* sc, double* partials, unsigned int* counter) {
-  step<float4>(s, op, vs, x, r, rhat, p, v, t, sc, partials, counter);
+                   RhsScal* sc, double* partials) {
+  step<float4>(s, op, vs, x, r, rhat, p, v, t, sc, partials);
 }
 
 void bicg_aux_f64(hipStream_t s, int op, const VecSet& vs, const double2* r64, double2* r,
-                  double2* rhat, double2* p, double2* v, RhsScal* sc, double* partials,
-                  unsigned int* counter) {
+                  double2* rhat, double2* p, double2* v, RhsScal* sc, double* partials) {
   dim3 g(vs.nblocks), b(BL_BS);
   if (op == AX_INIT)
-    hipLaunchKernelGGL((k_aux64<AX_INIT>), g, b, 0, s, vs, r64, r, rhat, p, v, sc, partials, counter);
+    hipLaunchKernelGGL((k_aux64<AX_INIT>), g, b, 0, s, vs, r64, r, rhat, p, v, sc, partials);
   else if (op == AX_RESTART)
-    hipLaunchKernelGGL((k_aux64<AX_RESTART>), g, b, 0, s, vs, r64, r, rhat, p, v, sc, partials,
-                       counter);
+    hipLaunchKernelGGL((k_aux64<AX_RESTART>), g, b, 0, s, vs, r64, r, rhat, p, v, sc, partials);
   else
-    hipLaunchKernelGGL((k_aux64<AX_REPLACE>), g, b, 0, s, vs, r64, r, rhat, p, v, sc, partials,
-                       counter);
+    hipLaunchKernelGGL((k_aux64<AX_REPLACE>), g, b, 0, s, vs, r64, r, rhat, p, v, sc, partials);
   DBQ_HIP(hipGetLastError());
   if (op == AX_INIT) launch_fin_aux<AX_INIT>(s, vs, sc, partials);
   else if (op == AX_RESTART) launch_fin_aux<AX_RESTART>(s, vs, sc, partials);
@@ -434,17 +428,17 @@ void bicg_aux_f64(hipStream_t s, int op, const VecSet& vs, const double2* r64, d
 
 void bicg_aux_f32(hipStream_t s, int op, const VecSet& vs32, const VecSet& vs64,
                   const double2* r64, float4* r, float4* rhat, float4* p, float4* v, float4* x32,
-                  RhsScal* sc, double* partials, unsigned int* counter) {
+                  RhsScal* sc, double* partials) {
   dim3 g(vs32.nblocks), b(BL_BS);
   if (op == AX_INIT)
     hipLaunchKernelGGL((k_aux32<AX_INIT>), g, b, 0, s, vs32, vs64, r64, r, rhat, p, v, x32, sc,
-                       partials, counter);
+                       partials);
   else if (op == AX_RESTART)
     hipLaunchKernelGGL((k_aux32<AX_RESTART>), g, b, 0, s, vs32, vs64, r64, r, rhat, p, v, x32,
-                       sc, partials, counter);
+                       sc, partials);
   else
     hipLaunchKernelGGL((k_aux32<AX_REPLACE>), g, b, 0, s, vs32, vs64, r64, r, rhat, p, v, x32,
-                       sc, partials, counter);
+                       sc, partials);
   DBQ_HIP(hipGetLastError());
   if (op == AX_INIT) launch_fin_aux<AX_INIT>(s, vs32, sc, partials);
   else if (op == AX_RESTART) launch_fin_aux<AX_RESTART>(s, vs32, sc, partials);

@@ -39,12 +39,9 @@ int dbq_create(dbq_ctx** out, void* stream) {
   if (!c) return DBQ_ENOMEM;
   c->stream = (hipStream_t)stream;
   if (hipGetDevice(&c->device) != hipSuccess ||
-      hipMalloc(&c->counters, sizeof(unsigned int) * dbq::NCOUNTERS) != hipSuccess ||
-      hipMemset(c->counters, 0, sizeof(unsigned int) * dbq::NCOUNTERS) != hipSuccess ||
       hipMalloc(&c->acct, sizeof(unsigned long long) * 32) != hipSuccess ||
       hipMemset(c->acct, 0, sizeof(unsigned long long) * 32) != hipSuccess) {
     (void)hipGetLastError();
-    if (c->counters) (void)hipFree(c->counters);
     if (c->acct) (void)hipFree(c->acct);
     delete c;
     return DBQ_EHIP;
@@ -58,7 +55,6 @@ int dbq_destroy(dbq_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   for (auto& b : c->pool) (void)hipFree(b.p);
   if (c->pinned) (void)hipHostFree(c->pinned);
-  if (c->counters) (void)hipFree(c->counters);
   if (c->acct) (void)hipFree(c->acct);
   for (auto& t : c->timers) {
     for (auto& pr : t.ev) {

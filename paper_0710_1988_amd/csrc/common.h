@@ -242,26 +242,5 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh /* [NV * B
   }
 }
 
-// Last-block detection: every block has stored its partials; returns true in the block that
-// finishes last (all others' partials are then visible after the acquire fence).
-__device__ __forceinline__ bool last_block_arrive(unsigned int* counter, unsigned int nblocks) {
-  __shared__ int s_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned int old = atomicAdd(counter, 1u);
-    s_last = (old == nblocks - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (s_last) {
-    __threadfence();
-    return true;
-  }
-  return false;
-}
-
-__device__ __forceinline__ void last_block_reset(unsigned int* counter) {
-  if (threadIdx.x == 0) atomicExch(counter, 0u);
-}
 
 }  // namespace dbq

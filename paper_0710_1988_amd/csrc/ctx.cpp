@@ -57,8 +57,6 @@ void* pinned_get(dbq_ctx* c, size_t bytes) {
   return c->pinned;
 }
 
-unsigned int* counter(dbq_ctx* c, int i) { return c->counters + (i % NCOUNTERS); }
-
 WsScope::WsScope(dbq_ctx* ctx) : c(ctx), mark(0) {}
 WsScope::~WsScope() {
   for (size_t i = 0; i < taken.size(); ++i) ws_release(c, reinterpret_cast<void*>(taken[i]));

@@ -35,8 +35,6 @@ struct dbq_ctx {
     double bytes = 0;
   } timers[2];
 
-  // ---- geometry-independent counters (kept for kernels that need a device-wide count)
-  unsigned int* counters = nullptr;  // device, NCOUNTERS entries, kept zero between launches
 
   // ---- device accumulators for the algorithmic bytes of gated Dslash launches (timing only):
   //      [kind] bytes so far, [8 + 8 * kind + lattice] id of the last launch that counted the
@@ -52,12 +50,9 @@ struct dbq_ctx {
 
 namespace dbq {
 
-constexpr int NCOUNTERS = 64;
-
 void* ws_get(dbq_ctx* c, size_t bytes);
 void ws_release(dbq_ctx* c, void* p);
 void* pinned_get(dbq_ctx* c, size_t bytes);
-unsigned int* counter(dbq_ctx* c, int i);
 
 // RAII: everything taken from the pool inside a scope is returned at its end
 struct WsScope {

@@ -148,19 +148,18 @@ enum BicgOp : int { BI_P = 0, BI_S = 1, BI_XR = 2 };
 // FP64 vectors (double2 elements) or FP32 vectors (float4 elements)
 void bicg_step_f64(hipStream_t s, int op, const VecSet& vs, double2* x, double2* r,
                    const double2* rhat, double2* p, const double2* v, const double2* t,
-                   RhsScal* sc, double* partials, unsigned int* counter);
+                   RhsScal* sc, double* partials);
 void bicg_step_f32(hipStream_t s, int op, const VecSet& vs, float4* x, float4* r,
                    const float4* rhat, float4* p, const float4* v, const float4* t,
-                   RhsScal* sc, double* partials, unsigned int* counter);
+                   RhsScal* sc, double* partials);
 // init: r (FP64) -> working r (copy or narrowed), rhat = r, p = v = 0, x32 = 0 (mixed),
 //       rho = ||r||^2 ... ; mode 0: all rhs with active != 0; uses `sel` when only_sel
 enum BicgAux : int { AX_INIT = 0, AX_RESTART = 1, AX_REPLACE = 2 };
 void bicg_aux_f64(hipStream_t s, int op, const VecSet& vs, const double2* r64, double2* r,
-                  double2* rhat, double2* p, double2* v, RhsScal* sc, double* partials,
-                  unsigned int* counter);
+                  double2* rhat, double2* p, double2* v, RhsScal* sc, double* partials);
 void bicg_aux_f32(hipStream_t s, int op, const VecSet& vs32, const VecSet& vs64,
                   const double2* r64, float4* r, float4* rhat, float4* p, float4* v, float4* x32,
-                  RhsScal* sc, double* partials, unsigned int* counter);
+                  RhsScal* sc, double* partials);
 // x64 += widen(x32), x32 = 0 for rhs with sel != 0
 void bicg_xacc(hipStream_t s, const VecSet& vs32, const VecSet& vs64, double2* x64, float4* x32,
                const RhsScal* sc);

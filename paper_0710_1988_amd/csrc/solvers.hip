@@ -18,7 +18,6 @@ namespace dbq {
 
 namespace {
 
-enum : int { C_XR = 1, C_RHAT = 2, C_TS = 3, C_RESID = 4, C_AUX = 5 };
 
 struct Op {
   Geom g;
@@ -175,7 +174,7 @@ std::pair<int, int> choose_shape(dbq_ctx* c, bool f32, const DsBatch& b) {
 }
 
 void run_dslash(dbq_ctx* c, bool f32, const DsBatch& b0, int dagger, int epi, RhsScal* sc,
-                double* partials, int) {
+                double* partials) {
   const auto shape = choose_shape(c, f32, b0);
   const int kind = f32 ? 1 : 0;
   DsBatch b = b0;
@@ -265,14 +264,14 @@ void apply_operator(dbq_ctx* c, const dbq_operator* o, const void* in, void* out
     double2* b = ws.get<double2>(12LL * V * nrhs);
     pack_spinor_f64(c->stream, op.g, in, a, nrhs);
     DsBatch bt = make_batch({DsSpec{&op, false, a, b, nullptr, nrhs, 0}});
-    run_dslash(c, false, bt, dagger, EPI_NONE, nullptr, nullptr, 0);
+    run_dslash(c, false, bt, dagger, EPI_NONE, nullptr, nullptr);
     unpack_spinor_f64(c->stream, op.g, b, out, nrhs);
   } else {
     float4* a = ws.get<float4>(6LL * V * nrhs);
     float4* b = ws.get<float4>(6LL * V * nrhs);
     pack_spinor_f32(c->stream, op.g, in, a, nrhs);
     DsBatch bt = make_batch({DsSpec{&op, true, a, b, nullptr, nrhs, 0}});
-    run_dslash(c, true, bt, dagger, EPI_NONE, nullptr, nullptr, 0);
+    run_dslash(c, true, bt, dagger, EPI_NONE, nullptr, nullptr);
     unpack_spinor_f32(c->stream, op.g, b, out, nrhs);
   }
 }
@@ -398,7 +397,7 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
   }
   const DsBatch bx0 = make_batch(sx0), bres = make_batch(sres);
   copy_f64(s, b64, r64, tot64);
-  if (any_x0) run_dslash(c, false, bx0, dagger, EPI_RESID, sc, partials, C_RESID);
+  if (any_x0) run_dslash(c, false, bx0, dagger, EPI_RESID, sc, partials);
 
   // ---- deflation: (U^H A V) y = U^H r0, x0 += V y with U = gamma5 V (roles swapped for A^H)
   bool any_defl = false;
@@ -419,7 +418,7 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
     }
     double2* W = ws.get<double2>(k * n);
     const DsBatch bw = make_batch({DsSpec{&op[i], false, right, W, nullptr, k, 0}});
-    run_dslash(c, false, bw, dagger, EPI_NONE, nullptr, nullptr, 0);
+    run_dslash(c, false, bw, dagger, EPI_NONE, nullptr, nullptr);
     const size_t gw = gram_work_elems(n, k, std::max(k, nrhs[i]));
     double* gwork = ws.get<double>(gw);
     double2* M = ws.get<double2>(k * k);
@@ -444,7 +443,7 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
       if (hs[j].sel) mvb[j] += 1;
     }
     push();
-    run_dslash(c, false, bx0, dagger, EPI_RESID, sc, partials, C_RESID);
+    run_dslash(c, false, bx0, dagger, EPI_RESID, sc, partials);
   }
 
   // ---- BiCGStab working vectors
@@ -496,24 +495,23 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
   }
   push();
   if (mixed)
-    bicg_aux_f32(s, AX_INIT, vs32, vs64, r64, r32, rhat32, p32, v32, x32, sc, partials,
-                 counter(c, C_AUX));
+    bicg_aux_f32(s, AX_INIT, vs32, vs64, r64, r32, rhat32, p32, v32, x32, sc, partials);
   else
-    bicg_aux_f64(s, AX_INIT, vs64, r64, r64, rhat, p, v, sc, partials, counter(c, C_AUX));
+    bicg_aux_f64(s, AX_INIT, vs64, r64, r64, rhat, p, v, sc, partials);
 
   auto iterate = [&]() {
     if (mixed) {
-      bicg_step_f32(s, BI_P, vs32, x32, r32, rhat32, p32, v32, t32, sc, partials, counter(c, C_XR));
-      run_dslash(c, true, bv, dagger, EPI_RHAT, sc, partials, C_RHAT);
-      bicg_step_f32(s, BI_S, vs32, x32, r32, rhat32, p32, v32, t32, sc, partials, counter(c, C_XR));
-      run_dslash(c, true, bt, dagger, EPI_TS, sc, partials, C_TS);
-      bicg_step_f32(s, BI_XR, vs32, x32, r32, rhat32, p32, v32, t32, sc, partials, counter(c, C_XR));
+      bicg_step_f32(s, BI_P, vs32, x32, r32, rhat32, p32, v32, t32, sc, partials);
+      run_dslash(c, true, bv, dagger, EPI_RHAT, sc, partials);
+      bicg_step_f32(s, BI_S, vs32, x32, r32, rhat32, p32, v32, t32, sc, partials);
+      run_dslash(c, true, bt, dagger, EPI_TS, sc, partials);
+      bicg_step_f32(s, BI_XR, vs32, x32, r32, rhat32, p32, v32, t32, sc, partials);
     } else {
-      bicg_step_f64(s, BI_P, vs64, x64, r64, rhat, p, v, t, sc, partials, counter(c, C_XR));
-      run_dslash(c, false, bv, dagger, EPI_RHAT, sc, partials, C_RHAT);
-      bicg_step_f64(s, BI_S, vs64, x64, r64, rhat, p, v, t, sc, partials, counter(c, C_XR));
-      run_dslash(c, false, bt, dagger, EPI_TS, sc, partials, C_TS);
-      bicg_step_f64(s, BI_XR, vs64, x64, r64, rhat, p, v, t, sc, partials, counter(c, C_XR));
+      bicg_step_f64(s, BI_P, vs64, x64, r64, rhat, p, v, t, sc, partials);
+      run_dslash(c, false, bv, dagger, EPI_RHAT, sc, partials);
+      bicg_step_f64(s, BI_S, vs64, x64, r64, rhat, p, v, t, sc, partials);
+      run_dslash(c, false, bt, dagger, EPI_TS, sc, partials);
+      bicg_step_f64(s, BI_XR, vs64, x64, r64, rhat, p, v, t, sc, partials);
     }
   };
 
@@ -545,10 +543,9 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
     push();
     if (any) {
       if (mixed)
-        bicg_aux_f32(s, AX_RESTART, vs32, vs64, r64, r32, rhat32, p32, v32, x32, sc, partials,
-                     counter(c, C_AUX));
+        bicg_aux_f32(s, AX_RESTART, vs32, vs64, r64, r32, rhat32, p32, v32, x32, sc, partials);
       else
-        bicg_aux_f64(s, AX_RESTART, vs64, r64, r64, rhat, p, v, sc, partials, counter(c, C_AUX));
+        bicg_aux_f64(s, AX_RESTART, vs64, r64, r64, rhat, p, v, sc, partials);
     }
   };
   if (mixed) {
@@ -563,9 +560,8 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
     bres_dec.decide = 1;
     auto relup_dev = [&]() {
       bicg_xacc(s, vs32, vs64, x64, x32, sc);
-      run_dslash(c, false, bres_dec, dagger, EPI_RESID, sc, partials, C_RESID);
-      bicg_aux_f32(s, AX_REPLACE, vs32, vs64, r64, r32, rhat32, p32, v32, x32, sc, partials,
-                   counter(c, C_AUX));
+      run_dslash(c, false, bres_dec, dagger, EPI_RESID, sc, partials);
+      bicg_aux_f32(s, AX_REPLACE, vs32, vs64, r64, r32, rhat32, p32, v32, x32, sc, partials);
     };
     relup_dev();  // rhs whose starting residual already meets the tolerance
     int nchk = every;
@@ -666,7 +662,7 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
         for (int j : A) hs[j].sel = 1;
         push();
         if (mixed) bicg_xacc(s, vs32, vs64, x64, x32, sc);
-        run_dslash(c, false, bres, dagger, EPI_RESID, sc, partials, C_RESID);
+        run_dslash(c, false, bres, dagger, EPI_RESID, sc, partials);
         pull();
         bool any_rep = false;
         for (int j : A) {
@@ -693,10 +689,9 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
         push();
         if (any_rep) {
           if (mixed)
-            bicg_aux_f32(s, AX_REPLACE, vs32, vs64, r64, r32, rhat32, p32, v32, x32, sc, partials,
-                         counter(c, C_AUX));
+            bicg_aux_f32(s, AX_REPLACE, vs32, vs64, r64, r32, rhat32, p32, v32, x32, sc, partials);
           else
-            bicg_aux_f64(s, AX_REPLACE, vs64, rt, r64, rhat, p, v, sc, partials, counter(c, C_AUX));
+            bicg_aux_f64(s, AX_REPLACE, vs64, rt, r64, rhat, p, v, sc, partials);
         }
       }
       // (2) breakdowns: restart with rhat <- r
@@ -719,10 +714,9 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
         push();
         if (any) {
           if (mixed)
-            bicg_aux_f32(s, AX_RESTART, vs32, vs64, r64, r32, rhat32, p32, v32, x32, sc, partials,
-                         counter(c, C_AUX));
+            bicg_aux_f32(s, AX_RESTART, vs32, vs64, r64, r32, rhat32, p32, v32, x32, sc, partials);
           else
-            bicg_aux_f64(s, AX_RESTART, vs64, r64, r64, rhat, p, v, sc, partials, counter(c, C_AUX));
+            bicg_aux_f64(s, AX_RESTART, vs64, r64, r64, rhat, p, v, sc, partials);
         }
       }
       // (3) out of matrix-vector products
@@ -755,7 +749,7 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
   }
   push();
   if (need) {
-    run_dslash(c, false, bres, dagger, EPI_RESID, sc, partials, C_RESID);
+    run_dslash(c, false, bres, dagger, EPI_RESID, sc, partials);
     pull();
     for (int j = 0; j < NR; ++j)
       if (!have_true[j]) rrt[j] = hs[j].rr_true;
@@ -891,7 +885,7 @@ struct Arnoldi {
     hipStream_t s = c->stream;
     for (int j = j0; j < m; ++j) {
       const DsBatch b = make_batch({DsSpec{op, false, col(j), col(j + 1), nullptr, 1, 0}});
-      run_dslash(c, false, b, dagger, EPI_NONE, nullptr, nullptr, 0);
+      run_dslash(c, false, b, dagger, EPI_NONE, nullptr, nullptr);
       ++mv;
       double2* w = col(j + 1);
       gram_f64(s, Vb, n, j + 1, w, n, 1, n, V, 0, h1, gwork, gw);
@@ -965,7 +959,7 @@ int gmresdr(dbq_ctx* c, const dbq_operator* o, const void* b, void* x, int m, in
   // r0 -> v_1, c = ||r0|| e_1
   if (hp[1] > 0) {
     const DsBatch bb = make_batch({DsSpec{&op, false, x64, tmp, nullptr, 1, 0}});
-    run_dslash(c, false, bb, 0, EPI_NONE, nullptr, nullptr, 0);
+    run_dslash(c, false, bb, 0, EPI_NONE, nullptr, nullptr);
     sub_f64(s, b64, tmp, ar.col(0), n);
     ar.mv += 1;
   } else {
@@ -1009,7 +1003,7 @@ int gmresdr(dbq_ctx* c, const dbq_operator* o, const void* b, void* x, int m, in
   *k_out = kout;
   // true residual for the statistics (not charged as a matrix-vector product)
   const DsBatch bb = make_batch({DsSpec{&op, false, x64, tmp, nullptr, 1, 0}});
-  run_dslash(c, false, bb, 0, EPI_NONE, nullptr, nullptr, 0);
+  run_dslash(c, false, bb, 0, EPI_NONE, nullptr, nullptr);
   sub_f64(s, b64, tmp, tmp, n);
   norm2_f64(s, tmp, n, 1, n, dn + 2, ar.nwork, ar.nw);
   DBQ_HIP(hipMemcpyAsync(hp, dn + 2, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1096,10 +1090,10 @@ int mr_project(dbq_ctx* c, const dbq_operator* o, const void* Q, int nq, const v
   pack_spinor_f64(s, op.g, Q, Qp, nrhs * nq);
   // r0 = b - A x0, W = A Q
   const DsBatch bx = make_batch({DsSpec{&op, false, x64, r64, nullptr, nrhs, 0}});
-  run_dslash(c, false, bx, 0, EPI_NONE, nullptr, nullptr, 0);
+  run_dslash(c, false, bx, 0, EPI_NONE, nullptr, nullptr);
   sub_f64(s, b64, r64, r64, size_t(nrhs) * n);
   const DsBatch bq = make_batch({DsSpec{&op, false, Qp, W, nullptr, nrhs * nq, 0}});
-  run_dslash(c, false, bq, 0, EPI_NONE, nullptr, nullptr, 0);
+  run_dslash(c, false, bq, 0, EPI_NONE, nullptr, nullptr);
   const size_t gw = gram_work_elems(n, nq, 1);
   double* gwork = ws.get<double>(gw);
   const size_t nw = norm_work(n, nrhs);
