@@ -14,6 +14,9 @@ Modules:
   previous solutions for multiple shifts (Sec. 4).
 * ``oracle.kappa``   -- kappa_c from the rightmost eigenvalue of the hopping term (Sec. 3).
 * ``oracle.force``   -- gradient of Re(eta^H A^{-1} b) with respect to links and source.
+* ``oracle.evenodd`` -- the even-odd reduced system of Sec. 3 and Sec. 4: the Schur complement
+  Ahat = D - kappa^2 H_eo D^{-1} H_oe on the even sites, its source and the odd-site
+  reconstruction.
 
 Every function runs in complex128.  Pins (tests/test_oracle_*.py) check these functions against
 closed forms, dense linear algebra and exact invariants, never against themselves.
