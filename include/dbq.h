@@ -57,11 +57,24 @@ typedef enum {
   DBQ_MIXED = 1  /* FP32 vectors and 12-real links inside BiCGStab, FP64 reliable updates */
 } dbq_prec;
 
+/* Operator of a call.  schur selects the system the iteration runs on (Sec. 3 and Sec. 4 solve
+ * the even-odd preconditioned one):
+ *   0: the full operator A(mu) on all V sites;
+ *   1: the even-odd reduced operator, the Schur complement on the even sites
+ *        Ahat(mu) = D - kappa^2 H_eo D^{-1} H_oe,   D = I + i*mu*gamma5,
+ *      (H_eo: the hops from odd to even sites), dagger gamma5 Ahat(-mu) gamma5.  Vectors keep the
+ *      caller layout of all V sites: a solver is still handed b and returns x of A x = b (it
+ *      solves Ahat x_e = b_e + kappa H_eo D^{-1} b_o and sets x_o = D^{-1} (b_o + kappa H_oe x_e));
+ *      deflation vectors are even-site vectors stored as full vectors with zero odd sites;
+ *      wilson_apply writes Ahat in_e to the even sites of out and zero to the odd ones.  One
+ *      application of Ahat is one matrix-vector product.  Not accepted by link_force. */
 typedef struct {
   int32_t L[4];
   const void* links; /* device, complex128 [4][V][3][3] */
   double kappa;
   double mu;         /* twisted mass; 0 for plain Wilson */
+  int32_t schur;     /* 0: A; 1: the even-odd reduced operator (see above) */
+  int32_t pad;       /* must be 0 */
 } dbq_operator;
 
 typedef struct {
@@ -101,7 +114,8 @@ int dbq_geometry_host(const int32_t L[4], int32_t* lex_of_eo, int32_t* nbr);
 int dbq_site_tile(const int32_t L[4], int32_t* T);
 
 /* out = A(mu) in (dagger = 0) or A(mu)^dagger in (dagger = 1) for nrhs right-hand sides
- * (Sec. 1 operator; the matrix-vector product every solver in the paper is costed in).
+ * (Sec. 1 operator; the matrix-vector product every solver in the paper is costed in); with
+ * op->schur = 1, out_e = Ahat in_e (or its dagger) and out_o = 0.
  * in, out: DEVICE complex128 [nrhs][V][12], must not overlap.  prec = DBQ_MIXED computes in
  * FP32 with 12-real links and returns the FP32 result widened to complex128. */
 int wilson_apply(dbq_ctx* ctx, const dbq_operator* op, const void* in, void* out,
@@ -116,6 +130,8 @@ int wilson_apply(dbq_ctx* ctx, const dbq_operator* op, const void* in, void* out
  * k_out: HOST, the number of columns returned (k, or k-1 when the k-th and (k+1)-th values are a
  * complex-conjugate pair, which would make the left-right projection singular).
  * Returns DBQ_NOT_CONVERGED when max_mv is reached first; V_out and theta are still written.
+ * With op->schur = 1 the Krylov space and V_out are those of Ahat (even sites; odd sites of V_out
+ * are zero), tol is relative to ||b|| of the full system, and x is the full solution.
  * Requires 2 <= k < m <= 128. */
 int gmresdr_first_rhs(dbq_ctx* ctx, const dbq_operator* op, const void* b, void* x,
                       int32_t m, int32_t k, double tol, int64_t max_mv,
@@ -128,6 +144,10 @@ int gmresdr_first_rhs(dbq_ctx* ctx, const dbq_operator* op, const void* b, void*
  * V[i]: DEVICE complex128 column-major n_i x k[i] (k[i] = 0: no deflation, plain BiCGStab).
  * B[i]: DEVICE complex128 [nrhs[i]][V_i][12]; X[i]: same shape, in: x0, out: solution.
  * per_rhs: HOST array of sum(nrhs) stats, in operator order.  prec: dbq_prec.
+ * With schur = 1 (the same for every operator of the call) V[i] holds eigenvectors of Ahat as
+ * full vectors with zero odd sites (as gmresdr_first_rhs returns them), the iteration runs on
+ * Ahat, and X[i] receives the full solution; rel_true_resid is ||bhat - Ahat x_e|| / ||b||, which
+ * equals ||b - A x|| / ||b|| up to the rounding of the odd-site reconstruction.
  * Returns the worst status over all right-hand sides (an error status if any, else
  * DBQ_NOT_CONVERGED if any did not converge). */
 int dbicgstab_solve(dbq_ctx* ctx, const dbq_operator* ops, int32_t nops,
@@ -141,7 +161,10 @@ int dbicgstab_solve(dbq_ctx* ctx, const dbq_operator* ops, int32_t nops,
  * through a QR factorisation of W = A_new Q_j (classical Gram-Schmidt twice) so cond(W) is not
  * squared.  Q: DEVICE complex128 [nrhs][nq][V][12]; B, X0: DEVICE complex128 [nrhs][V][12] (X0
  * in/out); rnorm_before_after: HOST double [2*nrhs] = ||r0||, ||r_new|| per rhs.
- * Costs (1 if x0 != 0) + nq matrix-vector products per rhs.  1 <= nq <= 32. */
+ * Costs (1 if x0 != 0) + nq matrix-vector products per rhs.  1 <= nq <= 32.
+ * With op_new->schur = 1 the projection is done on the reduced system of op_new (r0 = bhat -
+ * Ahat x0_e over the even parts of Q) and X0 receives the full vector with its odd sites
+ * reconstructed; the norms are those of the reduced residuals. */
 int project_shifts(dbq_ctx* ctx, const dbq_operator* op_new, const void* Q, int32_t nq,
                    const void* B, void* X0, int32_t nrhs, double* rnorm_before_after);
 
@@ -151,7 +174,8 @@ int project_shifts(dbq_ctx* ctx, const dbq_operator* op_new, const void* Q, int3
  * lambda, x: DEVICE complex128 [nrhs][V][12].
  * kind 0: F = DEVICE double [4][V][8], F[mu][y][a] = Re(i tr[T_a U_mu(y) G_mu(y)^H]), T_a = Gell-Mann/2,
  *         the derivative along U -> exp(i theta T_a) U.
- * kind 1: F = DEVICE complex128 [4][V][3][3] = G itself (dL = Re sum conj(G) dU). */
+ * kind 1: F = DEVICE complex128 [4][V][3][3] = G itself (dL = Re sum conj(G) dU).
+ * op->schur must be 0. */
 int link_force(dbq_ctx* ctx, const dbq_operator* op, const void* lambda, const void* x,
                int32_t nrhs, int32_t kind, void* F);
 

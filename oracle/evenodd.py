@@ -27,7 +27,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .wilson import gamma5, hopping
+from .wilson import gamma5, hopping, hopping_sites
 
 
 def parity_sites(lat, parity):
@@ -93,6 +93,23 @@ def schur_reconstruct(U, lat, kappa, xe, b, mu=0.0, dagger=False):
     xo = restrict(lat, b, 1) + kappa * _hop_half(U, lat, xe, 0, dagger)
     xo = _diag(xo, m, inverse=True).reshape(-1)
     return embed(lat, xe, 0) + embed(lat, xo, 1)
+
+
+def schur_apply_sites(U, lat, kappa, xe, sites, mu=0.0, dagger=False):
+    """(Ahat x_e)(x) at a list of even lexicographic sites only (for large lattices): the odd
+    neighbours' D^{-1} (H x_e), then the hop of those back to the sites.  Returns
+    (len(sites), 4, 3)."""
+    sites = np.asarray(sites, dtype=np.int64)
+    if np.any(lat.parity[sites] != 0):
+        raise ValueError("sites must be even")
+    m = -mu if dagger else mu
+    full = embed(lat, xe, 0)
+    nbr = np.unique(np.concatenate([lat.fwd[d][sites] for d in range(4)] +
+                                   [lat.bwd[d][sites] for d in range(4)]))
+    t = np.zeros((lat.V, 4, 3), dtype=np.complex128)
+    t[nbr] = _diag(hopping_sites(U, full, lat, nbr, dagger), m, inverse=True)
+    u = hopping_sites(U, t, lat, sites, dagger)
+    return _diag(full[sites], m, inverse=False) - kappa * kappa * u
 
 
 def gamma5_half(x):

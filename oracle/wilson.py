@@ -195,11 +195,10 @@ def gamma5_flat(x, V):
 
 
 # --------------------------------------------------------------------------- sampled apply
-def apply_A_sites(U, psi, lat, kappa, sites, mu=0.0, dagger=False):
-    """(A psi)(x) at a list of lexicographic sites only: lets large-lattice GPU outputs be
-    checked one site at a time.  Returns (len(sites), 4, 3)."""
-    V = lat.V
-    p = _as_sites(psi, V)
+def hopping_sites(U, psi, lat, sites, dagger=False):
+    """(H psi)(x) (``dagger``: H^dagger) at a list of lexicographic sites only.
+    Returns (len(sites), 4, 3)."""
+    p = _as_sites(psi, lat.V)
     sites = np.asarray(sites, dtype=np.int64)
     acc = np.zeros((len(sites), 4, 3), dtype=np.complex128)
     for mu_ in range(4):
@@ -213,6 +212,15 @@ def apply_A_sites(U, psi, lat, kappa, sites, mu=0.0, dagger=False):
         acc += np.einsum("st,xta->xsa", Pf, t)
         t = np.einsum("xba,xsb->xsa", np.conj(U[mu_][b]), p[b])
         acc += np.einsum("st,xta->xsa", Pb, t)
+    return acc
+
+
+def apply_A_sites(U, psi, lat, kappa, sites, mu=0.0, dagger=False):
+    """(A psi)(x) at a list of lexicographic sites only: lets large-lattice GPU outputs be
+    checked one site at a time.  Returns (len(sites), 4, 3)."""
+    p = _as_sites(psi, lat.V)
+    sites = np.asarray(sites, dtype=np.int64)
+    acc = hopping_sites(U, p, lat, sites, dagger)
     m = -mu if dagger else mu
     ps = p[sites]
     return ps - kappa * acc + 1j * m * np.einsum("st,xta->xsa", GAMMA5, ps)

@@ -103,13 +103,15 @@ def _spinors(x, V, name):
     return x.reshape(-1, V, 4, 3)
 
 
-def _operator(L, U, kappa, mu):
+def _operator(L, U, kappa, mu, schur=False):
     op = Operator()
     for i in range(4):
         op.L[i] = L[i]
     op.links = ctypes.c_void_p(U.data_ptr())
     op.kappa = float(kappa)
     op.mu = float(mu)
+    op.schur = 1 if schur else 0
+    op.pad = 0
     return op
 
 
@@ -122,8 +124,9 @@ def _prec(prec):
 
 
 # ----------------------------------------------------------------------------- entry points
-def wilson_apply(L, links, psi, kappa, mu=0.0, dagger=False, prec="fp64"):
-    """A(mu) psi (or A(mu)^dagger psi) for one or many right-hand sides; returns psi's shape."""
+def wilson_apply(L, links, psi, kappa, mu=0.0, dagger=False, prec="fp64", schur=False):
+    """A(mu) psi (or A(mu)^dagger psi) for one or many right-hand sides; returns psi's shape.
+    With ``schur`` the even-odd reduced operator: out_e = Ahat psi_e, out_o = 0."""
     torch = _torch()
     L, V = _lattice(L)
     U = _links(links, V)
@@ -132,17 +135,20 @@ def wilson_apply(L, links, psi, kappa, mu=0.0, dagger=False, prec="fp64"):
         raise ValueError("psi and links must be on the same device")
     out = torch.empty_like(p)
     h = _ctx(U.device)
-    op = _operator(L, U, kappa, mu)
+    op = _operator(L, U, kappa, mu, schur)
     st = _abi.load().wilson_apply(h, ctypes.byref(op), p.data_ptr(), out.data_ptr(), p.shape[0],
                                   int(bool(dagger)), _prec(prec))
     _check(st, h, ok=(0,))
     return out.reshape(psi.shape)
 
 
-def gmresdr_first_rhs(L, links, b, kappa, m, k, mu=0.0, tol=1e-8, max_mv=20000, x0=None):
+def gmresdr_first_rhs(L, links, b, kappa, m, k, mu=0.0, tol=1e-8, max_mv=20000, x0=None,
+                      schur=False):
     """GMRES-DR(m,k) on one right-hand side.  Returns (x, V, theta, stats): x like b, V complex128
     (k_out, V, 4, 3) holding the orthonormal columns of the n x k_out eigenvector basis, theta a
-    numpy complex array of the k_out harmonic Ritz values, stats a dict."""
+    numpy complex array of the k_out harmonic Ritz values, stats a dict.  With ``schur`` the
+    iteration runs on the even-odd reduced operator (V: its eigenvectors on the even sites, zero
+    on the odd ones) and x is still the full solution."""
     torch = _torch()
     L, Vol = _lattice(L)
     U = _links(links, Vol)
@@ -159,7 +165,7 @@ def gmresdr_first_rhs(L, links, b, kappa, m, k, mu=0.0, tol=1e-8, max_mv=20000, 
     kout = ctypes.c_int32(0)
     stats = Stats()
     h = _ctx(U.device)
-    op = _operator(L, U, kappa, mu)
+    op = _operator(L, U, kappa, mu, schur)
     st = _abi.load().gmresdr_first_rhs(h, ctypes.byref(op), bb.data_ptr(), x.data_ptr(), int(m),
                                        int(k), float(tol), int(max_mv), Vout.data_ptr(), theta,
                                        ctypes.byref(kout), ctypes.byref(stats))
@@ -173,7 +179,9 @@ def dbicgstab_solve(problems, tol=1e-8, max_mv=20000, prec="mixed", dagger=False
     """D-BiCGStab(k) over a batch of (possibly different-size) lattices in one call.
 
     problems: list (1..8) of dicts with keys L, links, kappa, mu (default 0), B (nrhs, V, 4, 3),
-    V (k, V, 4, 3) deflation vectors or None, X0 (like B) or None.
+    V (k, V, 4, 3) deflation vectors or None, X0 (like B) or None, schur (default False: the
+    even-odd reduced operator, the same for every problem; V then from
+    ``gmresdr_first_rhs(..., schur=True)``).
     Returns (X list, per-rhs stats list, overall status)."""
     torch = _torch()
     if not (1 <= len(problems) <= 8):
@@ -211,7 +219,7 @@ def dbicgstab_solve(problems, tol=1e-8, max_mv=20000, prec="mixed", dagger=False
         for t in (B, X) + ((Vd,) if Vd is not None else ()):
             if t.device != dev:
                 raise ValueError("all tensors must be on the links' device")
-        ops[i] = _operator(L, U, pr["kappa"], pr.get("mu", 0.0))
+        ops[i] = _operator(L, U, pr["kappa"], pr.get("mu", 0.0), pr.get("schur", False))
         Bp[i] = B.data_ptr()
         Xp[i] = X.data_ptr()
         nr[i] = B.shape[0]
@@ -227,9 +235,10 @@ def dbicgstab_solve(problems, tol=1e-8, max_mv=20000, prec="mixed", dagger=False
     return out, [s.as_dict() for s in stats], st
 
 
-def project_shifts(L, links, kappa, mu, Q, B, X0=None):
+def project_shifts(L, links, kappa, mu, Q, B, X0=None, schur=False):
     """Minimal-residual projection over previous solutions: Q (nrhs, nq, V, 4, 3), B (nrhs, V, 4, 3).
-    Returns (X0_new, rnorm_before (nrhs,), rnorm_after (nrhs,))."""
+    Returns (X0_new, rnorm_before (nrhs,), rnorm_after (nrhs,)).  With ``schur`` on the even-odd
+    reduced system (X0_new full, its odd sites reconstructed)."""
     torch = _torch()
     L, Vol = _lattice(L)
     U = _links(links, Vol)
@@ -246,7 +255,7 @@ def project_shifts(L, links, kappa, mu, Q, B, X0=None):
         raise ValueError("X0 must match B")
     rn = (ctypes.c_double * (2 * nrhs))()
     h = _ctx(U.device)
-    op = _operator(L, U, kappa, mu)
+    op = _operator(L, U, kappa, mu, schur)
     st = _abi.load().project_shifts(h, ctypes.byref(op), Qt.data_ptr(), nq, Bt.data_ptr(),
                                     X.data_ptr(), nrhs, rn)
     _check(st, h, ok=(0,))

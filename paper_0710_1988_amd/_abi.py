@@ -25,7 +25,8 @@ EXPORTED = ["dbq_create", "dbq_destroy", "dbq_last_error", "dbq_set_stream", "db
 
 class Operator(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32 * 4), ("links", ctypes.c_void_p),
-                ("kappa", ctypes.c_double), ("mu", ctypes.c_double)]
+                ("kappa", ctypes.c_double), ("mu", ctypes.c_double),
+                ("schur", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

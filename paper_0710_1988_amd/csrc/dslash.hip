@@ -234,18 +234,21 @@ __device__ __forceinline__ void spread(cx<T> (&acc)[12], const cx<T> (&chi)[6]) 
 }
 
 // One hop for NB right-hand sides: BACK = false -> (1 + S gamma) U_mu(x) psi(x+mu);
-// BACK = true -> (1 + S gamma) U_mu(y)^dag psi(y) with y = x - mu.
+// BACK = true -> (1 + S gamma) U_mu(y)^dag psi(y) with y = x - mu.  The link is read at site
+// site_link of the full link field (V sites per component); the spinor at index ys of vectors
+// with Vs sites per component (Vs = V, or V/2 for the half vectors of the even-odd reduced
+// operator).
 template <typename T, int MU, int S, bool BACK, int NB>
 __device__ __forceinline__ void hop(const typename IO<T>::SE* __restrict__ in, long long rstride,
                                     int nval, const typename IO<T>::LE* __restrict__ U, int V,
-                                    int site_link, int y, cx<T> (&acc)[NB][12]) {
+                                    int site_link, int Vs, int ys, cx<T> (&acc)[NB][12]) {
   cx<T> u[9];
   IO<T>::link(U, V, MU, site_link, u);
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     if (NB > 1 && j >= nval) break;
     cx<T> p[12];
-    IO<T>::load(in + j * rstride, V, y, p);
+    IO<T>::load(in + j * rstride, Vs, ys, p);
     cx<T> h[6];
     project<T, MU, S>(p, h);
     cx<T> chi[6];
@@ -266,18 +269,22 @@ __device__ __forceinline__ void hop(const typename IO<T>::SE* __restrict__ in, l
   }
 }
 
+// Both hops in direction MU of the site with coordinates c and internal index s; the input
+// spinors have Vs sites per component and a neighbour with internal index y sits at y - off
+// (off = V/2 for odd-site half vectors, 0 otherwise).
 template <typename T, bool DAG, int MU, int NB>
 __device__ __forceinline__ void hops_mu(const typename IO<T>::SE* __restrict__ in,
                                         long long rstride, int nval,
                                         const typename IO<T>::LE* __restrict__ U, const Geom& g,
-                                        int s, const int (&c)[4], cx<T> (&acc)[NB][12]) {
+                                        int s, const int (&c)[4], cx<T> (&acc)[NB][12],
+                                        int Vs, int off) {
   // forward hop uses (1 - gamma) (dagger: 1 + gamma), backward the opposite
   constexpr int SF = DAG ? +1 : -1;
   constexpr int SB = -SF;
   const int yf = eo_neighbour<MU, +1>(g, c);
   const int yb = eo_neighbour<MU, -1>(g, c);
-  hop<T, MU, SF, false, NB>(in, rstride, nval, U, g.V, s, yf, acc);
-  hop<T, MU, SB, true, NB>(in, rstride, nval, U, g.V, yb, yb, acc);
+  hop<T, MU, SF, false, NB>(in, rstride, nval, U, g.V, s, Vs, yf - off, acc);
+  hop<T, MU, SB, true, NB>(in, rstride, nval, U, g.V, yb, Vs, yb - off, acc);
 }
 
 __device__ __forceinline__ bool finite_d(double v) { return isfinite(v); }
@@ -517,13 +524,13 @@ void k_dslash(DsBatch B, RhsScal* __restrict__ sc, double* __restrict__ partials
 #pragma unroll
       for (int k = 0; k < 12; ++k) acc[j][k] = cx<T>{T(0), T(0)};
     int sl = s;  // link site of the forward hops, chained like the coordinates
-    hops_mu<T, DAG, 0, NB>(in, rstride, nval, U, L.g, sl, c, acc);
+    hops_mu<T, DAG, 0, NB>(in, rstride, nval, U, L.g, sl, c, acc, V, 0);
     chain(c, sl, acc);
-    hops_mu<T, DAG, 1, NB>(in, rstride, nval, U, L.g, sl, c, acc);
+    hops_mu<T, DAG, 1, NB>(in, rstride, nval, U, L.g, sl, c, acc, V, 0);
     chain(c, sl, acc);
-    hops_mu<T, DAG, 2, NB>(in, rstride, nval, U, L.g, sl, c, acc);
+    hops_mu<T, DAG, 2, NB>(in, rstride, nval, U, L.g, sl, c, acc, V, 0);
     chain(c, sl, acc);
-    hops_mu<T, DAG, 3, NB>(in, rstride, nval, U, L.g, sl, c, acc);
+    hops_mu<T, DAG, 3, NB>(in, rstride, nval, U, L.g, sl, c, acc, V, 0);
     const T kap = T(L.kappa);
     const T tm = T(DAG ? -L.mu : L.mu);
 #pragma unroll
@@ -538,6 +545,132 @@ void k_dslash(DsBatch B, RhsScal* __restrict__ sc, double* __restrict__ partials
       finish_site<T, EPI>(psi, acc[j], kap, tm, ax, red[3 * j], red[3 * j + 1], red[3 * j + 2],
                           o);
       IO<T>::store(out + j * rstride, V, s, o);
+    }
+  }
+  if (EPI != EPI_NONE) {
+    __shared__ double sh[NB * 3 * (DS_BS / 64)];
+    block_sum<NB * 3, DS_BS>(red, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (j >= nval) break;
+        double* pp = partials + ((long long)(L.rhs_base + r0 + j) * B.pstride + sb) * 3;
+        pp[0] = red[3 * j];
+        pp[1] = red[3 * j + 1];
+        pp[2] = red[3 * j + 2];
+      }
+    }
+  }
+}
+
+// ============================================================================ even-odd halves
+// The even-odd reduced operator of Sec. 3 and Sec. 4 on half vectors (the sites of one parity,
+// [rhs][component][V/2] in the internal order minus the parity offset), as two launches of one
+// kernel that computes the sites of one parity from the hop of the other parity's vector:
+//   STEP 1 (odd sites):  out = D^{-1} (cen + c H_oe in),         D^{-1} = (1 - i t gamma5)/(1 + t^2)
+//   STEP 2 (even sites): out = D cen - c H_eo in  (+ epilogue),  D = 1 + i t gamma5
+// with c = L.kappa and t = L.mu (-mu for the dagger, whose hops use H^dagger).  cen may be null
+// in STEP 1 (read as zero); c = 0 skips the hops.  The Schur complement
+// Ahat = D - kappa^2 H_eo D^{-1} H_oe is STEP 1 (c = 1, no cen) followed by STEP 2 (c = kappa^2,
+// cen = the vector Ahat is applied to); the same kernel forms the reduced right-hand side and
+// the odd half of the solution.  The epilogues are those of the full operator.
+// STEP 1's result D^{-1} (cen + c acc)
+template <typename T>
+__device__ __forceinline__ void finish_odd(const cx<T> (&cen)[12], const cx<T> (&acc)[12], T c,
+                                           T tm, cx<T> (&o)[12]) {
+  const T inv = T(1) / fma(tm, tm, T(1));
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const T t = k < 6 ? tm : -tm;
+    const T wr = fma(c, acc[k].re, cen[k].re);
+    const T wi = fma(c, acc[k].im, cen[k].im);
+    // (1 - i t) (wr + i wi) = (wr + t wi) + i (wi - t wr)
+    o[k].re = fma(t, wi, wr) * inv;
+    o[k].im = fma(-t, wr, wi) * inv;
+  }
+}
+
+template <typename T, bool DAG, int EPI, int NB, int STEP>
+__global__ __launch_bounds__(DS_BS) DBQ_DS_ATTR
+void k_dslash_half(DsBatch B, RhsScal* __restrict__ sc, double* __restrict__ partials, int gate) {
+  typedef typename IO<T>::SE SE;
+  typedef typename IO<T>::LE LE;
+  constexpr int NSE = IO<T>::NSE;
+  constexpr int P = STEP == 1 ? 1 : 0;  // parity of the output sites
+  const int lb = xcd_block(blockIdx.x, B.nblocks);
+  int l = 0;
+#pragma unroll
+  for (int i = 1; i < MAXLAT; ++i)
+    if (i < B.nlat && lb >= B.lat[i].blk_begin) l = i;
+  const DsLat& L = B.lat[l];
+  const int ng = (L.nrhs + NB - 1) / NB;
+  const int loc = lb - L.blk_begin;
+  // block order as in k_dslash: chunks of G rhs groups, site blocks, rhs groups of a chunk
+  const int G = (B.rgroup <= 0 || B.rgroup > ng) ? ng : B.rgroup;
+  const int chunk = loc / (L.nsb * G);
+  const int rem = loc - chunk * (L.nsb * G);
+  const int Gc = min(G, ng - chunk * G);
+  const int sb = rem / Gc;
+  const int r0 = (chunk * G + (rem - sb * Gc)) * NB;
+  const int nval = min(NB, L.nrhs - r0);
+  const int Vh = L.g.V >> 1;
+  const long long rstride = (long long)NSE * Vh;
+  bool act[NB];
+  bool any = false;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    bool a = j < nval;
+    if (a && gate == 1) a = sc[L.rhs_base + r0 + j].active != 0;
+    else if (a && gate == 2) a = sc[L.rhs_base + r0 + j].sel != 0;
+    act[j] = a;
+    any = any || a;
+  }
+  const int h = sb * DS_BS + threadIdx.x;
+  double red[NB * 3];
+#pragma unroll
+  for (int i = 0; i < NB * 3; ++i) red[i] = 0.0;
+  if (any && h < Vh) {
+    const SE* in = (const SE*)L.in + r0 * rstride;
+    SE* out = (SE*)L.out + r0 * rstride;
+    const LE* U = (const LE*)L.links;
+    const int s = P * Vh + h;
+    int c[4], p;
+    eo_coords(L.g, s, c, p);
+    cx<T> acc[NB][12];
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) acc[j][k] = cx<T>{T(0), T(0)};
+    const T coef = T(L.kappa);
+    if (coef != T(0)) {
+      const int off = (1 - P) * Vh;  // neighbours have the other parity
+      hops_mu<T, DAG, 0, NB>(in, rstride, nval, U, L.g, s, c, acc, Vh, off);
+      hops_mu<T, DAG, 1, NB>(in, rstride, nval, U, L.g, s, c, acc, Vh, off);
+      hops_mu<T, DAG, 2, NB>(in, rstride, nval, U, L.g, s, c, acc, Vh, off);
+      hops_mu<T, DAG, 3, NB>(in, rstride, nval, U, L.g, s, c, acc, Vh, off);
+    }
+    const T tm = T(DAG ? -L.mu : L.mu);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      if (!act[j]) continue;
+      cx<T> ce[12];
+      if (L.cen) {
+        IO<T>::load((const SE*)L.cen + (r0 + j) * rstride, Vh, h, ce);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) ce[k] = cx<T>{T(0), T(0)};
+      }
+      cx<T> o[12];
+      if (STEP == 1) {
+        finish_odd<T>(ce, acc[j], coef, tm, o);
+      } else {
+        cx<T> ax[12];
+        if (EPI == EPI_RHAT || EPI == EPI_RESID)
+          IO<T>::load((const SE*)L.aux + (r0 + j) * rstride, Vh, h, ax);
+        finish_site<T, EPI>(ce, acc[j], coef, tm, ax, red[3 * j], red[3 * j + 1],
+                            red[3 * j + 2], o);
+      }
+      IO<T>::store(out + j * rstride, Vh, h, o);
     }
   }
   if (EPI != EPI_NONE) {
@@ -965,6 +1098,64 @@ double launch(hipStream_t s, DsBatch& b, int dagger, int epi, RhsScal* sc, doubl
   return bytes;
 }
 
+template <typename T, bool DAG, int NB, int STEP>
+void launch_half_epi(hipStream_t s, const DsBatch& b, int epi, RhsScal* sc, double* partials,
+                     int gate) {
+  dim3 grid(b.nblocks), block(DS_BS);
+  switch (epi) {
+    case EPI_NONE: hipLaunchKernelGGL((k_dslash_half<T, DAG, EPI_NONE, NB, STEP>), grid, block, 0, s, b, sc, partials, gate); break;
+    case EPI_RHAT: hipLaunchKernelGGL((k_dslash_half<T, DAG, EPI_RHAT, NB, STEP>), grid, block, 0, s, b, sc, partials, gate); break;
+    case EPI_TS: hipLaunchKernelGGL((k_dslash_half<T, DAG, EPI_TS, NB, STEP>), grid, block, 0, s, b, sc, partials, gate); break;
+    default: hipLaunchKernelGGL((k_dslash_half<T, DAG, EPI_RESID, NB, STEP>), grid, block, 0, s, b, sc, partials, gate); break;
+  }
+}
+
+template <typename T, bool DAG, int NB>
+void launch_half_step(hipStream_t s, const DsBatch& b, int step, int epi, RhsScal* sc,
+                      double* partials, int gate) {
+  if (step == 1) {
+    dim3 grid(b.nblocks), block(DS_BS);
+    hipLaunchKernelGGL((k_dslash_half<T, DAG, EPI_NONE, NB, 1>), grid, block, 0, s, b, sc, partials, gate);
+  } else {
+    launch_half_epi<T, DAG, NB, 2>(s, b, epi, sc, partials, gate);
+  }
+}
+
+template <typename T>
+void launch_half(hipStream_t s, DsBatch& b, int step, int dagger, int epi, RhsScal* sc,
+                 double* partials, int nb, int rgroup, int gate) {
+  DBQ_CHECK(b.nlat >= 1 && b.nlat <= MAXLAT, "dslash (half): bad lattice count");
+  DBQ_CHECK(step == 1 || step == 2, "dslash (half): step must be 1 or 2");
+  DBQ_CHECK(step == 2 || epi == EPI_NONE, "dslash (half): epilogues follow step 2");
+  DBQ_CHECK(epi == EPI_NONE || (sc && partials), "dslash (half): epilogue needs scalars");
+  DBQ_CHECK(gate == 0 || sc, "dslash (half): gating needs scalars");
+  DBQ_CHECK(nb == 1 || nb == 2, "dslash (half): rhs per thread must be 1 or 2");
+  b.nb = nb;
+  b.rgroup = rgroup;
+  long long blk = 0;
+  for (int i = 0; i < b.nlat; ++i) {
+    DsLat& L = b.lat[i];
+    DBQ_CHECK(L.g.V % 2 == 0, "dslash (half): odd volume");
+    DBQ_CHECK(L.in && L.out, "dslash (half): null vector");
+    DBQ_CHECK(step == 2 || epi == EPI_NONE, "dslash (half): bad epilogue");
+    DBQ_CHECK(!((epi == EPI_RHAT || epi == EPI_RESID) && !L.aux), "dslash (half): null aux");
+    L.blk_begin = int(blk);
+    L.nsb = (L.g.V / 2 + DS_BS - 1) / DS_BS;
+    blk += (long long)L.nsb * ((L.nrhs + nb - 1) / nb);
+    DBQ_CHECK(epi == EPI_NONE || L.nsb <= b.pstride, "dslash (half): partial-sum slots too few");
+  }
+  DBQ_CHECK(blk > 0 && blk < (1ll << 31), "dslash (half): grid size out of range");
+  b.nblocks = int(blk);
+  if (dagger) {
+    if (nb == 2) launch_half_step<T, true, 2>(s, b, step, epi, sc, partials, gate);
+    else launch_half_step<T, true, 1>(s, b, step, epi, sc, partials, gate);
+  } else {
+    if (nb == 2) launch_half_step<T, false, 2>(s, b, step, epi, sc, partials, gate);
+    else launch_half_step<T, false, 1>(s, b, step, epi, sc, partials, gate);
+  }
+  DBQ_HIP(hipGetLastError());
+}
+
 }  // namespace
 
 void launch_ds_finalize(hipStream_t s, const DsBatch& b, int epi, RhsScal* sc,
@@ -990,6 +1181,15 @@ double launch_dslash_f64(hipStream_t s, DsBatch& b, int dagger, int epi, RhsScal
 double launch_dslash_f32(hipStream_t s, DsBatch& b, int dagger, int epi, RhsScal* sc,
                          double* partials, int nb, int rgroup) {
   return launch<float>(s, b, dagger, epi, sc, partials, nb, rgroup);
+}
+
+void launch_dslash_half_f64(hipStream_t s, DsBatch& b, int step, int dagger, int epi,
+                            RhsScal* sc, double* partials, int nb, int rgroup, int gate) {
+  launch_half<double>(s, b, step, dagger, epi, sc, partials, nb, rgroup, gate);
+}
+void launch_dslash_half_f32(hipStream_t s, DsBatch& b, int step, int dagger, int epi,
+                            RhsScal* sc, double* partials, int nb, int rgroup, int gate) {
+  launch_half<float>(s, b, step, dagger, epi, sc, partials, nb, rgroup, gate);
 }
 
 }  // namespace dbq

@@ -64,6 +64,7 @@ struct DsLat {
   const void* in;   // [nrhs][.][V]
   void* out;
   const void* aux;  // epilogue input with the layout of `in` (rhat, b) or null
+  const void* cen;  // half-lattice kernels: the output parity's own input, or null
   int nrhs;
   int rhs_base;     // global rhs index of this lattice's first rhs
   int nsb;          // site blocks per rhs
@@ -93,6 +94,7 @@ struct DsBatch {
   int rgroup;      // thread rhs-groups sharing a sweep over the site blocks, set by the launcher
   DsAcct acct;     // zero unless the caller accounts bytes of a gated launch
   int decide;      // RESID finalize also decides convergence / replacement (device loop)
+  int schur;       // the lattices' operator is the even-odd reduced one (half vectors)
 };
 
 enum Epi : int { EPI_NONE = 0, EPI_RHAT = 1, EPI_TS = 2, EPI_RESID = 3 };
@@ -134,6 +136,15 @@ double launch_dslash_f64(hipStream_t s, DsBatch& b, int dagger, int epi, RhsScal
                          double* partials, int nb, int rgroup);
 double launch_dslash_f32(hipStream_t s, DsBatch& b, int dagger, int epi, RhsScal* sc,
                          double* partials, int nb, int rgroup);
+// Half-lattice kernels of the even-odd reduced operator on half vectors [rhs][.][V/2] (the sites
+// of one parity): step 1 computes the odd sites, out = D^{-1} (cen + c H_oe in); step 2 the even
+// ones, out = D cen - c H_eo in followed by the epilogue; c = lat.kappa, D = 1 + i t gamma5 with
+// t = lat.mu (-mu for the dagger, whose hops are those of H^dagger); cen may be null in step 1.
+// gate: 0 = every rhs, 1 = the active ones, 2 = the selected ones (needs sc).
+void launch_dslash_half_f64(hipStream_t s, DsBatch& b, int step, int dagger, int epi,
+                            RhsScal* sc, double* partials, int nb, int rgroup, int gate);
+void launch_dslash_half_f32(hipStream_t s, DsBatch& b, int step, int dagger, int epi,
+                            RhsScal* sc, double* partials, int nb, int rgroup, int gate);
 // partial-sum slots per rhs that every launch shape of the Dslash needs for a lattice
 inline int ds_partial_slots(const Geom& g) {
   return std::max(2 * ((g.Vh + DS_BS - 1) / DS_BS), g.V >> (g.lTh + 1));

@@ -22,9 +22,13 @@ namespace {
 struct Op {
   Geom g;
   double kappa = 0, mu = 0;
+  bool schur = false;  // the even-odd reduced operator on the even sites
   double2* l64 = nullptr;
   float4* l32 = nullptr;
-  long long n() const { return 12LL * g.V; }
+  // sites and complex elements of the vectors the solvers iterate on
+  long long sites() const { return schur ? g.V / 2 : g.V; }
+  long long n() const { return 12LL * sites(); }
+  long long nfull() const { return 12LL * g.V; }
 };
 
 void check_op(const dbq_operator* o) {
@@ -38,6 +42,8 @@ void check_op(const dbq_operator* o) {
   DBQ_CHECK(V <= (1ll << 26), "lattice too large (V > 2^26)");
   DBQ_CHECK(o->links != nullptr, "null links");
   DBQ_CHECK(std::isfinite(o->kappa) && std::isfinite(o->mu), "non-finite kappa or mu");
+  DBQ_CHECK(o->schur == 0 || o->schur == 1, "schur must be 0 or 1");
+  DBQ_CHECK(o->pad == 0, "operator pad field must be 0");
 }
 
 Op make_op(dbq_ctx* c, WsScope& ws, const dbq_operator* o, bool f64, bool f32) {
@@ -45,6 +51,7 @@ Op make_op(dbq_ctx* c, WsScope& ws, const dbq_operator* o, bool f64, bool f32) {
   op.g = make_geom(o->L);
   op.kappa = o->kappa;
   op.mu = o->mu;
+  op.schur = o->schur != 0;
   if (f64) {
     op.l64 = ws.get<double2>(36LL * op.g.V);
     pack_links_f64(c->stream, op.g, o->links, op.l64);
@@ -79,6 +86,7 @@ DsBatch make_batch(const std::vector<DsSpec>& v) {
     L.in = v[i].in;
     L.out = v[i].out;
     L.aux = v[i].aux;
+    L.cen = nullptr;
     L.nrhs = v[i].nrhs;
     L.rhs_base = v[i].rhs_base;
     // site blocks (set again by the launcher for the launch shape it uses)
@@ -88,7 +96,9 @@ DsBatch make_batch(const std::vector<DsSpec>& v) {
     L.mu = v[i].op->mu;
     nr = std::max(nr, L.rhs_base + L.nrhs);
     ps = std::max(ps, ds_partial_slots(L.g));
+    DBQ_CHECK(v[i].op->schur == v[0].op->schur, "batch: mixed full and reduced operators");
   }
+  b.schur = v[0].op->schur ? 1 : 0;
   b.nblocks = 0;
   b.nb = 1;
   b.nrhs_total = nr;
@@ -173,8 +183,119 @@ std::pair<int, int> choose_shape(dbq_ctx* c, bool f32, const DsBatch& b) {
   return best;
 }
 
+// Launch shape (nb, rg) of the half-lattice kernels for a batch of the reduced operator: nb = 1
+// or 2 rhs per thread, rg as for the site kernel; timed once per (precision, volume, batch size)
+// on step 1 into a scratch output.  DBQ_DS_NB / DBQ_DS_RG force the values (nb clamped to 1, 2).
+std::pair<int, int> choose_shape_half(dbq_ctx* c, bool f32, const DsBatch& b) {
+  int maxr = 1;
+  for (int i = 0; i < b.nlat; ++i) maxr = std::max(maxr, b.lat[i].nrhs);
+  const char* e_nb = std::getenv("DBQ_DS_NB");
+  const char* e_rg = std::getenv("DBQ_DS_RG");
+  if (e_nb || e_rg) {
+    const int nb = (e_nb && std::atoi(e_nb) == 2) ? 2 : 1;
+    return {nb, e_rg ? std::max(0, std::atoi(e_rg)) : 0};
+  }
+  std::vector<std::pair<int, int>> cand;
+  for (int nb : {1, 2}) {
+    if (nb > maxr) continue;
+    const int ng = (maxr + nb - 1) / nb;
+    for (int rg : {1, 2, 4, 0})
+      if (rg < ng) cand.push_back({nb, rg});
+  }
+  if (cand.size() == 1) return cand[0];
+  int big = 0;
+  for (int i = 1; i < b.nlat; ++i)
+    if ((long long)b.lat[i].g.V * b.lat[i].nrhs > (long long)b.lat[big].g.V * b.lat[big].nrhs) big = i;
+  const auto key = std::make_tuple(f32 ? 3 : 2, b.lat[big].g.V, b.lat[big].nrhs);
+  auto it = c->ds_tune.find(key);
+  if (it != c->ds_tune.end()) return it->second;
+  WsScope ws(c);
+  DsBatch t;
+  std::memset(&t, 0, sizeof(t));
+  t.nlat = 1;
+  t.schur = 1;
+  t.lat[0] = b.lat[big];
+  t.lat[0].rhs_base = 0;
+  t.lat[0].aux = nullptr;
+  t.lat[0].cen = nullptr;
+  t.lat[0].kappa = 1.0;
+  t.nrhs_total = t.lat[0].nrhs;
+  t.pstride = ds_partial_slots(t.lat[0].g);
+  const size_t bytes = size_t(t.lat[0].nrhs) * (t.lat[0].g.V / 2) *
+                       (f32 ? 6 * sizeof(float4) : 12 * sizeof(double2));
+  t.lat[0].out = ws.take(bytes);
+  hipEvent_t e0, e1;
+  DBQ_HIP(hipEventCreate(&e0));
+  DBQ_HIP(hipEventCreate(&e1));
+  std::pair<int, int> best = cand[0];
+  float best_ms = 1e30f;
+  for (const auto& sh : cand) {
+    for (int rep = 0; rep < 2; ++rep) {  // warm-up, then timed
+      DBQ_HIP(hipEventRecord(e0, c->stream));
+      for (int k = 0; k < 3; ++k) {
+        if (f32) launch_dslash_half_f32(c->stream, t, 1, 0, EPI_NONE, nullptr, nullptr, sh.first, sh.second, 0);
+        else launch_dslash_half_f64(c->stream, t, 1, 0, EPI_NONE, nullptr, nullptr, sh.first, sh.second, 0);
+      }
+      DBQ_HIP(hipEventRecord(e1, c->stream));
+    }
+    DBQ_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    DBQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (std::getenv("DBQ_DEBUG"))
+      std::fprintf(stderr, "[dbq] tune half %s V=%d nrhs=%d nb=%d rg=%d: %.1f us\n",
+                   f32 ? "fp32" : "fp64", t.lat[0].g.V, maxr, sh.first, sh.second, ms * 1e3f / 3);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = sh;
+    }
+  }
+  DBQ_HIP(hipEventDestroy(e0));
+  DBQ_HIP(hipEventDestroy(e1));
+  c->ds_tune[key] = best;
+  return best;
+}
+
+// The reduced operator Ahat = D - kappa^2 H_eo D^{-1} H_oe on a batch of half vectors: step 1
+// into a scratch odd-site vector, step 2 (with the batch's epilogue) into the output.  Gated
+// launches skip the same rhs in both steps.
+void run_schur(dbq_ctx* c, bool f32, const DsBatch& b0, int dagger, int epi, RhsScal* sc,
+               double* partials) {
+  WsScope ws(c);
+  const int gate = sc ? (epi == EPI_RESID ? 2 : 1) : 0;
+  DsBatch b1 = b0;
+  b1.acct = DsAcct{};
+  for (int i = 0; i < b1.nlat; ++i) {
+    DsLat& L = b1.lat[i];
+    L.out = ws.take(size_t(L.nrhs) * (L.g.V / 2) * (f32 ? 6 * sizeof(float4) : 12 * sizeof(double2)));
+    L.cen = nullptr;
+    L.aux = nullptr;
+    L.kappa = 1.0;
+  }
+  const auto shape = choose_shape_half(c, f32, b1);
+  DsBatch b2 = b0;
+  b2.acct = DsAcct{};
+  for (int i = 0; i < b2.nlat; ++i) {
+    DsLat& L = b2.lat[i];
+    L.in = b1.lat[i].out;
+    L.cen = b0.lat[i].in;
+    L.kappa = b0.lat[i].kappa * b0.lat[i].kappa;
+  }
+  if (f32) {
+    launch_dslash_half_f32(c->stream, b1, 1, dagger, EPI_NONE, sc, partials, shape.first, shape.second, gate);
+    launch_dslash_half_f32(c->stream, b2, 2, dagger, epi, sc, partials, shape.first, shape.second, gate);
+  } else {
+    launch_dslash_half_f64(c->stream, b1, 1, dagger, EPI_NONE, sc, partials, shape.first, shape.second, gate);
+    launch_dslash_half_f64(c->stream, b2, 2, dagger, epi, sc, partials, shape.first, shape.second, gate);
+  }
+  launch_ds_finalize(c->stream, b2, epi, sc, partials);
+}
+
 void run_dslash(dbq_ctx* c, bool f32, const DsBatch& b0, int dagger, int epi, RhsScal* sc,
                 double* partials) {
+  if (b0.schur) {
+    run_schur(c, f32, b0, dagger, epi, sc, partials);
+    return;
+  }
   const auto shape = choose_shape(c, f32, b0);
   const int kind = f32 ? 1 : 0;
   DsBatch b = b0;
@@ -199,6 +320,78 @@ void run_dslash(dbq_ctx* c, bool f32, const DsBatch& b0, int dagger, int epi, Rh
           : launch_dslash_f64(c->stream, b, dagger, epi, sc, partials, shape.first, rg);
   timer_end(c, kind, e0, dev_acct ? 0.0 : bytes);
   launch_ds_finalize(c->stream, b, epi, sc, partials);
+}
+
+// ---- even-odd reduced system: half vectors and the full system's right-hand side and solution.
+// Internal vectors are [rhs][6][sites] of esize-byte elements (32 in FP64, 16 in FP32); the even
+// sites are the first V/2 of each component array and the odd sites the rest, so a half vector
+// is a strided copy.
+void split_parity(hipStream_t s, const Geom& g, const void* full, void* even, void* odd, int nrhs,
+                  size_t esize) {
+  const size_t row = size_t(g.V / 2) * esize, pitch = size_t(g.V) * esize;
+  const size_t rows = size_t(6) * nrhs;
+  if (even)
+    DBQ_HIP(hipMemcpy2DAsync(even, row, full, pitch, row, rows, hipMemcpyDeviceToDevice, s));
+  if (odd)
+    DBQ_HIP(hipMemcpy2DAsync(odd, row, (const char*)full + row, pitch, row, rows,
+                             hipMemcpyDeviceToDevice, s));
+}
+// full vector from its halves; odd = null gives zero odd sites
+void merge_parity(hipStream_t s, const Geom& g, const void* even, const void* odd, void* full,
+                  int nrhs, size_t esize) {
+  const size_t row = size_t(g.V / 2) * esize, pitch = size_t(g.V) * esize;
+  const size_t rows = size_t(6) * nrhs;
+  DBQ_HIP(hipMemcpy2DAsync(full, pitch, even, row, row, rows, hipMemcpyDeviceToDevice, s));
+  if (odd)
+    DBQ_HIP(hipMemcpy2DAsync((char*)full + row, pitch, odd, row, row, rows,
+                             hipMemcpyDeviceToDevice, s));
+  else
+    DBQ_HIP(hipMemset2DAsync((char*)full + row, pitch, 0, row, rows, s));
+}
+
+// one FP64 half-lattice launch on nrhs vectors of one operator (coefficient c, twisted mass t)
+void half_step(dbq_ctx* c, const Op& op, int step, const double2* in, const double2* cen,
+               double2* out, double coef, double t, int nrhs, int dagger) {
+  DsBatch b = make_batch({DsSpec{&op, false, in, out, nullptr, nrhs, 0}});
+  b.lat[0].cen = cen;
+  b.lat[0].kappa = coef;
+  b.lat[0].mu = t;
+  launch_dslash_half_f64(c->stream, b, step, dagger, EPI_NONE, nullptr, nullptr, 1, 0, 0);
+}
+
+// canonical vectors -> even half of the packed FP64 vectors (x0, deflation vectors)
+void pack_even_f64(dbq_ctx* c, WsScope& ws, const Op& op, const void* canon, double2* half,
+                   int nrhs) {
+  double2* f = ws.get<double2>(size_t(op.nfull()) * nrhs);
+  pack_spinor_f64(c->stream, op.g, canon, f, nrhs);
+  split_parity(c->stream, op.g, f, half, nullptr, nrhs, 32);
+}
+// even-site half vectors -> canonical full vectors with zero odd sites
+void unpack_even_f64(dbq_ctx* c, WsScope& ws, const Op& op, const double2* half, void* canon,
+                     int nrhs) {
+  double2* f = ws.get<double2>(size_t(op.nfull()) * nrhs);
+  merge_parity(c->stream, op.g, half, nullptr, f, nrhs, 32);
+  unpack_spinor_f64(c->stream, op.g, f, canon, nrhs);
+}
+// bhat = b_e + kappa H_eo D^{-1} b_o (dagger: H^dagger and D(-mu)) from a packed full b; b_o is
+// left in bodd for the odd half of the solution
+void schur_rhs(dbq_ctx* c, WsScope& ws, const Op& op, const double2* bfull, double2* bhat,
+               double2* bodd, int nrhs, int dagger) {
+  const size_t nh = size_t(op.n()) * nrhs;
+  double2* be = ws.get<double2>(nh);
+  double2* u = ws.get<double2>(nh);
+  split_parity(c->stream, op.g, bfull, be, bodd, nrhs, 32);
+  half_step(c, op, 1, be, bodd, u, 0.0, op.mu, nrhs, dagger);       // u = D^{-1} b_o
+  half_step(c, op, 2, u, be, bhat, -op.kappa, 0.0, nrhs, dagger);   // b_e + kappa H_eo u
+}
+// canonical full solution from x_e: x_o = D^{-1} (b_o + kappa H_oe x_e)
+void schur_solution(dbq_ctx* c, WsScope& ws, const Op& op, const double2* xe, const double2* bodd,
+                    void* canon, int nrhs, int dagger) {
+  double2* xo = ws.get<double2>(size_t(op.n()) * nrhs);
+  double2* f = ws.get<double2>(size_t(op.nfull()) * nrhs);
+  half_step(c, op, 1, xe, bodd, xo, op.kappa, op.mu, nrhs, dagger);
+  merge_parity(c->stream, op.g, xe, xo, f, nrhs, 32);
+  unpack_spinor_f64(c->stream, op.g, f, canon, nrhs);
 }
 
 template <typename T>
@@ -259,6 +452,28 @@ void apply_operator(dbq_ctx* c, const dbq_operator* o, const void* in, void* out
   const bool f32 = prec == DBQ_MIXED;
   Op op = make_op(c, ws, o, !f32, f32);
   const long long V = op.g.V;
+  if (op.schur) {
+    // out_e = Ahat in_e, out_o = 0
+    if (!f32) {
+      double2* a = ws.get<double2>(size_t(op.n()) * nrhs);
+      double2* b = ws.get<double2>(size_t(op.n()) * nrhs);
+      pack_even_f64(c, ws, op, in, a, nrhs);
+      DsBatch bt = make_batch({DsSpec{&op, false, a, b, nullptr, nrhs, 0}});
+      run_dslash(c, false, bt, dagger, EPI_NONE, nullptr, nullptr);
+      unpack_even_f64(c, ws, op, b, out, nrhs);
+    } else {
+      float4* f = ws.get<float4>(6LL * V * nrhs);
+      float4* a = ws.get<float4>(3LL * V * nrhs);
+      float4* b = ws.get<float4>(3LL * V * nrhs);
+      pack_spinor_f32(c->stream, op.g, in, f, nrhs);
+      split_parity(c->stream, op.g, f, a, nullptr, nrhs, 16);
+      DsBatch bt = make_batch({DsSpec{&op, true, a, b, nullptr, nrhs, 0}});
+      run_dslash(c, true, bt, dagger, EPI_NONE, nullptr, nullptr);
+      merge_parity(c->stream, op.g, b, nullptr, f, nrhs, 16);
+      unpack_spinor_f32(c->stream, op.g, f, out, nrhs);
+    }
+    return;
+  }
   if (!f32) {
     double2* a = ws.get<double2>(12LL * V * nrhs);
     double2* b = ws.get<double2>(12LL * V * nrhs);
@@ -298,6 +513,8 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
   WsScope ws(c);
   std::vector<Op> op(nops);
   for (int i = 0; i < nops; ++i) op[i] = make_op(c, ws, &ops[i], true, mixed);
+  for (int i = 1; i < nops; ++i)
+    DBQ_CHECK(op[i].schur == op[0].schur, "operators of one call must all be full or all reduced");
 
   // ---- right-hand-side bookkeeping
   std::vector<int> base(nops), lat_of;
@@ -321,9 +538,21 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
   double2* b64 = ws.get<double2>(tot64);
   double2* x64 = ws.get<double2>(tot64);
   double2* r64 = ws.get<double2>(tot64);
+  // reduced operator: the iteration runs on bhat and x_e; the packed full b gives ||b|| and its
+  // odd half the odd half of the solution
+  std::vector<double2*> bfull(nops, nullptr), bodd(nops, nullptr);
   for (int i = 0; i < nops; ++i) {
-    pack_spinor_f64(s, op[i].g, B[i], b64 + off64[base[i]], nrhs[i]);
-    pack_spinor_f64(s, op[i].g, X[i], x64 + off64[base[i]], nrhs[i]);
+    const long long o = off64[base[i]];
+    if (op[i].schur) {
+      bfull[i] = ws.get<double2>(size_t(op[i].nfull()) * nrhs[i]);
+      bodd[i] = ws.get<double2>(size_t(op[i].n()) * nrhs[i]);
+      pack_spinor_f64(s, op[i].g, B[i], bfull[i], nrhs[i]);
+      schur_rhs(c, ws, op[i], bfull[i], b64 + o, bodd[i], nrhs[i], dagger);
+      pack_even_f64(c, ws, op[i], X[i], x64 + o, nrhs[i]);
+    } else {
+      pack_spinor_f64(s, op[i].g, B[i], b64 + o, nrhs[i]);
+      pack_spinor_f64(s, op[i].g, X[i], x64 + o, nrhs[i]);
+    }
   }
   VecSet vs64 = make_vecset(c, ws, ne64);
   VecSet vs32{};
@@ -353,13 +582,16 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
   long long maxn = 0;
   int maxr = 1;
   for (int i = 0; i < nops; ++i) {
-    maxn = std::max(maxn, op[i].n());
+    maxn = std::max(maxn, op[i].nfull());
     maxr = std::max(maxr, nrhs[i]);
   }
   size_t nw = norm_work(maxn, maxr);
   double* nwork = ws.get<double>(nw);
   for (int i = 0; i < nops; ++i) {
-    norm2_f64(s, b64 + off64[base[i]], op[i].n(), nrhs[i], op[i].n(), dn + base[i], nwork, nw);
+    // tol is relative to ||b|| of the full system also for the reduced operator
+    const double2* bn = op[i].schur ? bfull[i] : b64 + off64[base[i]];
+    const long long nn = op[i].schur ? op[i].nfull() : op[i].n();
+    norm2_f64(s, bn, nn, nrhs[i], nn, dn + base[i], nwork, nw);
     norm2_f64(s, x64 + off64[base[i]], op[i].n(), nrhs[i], op[i].n(), dn + NR + base[i], nwork, nw);
   }
   DBQ_HIP(hipMemcpyAsync(hn, dn, sizeof(double) * 2 * NR, hipMemcpyDeviceToHost, s));
@@ -406,10 +638,11 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
     const int k = kk[i];
     if (k == 0) continue;
     any_defl = true;
-    const long long n = op[i].n(), V = op[i].g.V;
+    const long long n = op[i].n(), V = op[i].sites();
     const long long o = off64[base[i]];
     double2* Vp = ws.get<double2>(k * n);
-    pack_spinor_f64(s, op[i].g, Vin[i], Vp, k);
+    if (op[i].schur) pack_even_f64(c, ws, op[i], Vin[i], Vp, k);
+    else pack_spinor_f64(s, op[i].g, Vin[i], Vp, k);
     const double2* right = Vp;
     if (dagger) {
       double2* R5 = ws.get<double2>(k * n);
@@ -754,8 +987,10 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
     for (int j = 0; j < NR; ++j)
       if (!have_true[j]) rrt[j] = hs[j].rr_true;
   }
-  for (int i = 0; i < nops; ++i)
-    unpack_spinor_f64(s, op[i].g, x64 + off64[base[i]], X[i], nrhs[i]);
+  for (int i = 0; i < nops; ++i) {
+    if (op[i].schur) schur_solution(c, ws, op[i], x64 + off64[base[i]], bodd[i], X[i], nrhs[i], dagger);
+    else unpack_spinor_f64(s, op[i].g, x64 + off64[base[i]], X[i], nrhs[i]);
+  }
   DBQ_HIP(hipStreamSynchronize(s));
   for (int j = 0; j < NR; ++j) {
     dbq_stats& o = st[j];
@@ -783,7 +1018,7 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
       for (int jl = 0; jl < nrhs[i]; ++jl)
         if (stalled[base[i] + jl]) js.push_back(base[i] + jl);
       if (js.empty()) continue;
-      const size_t vb = size_t(op[i].n()) * sizeof(double2);
+      const size_t vb = size_t(op[i].nfull()) * sizeof(double2);  // canonical full vectors
       char* bs = (char*)ws.take(vb * js.size());
       char* xs = (char*)ws.take(vb * js.size());
       for (size_t q = 0; q < js.size(); ++q) {
@@ -809,7 +1044,7 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
     size_t q2 = 0;
     for (size_t l = 0; l < rows.size(); ++l) {
       const int li = lat[l];
-      const size_t vb = size_t(op[li].n()) * sizeof(double2);
+      const size_t vb = size_t(op[li].nfull()) * sizeof(double2);
       for (size_t q = 0; q < rows[l].size(); ++q, ++q2) {
         const int j = rows[l][q];
         DBQ_HIP(hipMemcpyAsync((char*)X[li] + size_t(j - base[li]) * vb,
@@ -855,7 +1090,7 @@ struct Arnoldi {
 
   Arnoldi(dbq_ctx* ctx, WsScope& ws, const Op* o, int mm, int k) : c(ctx), op(o), m(mm) {
     n = o->n();
-    V = o->g.V;
+    V = o->sites();
     const int m1 = m + 1;
     Vb = ws.get<double2>(size_t(m1) * n);
     Vb2 = ws.get<double2>(size_t(m1) * n);
@@ -944,12 +1179,28 @@ int gmresdr(dbq_ctx* c, const dbq_operator* o, const void* b, void* x, int m, in
   double2* b64 = ws.get<double2>(n);
   double2* x64 = ws.get<double2>(n);
   double2* tmp = ws.get<double2>(n);
-  pack_spinor_f64(s, op.g, b, b64, 1);
-  pack_spinor_f64(s, op.g, x, x64, 1);
+  double2 *bfull = nullptr, *bodd = nullptr;
+  if (op.schur) {
+    // the Krylov space of Ahat from bhat and x_e; ||b|| of the full system sets the tolerance
+    bfull = ws.get<double2>(op.nfull());
+    bodd = ws.get<double2>(n);
+    pack_spinor_f64(s, op.g, b, bfull, 1);
+    schur_rhs(c, ws, op, bfull, b64, bodd, 1, 0);
+    pack_even_f64(c, ws, op, x, x64, 1);
+  } else {
+    pack_spinor_f64(s, op.g, b, b64, 1);
+    pack_spinor_f64(s, op.g, x, x64, 1);
+  }
   Arnoldi ar(c, ws, &op, m, k);
   double* dn = ws.get<double>(4);
   double* hp = (double*)pinned_get(c, 64 * sizeof(double) + 2 * 128 * sizeof(double2));
-  norm2_f64(s, b64, n, 1, n, dn, ar.nwork, ar.nw);
+  if (op.schur) {
+    const size_t nwf = norm_work(op.nfull(), 1);
+    double* wf = ws.get<double>(nwf);
+    norm2_f64(s, bfull, op.nfull(), 1, op.nfull(), dn, wf, nwf);
+  } else {
+    norm2_f64(s, b64, n, 1, n, dn, ar.nwork, ar.nw);
+  }
   norm2_f64(s, x64, n, 1, n, dn + 1, ar.nwork, ar.nw);
   DBQ_HIP(hipMemcpyAsync(hp, dn, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   DBQ_HIP(hipStreamSynchronize(s));
@@ -974,7 +1225,7 @@ int gmresdr(dbq_ctx* c, const dbq_operator* o, const void* b, void* x, int m, in
     ar.extend(j0);
     ++cycles;
     ar.cycle_end(k, 0, tol * bn);
-    combine_f64(s, ar.Vb, n, m, ar.d, m, x64, n, 1, n, op.g.V, 0, 1);
+    combine_f64(s, ar.Vb, n, m, ar.d, m, x64, n, 1, n, op.sites(), 0, 1);
     DBQ_HIP(hipMemcpyAsync(hp, ar.info, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
     DBQ_HIP(hipStreamSynchronize(s));
     conv = hp[2] != 0.0;
@@ -992,9 +1243,14 @@ int gmresdr(dbq_ctx* c, const dbq_operator* o, const void* b, void* x, int m, in
   DBQ_HIP(hipStreamSynchronize(s));
   const int kout = int(hp[1]);
   double2* Vint = ws.get<double2>(size_t(kout) * n);
-  combine_f64(s, ar.Vb, n, m, ar.P, m + 1, Vint, n, kout, n, op.g.V, 0, 0);
-  unpack_spinor_f64(s, op.g, Vint, Vout, kout);
-  unpack_spinor_f64(s, op.g, x64, x, 1);
+  combine_f64(s, ar.Vb, n, m, ar.P, m + 1, Vint, n, kout, n, op.sites(), 0, 0);
+  if (op.schur) {
+    unpack_even_f64(c, ws, op, Vint, Vout, kout);
+    schur_solution(c, ws, op, x64, bodd, x, 1, 0);
+  } else {
+    unpack_spinor_f64(s, op.g, Vint, Vout, kout);
+    unpack_spinor_f64(s, op.g, x64, x, 1);
+  }
   for (int i = 0; i < kout; ++i) {
     theta[2 * i] = th_h[i].x;
     theta[2 * i + 1] = th_h[i].y;
@@ -1030,6 +1286,8 @@ int kappa_crit(dbq_ctx* c, const int32_t L[4], const void* links, int m, int k, 
   o.links = links;
   o.kappa = -1.0;  // apply I + H: same eigenvectors, eigenvalues shifted by one
   o.mu = 0.0;
+  o.schur = 0;
+  o.pad = 0;
   check_op(&o);
   hipStream_t s = c->stream;
   WsScope ws(c);
@@ -1079,15 +1337,26 @@ int mr_project(dbq_ctx* c, const dbq_operator* o, const void* Q, int nq, const v
   hipStream_t s = c->stream;
   WsScope ws(c);
   Op op = make_op(c, ws, o, true, false);
-  const long long n = op.n(), V = op.g.V;
+  const long long n = op.n(), V = op.sites();
   double2* b64 = ws.get<double2>(size_t(nrhs) * n);
   double2* x64 = ws.get<double2>(size_t(nrhs) * n);
   double2* r64 = ws.get<double2>(size_t(nrhs) * n);
   double2* Qp = ws.get<double2>(size_t(nrhs) * nq * n);
   double2* W = ws.get<double2>(size_t(nrhs) * nq * n);
-  pack_spinor_f64(s, op.g, B, b64, nrhs);
-  pack_spinor_f64(s, op.g, X0, x64, nrhs);
-  pack_spinor_f64(s, op.g, Q, Qp, nrhs * nq);
+  double2* bodd = nullptr;
+  if (op.schur) {
+    // projection on the reduced system of the new operator: bhat, x0_e and the even parts of Q
+    double2* bfull = ws.get<double2>(size_t(nrhs) * op.nfull());
+    bodd = ws.get<double2>(size_t(nrhs) * n);
+    pack_spinor_f64(s, op.g, B, bfull, nrhs);
+    schur_rhs(c, ws, op, bfull, b64, bodd, nrhs, 0);
+    pack_even_f64(c, ws, op, X0, x64, nrhs);
+    pack_even_f64(c, ws, op, Q, Qp, nrhs * nq);
+  } else {
+    pack_spinor_f64(s, op.g, B, b64, nrhs);
+    pack_spinor_f64(s, op.g, X0, x64, nrhs);
+    pack_spinor_f64(s, op.g, Q, Qp, nrhs * nq);
+  }
   // r0 = b - A x0, W = A Q
   const DsBatch bx = make_batch({DsSpec{&op, false, x64, r64, nullptr, nrhs, 0}});
   run_dslash(c, false, bx, 0, EPI_NONE, nullptr, nullptr);
@@ -1129,7 +1398,8 @@ int mr_project(dbq_ctx* c, const dbq_operator* o, const void* Q, int nq, const v
     combine_f64(s, Qj, n, nq, z, nq, x64 + size_t(j) * n, n, 1, n, V, 0, 1);
   }
   norm2_f64(s, r64, n, nrhs, n, nrm + nrhs, nwork, nw);
-  unpack_spinor_f64(s, op.g, x64, X0, nrhs);
+  if (op.schur) schur_solution(c, ws, op, x64, bodd, X0, nrhs, 0);
+  else unpack_spinor_f64(s, op.g, x64, X0, nrhs);
   double* hp = (double*)pinned_get(c, sizeof(double) * 2 * nrhs);
   DBQ_HIP(hipMemcpyAsync(hp, nrm, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, s));
   DBQ_HIP(hipStreamSynchronize(s));
@@ -1148,6 +1418,7 @@ void force(dbq_ctx* c, const dbq_operator* o, const void* lambda, const void* x,
   DBQ_CHECK(lambda && x && F, "null argument");
   DBQ_CHECK(nrhs >= 1, "nrhs must be >= 1");
   DBQ_CHECK(kind == 0 || kind == 1, "kind must be 0 or 1");
+  DBQ_CHECK(o->schur == 0, "link_force needs the full operator (schur = 0)");
   const Geom g = make_geom(o->L);
   launch_link_force(c->stream, g, o->links, o->kappa, lambda, x, nrhs, kind, F);
 }

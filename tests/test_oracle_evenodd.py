@@ -142,3 +142,18 @@ def test_deflated_solve_of_the_reduced_system_solves_the_full_one():
     x = EO.schur_reconstruct(U, lat, kappa, xe, b).reshape(-1)
     r = b.reshape(-1) - W.apply_A(U, x, lat, kappa)
     assert np.linalg.norm(r) <= 2e-10 * np.linalg.norm(bh)
+
+
+def test_sampled_sites_equal_the_whole_field():
+    """The one-site-at-a-time Schur apply (for full-size GPU checks) agrees with the pinned
+    whole-field one."""
+    L = (4, 4, 2, 6)
+    lat = W.Lattice(L)
+    U = _field(L, 41)
+    xe = _gauss(L, 42)[lat.parity == 0].reshape(-1)
+    ev = np.nonzero(lat.parity == 0)[0]
+    pick = np.array([0, 5, 17, 40, len(ev) - 1])
+    for mu, dagger in [(0.0, False), (0.2, True)]:
+        whole = EO.schur_apply(U, lat, 0.13, xe, mu, dagger).reshape(-1, 4, 3)
+        got = EO.schur_apply_sites(U, lat, 0.13, xe, ev[pick], mu, dagger)
+        assert np.array_equal(got, whole[pick])
