@@ -118,8 +118,9 @@ def _timed(torch, fn):
     return r, time.perf_counter() - t
 
 
-def _setup(dbq, torch, synth, L, c, seed, kappa_frac, m, k, mu_defl=0.0, kc_mu=None):
-    """Field, kappa_c (GPU), kappa and the GMRES-DR(m,k) deflation space of a point source."""
+def _setup(dbq, torch, synth, L, c, seed, kappa_frac, m, k, mu_defl=0.0, kc_mu=None, schur=False):
+    """Field, kappa_c (GPU), kappa and the GMRES-DR(m,k) deflation space of a point source (of the
+    even-odd reduced operator with ``schur``)."""
     U = torch.from_numpy(synth.gauge_field(L, c, seed)).cuda()
     (kc, lam, res, st), t_kc = _timed(torch, lambda: dbq.kappa_critical(L, U, m=96, k=32,
                                                                          tol=1e-8))
@@ -127,12 +128,44 @@ def _setup(dbq, torch, synth, L, c, seed, kappa_frac, m, k, mu_defl=0.0, kc_mu=N
     kap = kappa_frac * kc
     b0 = torch.from_numpy(synth.point_source(L)).cuda()
     (x0, V, th, gst), t_gd = _timed(torch, lambda: dbq.gmresdr_first_rhs(L, U, b0, kap, m, k,
-                                                                         mu=mu_defl, tol=1e-8))
+                                                                         mu=mu_defl, tol=1e-8,
+                                                                         schur=schur))
     log(f"  {L}: GMRES-DR({m},{k}) {gst['matvecs']} MVPs {gst['status_name']} ({t_gd:.1f} s)")
     info = dict(lattice=list(L), c=c, seed=seed, kappa_c=kc, kappa=kap, kappa_c_s=round(t_kc, 2),
                 gmresdr=f"({m},{k})", gmresdr_mu=mu_defl, gmresdr_s=round(t_gd, 2),
                 gmresdr_mvps=gst["matvecs"], gmresdr_status=gst["status_name"], k_out=int(V.shape[0]))
     return U, kap, V, info
+
+
+def even_odd(dbq, torch, L, U, kappa, B, m, k, tol, steps):
+    """The same sources solved on the even-odd reduced system (the form Sec. 3 and Sec. 4 solve):
+    GMRES-DR(m,k) on Ahat for the point source, then mixed batched D-BiCGStab(k) on Ahat; the
+    solutions are full solutions of A x = b.  One Ahat application counts as one MVP."""
+    b0 = torch.from_numpy(synth_point(L)).cuda()
+    (x0, V, th, gst), t_gd = _timed(torch, lambda: dbq.gmresdr_first_rhs(
+        L, U, b0, kappa, m, k, tol=tol, schur=True))
+    log(f"even-odd GMRES-DR({m},{k}): {gst['matvecs']} MVPs {gst['status_name']} ({t_gd:.2f} s)")
+    prob = dict(L=L, links=U, kappa=kappa, B=B, V=V, schur=True)
+    dbq.dbicgstab_solve([prob], tol=tol, prec="mixed")  # warm-up (tunes the launch shape)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        X, st, status = dbq.dbicgstab_solve([prob], tol=tol, prec="mixed")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / steps
+    nrhs = B.shape[0]
+    out = dict(ms_per_source=round(ms / nrhs, 4), ms_per_step=round(ms, 3), steps=steps,
+               all_converged=status == 0, worst_rel_true_resid=max(x["rel_true_resid"] for x in st),
+               mvps_per_source=float(np.mean([x["matvecs"] for x in st])),
+               gmresdr_mvps=gst["matvecs"], gmresdr_status=gst["status_name"],
+               gmresdr_s=round(t_gd, 3), k_out=int(V.shape[0]))
+    log(f"even-odd mixed batched: {out}")
+    return out
+
+
+def synth_point(L):
+    import synth
+    return synth.point_source(L)
 
 
 def leg_c3(dbq, torch, synth):
@@ -192,13 +225,15 @@ def leg_c4(dbq, torch, synth):
     return {"16x16x16x16_gradient_nrhs8": info}
 
 
-def leg_c5(dbq, torch, synth):
+def leg_c5(dbq, torch, synth, schur=False):
     """Twisted-mass shifts on 24^3 x 48 at kappa_c: 8 masses mu = 0.001 * 20^(j/7) from the
     heaviest, each started from the minimal-residual combination of the previous solutions and
-    deflated with GMRES-DR(60,40) of A(mu = 0.02); 12 Z2 sources, mixed precision."""
+    deflated with GMRES-DR(60,40) of A(mu = 0.02); 12 Z2 sources, mixed precision.  With
+    ``schur`` every step runs on the even-odd reduced system (as Sec. 4 does)."""
     L = (24, 24, 24, 48)
     mus = [0.001 * 20 ** (j / 7) for j in range(8)][::-1]
-    U, kap, V, info = _setup(dbq, torch, synth, L, 0.6, 105, 1.0, 60, 40, mu_defl=mus[0])
+    U, kap, V, info = _setup(dbq, torch, synth, L, 0.6, 105, 1.0, 60, 40, mu_defl=mus[0],
+                             schur=schur)
     B = torch.from_numpy(synth.z2_sources(L, 12, 1105)).cuda()
     sols, shifts = [], []
     torch.cuda.synchronize()
@@ -207,24 +242,29 @@ def leg_c5(dbq, torch, synth):
         X0, r0, r1 = None, None, None
         if sols:
             Q = torch.stack(sols, dim=1)
-            X0, r0, r1 = dbq.project_shifts(L, U, kap, m, Q, B)
+            X0, r0, r1 = dbq.project_shifts(L, U, kap, m, Q, B, schur=schur)
             del Q
         (X, st, status), t = _timed(torch, lambda: dbq.dbicgstab_solve(
-            [dict(L=L, links=U, kappa=kap, mu=m, B=B, V=V, X0=X0)], tol=1e-8, prec="mixed",
-            max_mv=40000))
+            [dict(L=L, links=U, kappa=kap, mu=m, B=B, V=V, X0=X0, schur=schur)], tol=1e-8,
+            prec="mixed", max_mv=40000))
         shifts.append(dict(mu=m, solve_s=round(t, 3), status=status,
                            mvps_per_source=float(np.mean([x["matvecs"] for x in st])),
                            worst_rel_true_resid=max(x["rel_true_resid"] for x in st),
                            mr_resid_before_after=None if r0 is None else
                            [float(np.mean(r0)), float(np.mean(r1))]))
         sols.append(X[0])
-        log(f"C5 mu={m:.5f}: {shifts[-1]}")
+        log(f"C5{' even-odd' if schur else ''} mu={m:.5f}: {shifts[-1]}")
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     info.update(nrhs=12, shifts=shifts, total_s=round(total, 3),
                 ms_per_source_all_shifts=round(total * 1e3 / 12, 2),
                 total_mvps_per_source=float(sum(x["mvps_per_source"] for x in shifts)))
-    return {"24x24x24x48_twisted_shifts_nrhs12": info}
+    key = "24x24x24x48_twisted_shifts_nrhs12" + ("_even_odd" if schur else "")
+    return {key: info}
+
+
+def leg_c5eo(dbq, torch, synth):
+    return leg_c5(dbq, torch, synth, schur=True)
 
 
 def main():
@@ -239,7 +279,7 @@ def main():
     ap.add_argument("--extra", default="",
                     help="comma-separated extra workload legs, outside the timed steps: c3 "
                          "(20^3x32 and the uneven batch), c4 (16^4 gradient), c5 (24^3x48 "
-                         "twisted-mass shifts)")
+                         "twisted-mass shifts), c5eo (the same on the even-odd reduced system)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB with a plain device copy (a known-size reference "
                          "for hardware byte counters)")
@@ -386,9 +426,12 @@ def main():
         log(f"FP64 single-rhs: {fp64_ms:.1f} ms/source ({mv64:.0f} MVPs); undeflated "
             f"{und_ms:.1f} ms ({su[0]['matvecs']} MVPs)")
         del X
+        eo = even_odd(dbq, torch, L, U, kappa, B, m, k, tol, max(1, min(a.steps, 3)))
+        eo["speedup_vs_full_operator"] = round((ms_step / nrhs) / eo["ms_per_source"], 2)
+        out["even_odd_reduced_system"] = eo
         out["dslash_24x24x24x48"] = dslash_sweep(dbq, torch)
         log(f"dslash sweep: {out['dslash_24x24x24x48']}")
-    legs = {"c3": leg_c3, "c4": leg_c4, "c5": leg_c5}
+    legs = {"c3": leg_c3, "c4": leg_c4, "c5": leg_c5, "c5eo": leg_c5eo}
     for name in [x for x in a.extra.split(",") if x]:
         if name not in legs:
             raise SystemExit(f"unknown leg {name}")

@@ -99,8 +99,10 @@ __device__ void fin_xr(RhsScal& q, double a0, double a1, double a2) {
   if (q.delta2 > 0.0) {
     if (a2 > q.rr_max) q.rr_max = a2;
     // a drop by the reliable-update factor, or a long stretch without one (checked for a
-    // stall by the FP64 residual that follows)
-    if (a2 < q.delta2 * q.rr_max || q.since >= STALL_ITERS) q.flags |= F_RELIABLE;
+    // stall by the FP64 residual that follows), or growth by 100x over the last FP64
+    // residual (checked for divergence)
+    if (a2 < q.delta2 * q.rr_max || q.since >= STALL_ITERS || a2 > 1e4 * q.rr_prev)
+      q.flags |= F_RELIABLE;
   }
   if (norm2(rn) <= 1e-28 * q.rhat2 * a2) q.flags |= F_BREAK;
   if (q.flags & F_OMEGA0) q.flags |= F_BREAK;

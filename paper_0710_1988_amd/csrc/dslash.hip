@@ -370,12 +370,14 @@ __device__ void finalize(const DsBatch& B, RhsScal* sc, const double* partials) 
             } else {
               // a stall: the FP32 recursion claimed a 10x drop (or ran STALL_ITERS iterations
               // without one) but the FP64 residual fell by less than 2x since the last check;
-              // convergence claims just above the tolerance are not counted
+              // convergence claims just above the tolerance are not counted.  A residual grown
+              // by 100x since the last check means the FP32 iteration diverges: stop at once.
               const bool slow = a0 > 0.25 * q.rr_prev;
+              const bool diverged = a0 > 1e4 * q.rr_prev;
               if (!slow) q.stalls = 0;
               else if (q.rr <= 0.01 * q.rr_prev || q.since >= STALL_ITERS) q.stalls += 1;
               q.rr_prev = a0;
-              if (q.stalls >= 2) {
+              if (q.stalls >= 2 || diverged) {
                 q.flags = F_STALL;
                 q.active = 0;
                 q.sel = 0;
@@ -812,10 +814,12 @@ __device__ __forceinline__ int slot_site(const Geom& g, const TileGeo& t, const 
   return p * g.Vh + (tile_n << g.lTh) + in_tile_half(g, ic);
 }
 
+// the spinor in LDS slot `slot` of a staging area with NS slots per component
+template <int NS>
 __device__ __forceinline__ void lds_spinor(const float4* lds, int slot, zf (&p)[12]) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
-    const float4 v = lds[k * TL_SLOTS + slot];
+    const float4 v = lds[k * NS + slot];
     p[2 * k] = zf{v.x, v.y};
     p[2 * k + 1] = zf{v.z, v.w};
   }
@@ -834,13 +838,13 @@ __device__ __forceinline__ void rebuild(const float4 (&l)[3], zf (&u)[9]) {
 }
 
 // one hop from LDS: BACK = false -> (1 + S gamma) U psi(slot); BACK = true -> U^dagger instead
-template <int MU, int S, bool BACK>
+template <int MU, int S, bool BACK, int NS = TL_SLOTS>
 __device__ __forceinline__ void hop_lds(const float4* lds, int slot, const float4 (&l)[3],
                                         zf (&acc)[12]) {
   zf u[9];
   rebuild(l, u);
   zf p[12];
-  lds_spinor(lds, slot, p);
+  lds_spinor<NS>(lds, slot, p);
   zf h[6];
   project<float, MU, S>(p, h);
   zf chi[6];
@@ -985,7 +989,7 @@ __global__ __launch_bounds__(DS_BS) void k_dslash_tile(DsBatch B, RhsScal* __res
       hop_lds<3, SF, false>(buf, ns[6], lf[3], acc);
       hop_lds<3, SB, true>(buf, ns[7], lbk[3], acc);
       zf psi[12];
-      lds_spinor(buf, tid, psi);
+      lds_spinor<TL_SLOTS>(buf, tid, psi);
       zf o[12];
       finish_site<float, EPI>(psi, acc, kap, tm, ax, red[0], red[1], red[2], o);
       IO<float>::store((float4*)L.out + (long long)r * 6 * V, V, s, o);
@@ -1003,6 +1007,240 @@ __global__ __launch_bounds__(DS_BS) void k_dslash_tile(DsBatch B, RhsScal* __res
     if (jn < Gc) {
       __syncthreads();  // every thread is done with the copy that is overwritten next
       stage(jn, lds);
+    }
+    j = jn;
+  }
+}
+
+// ---------------------------------------------------------------------------- half-lattice tiles
+// The two steps of the even-odd reduced operator (see k_dslash_half) with the LDS staging of
+// k_dslash_tile: one block of TH_BS threads per (tile, rhs chunk) computes the tile's sites of the
+// output parity P; it stages, per rhs, the tile's sites of the other parity Q and the parity-Q
+// halves of the 8 neighbouring faces (the only neighbours those sites have), so every staged
+// spinor passes through the vector memory unit once per rhs as a centre-tile site and at most
+// once more per face it lies on.
+//   LDS slots per component: [0, Vt/2) the tile's parity-Q sites in memory order; then per face f
+//   = (mu, +-) the Vt/(2 T_mu) parity-Q sites of that face, indexed by the face's lexicographic
+//   position (three other in-tile coordinates) shifted right by one (the lowest of those
+//   coordinates has even extent, so each pair holds one site of each parity).
+constexpr int TH_BS = 128;     // threads per block: the parity-P sites of a 4^4 tile
+constexpr int TH_SLOTS = 384;  // 128 + 8 x 32
+
+__device__ __forceinline__ TileGeo tile_geo_half(const Geom& g) {
+  TileGeo t;
+  t.vh = 1 << g.lTh;
+  t.vt = 2 * t.vh;
+  int b = t.vh;
+#pragma unroll
+  for (int f = 0; f < 8; ++f) {
+    t.fbase[f] = b;
+    b += (t.vt >> g.lT[f >> 1]) >> 1;
+  }
+  return t;
+}
+
+// LDS slot of the (parity-Q) neighbour x + DIR*MU of the tile site with in-tile coordinates ic
+template <int MU, int DIR>
+__device__ __forceinline__ int nbr_slot_half(const Geom& g, const TileGeo& t, const int (&ic)[4]) {
+  const int v = ic[MU] + DIR;
+  if (v >= 0 && v < g.T[MU]) {
+    int d[4] = {ic[0], ic[1], ic[2], ic[3]};
+    d[MU] = v;
+    return in_tile_half(g, d);
+  }
+  return t.fbase[2 * MU + (DIR > 0 ? 0 : 1)] + (face_index<MU>(g, ic) >> 1);
+}
+
+// index in the parity-Q half vector of the site held in LDS slot j of tile tc; slots past the
+// last face repeat the tile's first site (their copies are never read)
+__device__ __forceinline__ int slot_site_half(const Geom& g, const TileGeo& t, const int (&tc)[4],
+                                              int tile, int j, int nslots, int Q) {
+  if (j < t.vh) return (tile << g.lTh) + j;
+  if (j >= nslots) return tile << g.lTh;
+  int f = 0, fb = t.fbase[0];
+#pragma unroll
+  for (int i = 1; i < 8; ++i)
+    if (j >= t.fbase[i]) {
+      f = i;
+      fb = t.fbase[i];
+    }
+  const int mu = f >> 1;
+  const int dir = (f & 1) ? -1 : +1;
+  uint32_t q = uint32_t(j - fb) << 1;
+  int ic[4], tn[4];
+#pragma unroll
+  for (int nu = 0; nu < 4; ++nu) {
+    if (nu == mu) {
+      ic[nu] = dir > 0 ? 0 : g.T[nu] - 1;
+      int v = tc[nu] + dir;
+      tn[nu] = v < 0 ? g.NT[nu] - 1 : (v == g.NT[nu] ? 0 : v);
+    } else {
+      ic[nu] = int(q & uint32_t(g.T[nu] - 1));
+      q >>= g.lT[nu];
+      tn[nu] = tc[nu];
+    }
+  }
+  // the pair's parity-Q member: step the lowest other coordinate (even extent) by one
+  if (((ic[0] + ic[1] + ic[2] + ic[3]) & 1) != Q) {
+    if (mu == 0) ic[1] += 1;
+    else ic[0] += 1;
+  }
+  const int tile_n = tn[0] + g.NT[0] * (tn[1] + g.NT[1] * (tn[2] + g.NT[2] * tn[3]));
+  return (tile_n << g.lTh) + in_tile_half(g, ic);
+}
+
+template <bool DAG, int EPI, int STEP>
+__global__ __launch_bounds__(TH_BS) void k_dslash_tile_half(DsBatch B, RhsScal* __restrict__ sc,
+                                                            double* __restrict__ partials,
+                                                            int gate) {
+  constexpr int P = STEP == 1 ? 1 : 0;  // output parity
+  constexpr int Q = 1 - P;              // parity of the hop input
+  __shared__ float4 lds[6 * TH_SLOTS];
+  const int lb = xcd_block(blockIdx.x, B.nblocks);
+  int l = 0;
+#pragma unroll
+  for (int i = 1; i < MAXLAT; ++i)
+    if (i < B.nlat && lb >= B.lat[i].blk_begin) l = i;
+  const DsLat& L = B.lat[l];
+  const Geom& g = L.g;
+  const int G = tile_chunk(B.rgroup, L.nrhs);
+  const int nch = (L.nrhs + G - 1) / G;
+  const int loc = lb - L.blk_begin;
+  const int tile = loc / nch;
+  const int r0 = (loc - tile * nch) * G;
+  const int Gc = min(G, L.nrhs - r0);
+  const int Vh = g.V >> 1;
+  const TileGeo tg = tile_geo_half(g);
+  const int nslots = tg.fbase[7] + ((tg.vt >> g.lT[3]) >> 1);
+  int tc[4];
+  {
+    const uint32_t q1 = g.dNT0.div(uint32_t(tile));
+    const uint32_t q2 = g.dNT1.div(q1);
+    const uint32_t q3 = g.dNT2.div(q2);
+    tc[0] = int(uint32_t(tile) - q1 * uint32_t(g.NT[0]));
+    tc[1] = int(q1 - q2 * uint32_t(g.NT[1]));
+    tc[2] = int(q2 - q3 * uint32_t(g.NT[2]));
+    tc[3] = int(q3);
+  }
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // LDS-direct copies: wave wv fills the 64-slot chunks wv, wv + 2, wv + 4 of every component
+  const int nck = (nslots + 63) >> 6;
+  int seo[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    seo[i] = slot_site_half(g, tg, tc, tile, (wv + 2 * i) * 64 + lane, nslots, Q);
+
+  const bool own = tid < tg.vh;
+  const int h = (tile << g.lTh) + tid;  // output index in the parity-P half vector
+  int ns[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  float4 lf[4][3], lbk[4][3];
+  if (own) {
+    int ic[4];
+    tile_coords(g, tg, P * tg.vh + tid, ic);
+    const int s = P * Vh + h;
+    int c[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) c[mu] = (tc[mu] << g.lT[mu]) + ic[mu];
+    ns[0] = nbr_slot_half<0, +1>(g, tg, ic);
+    ns[1] = nbr_slot_half<0, -1>(g, tg, ic);
+    ns[2] = nbr_slot_half<1, +1>(g, tg, ic);
+    ns[3] = nbr_slot_half<1, -1>(g, tg, ic);
+    ns[4] = nbr_slot_half<2, +1>(g, tg, ic);
+    ns[5] = nbr_slot_half<2, -1>(g, tg, ic);
+    ns[6] = nbr_slot_half<3, +1>(g, tg, ic);
+    ns[7] = nbr_slot_half<3, -1>(g, tg, ic);
+    int yb[4];
+    yb[0] = eo_neighbour<0, -1>(g, c);
+    yb[1] = eo_neighbour<1, -1>(g, c);
+    yb[2] = eo_neighbour<2, -1>(g, c);
+    yb[3] = eo_neighbour<3, -1>(g, c);
+    const float4* U = (const float4*)L.links;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        lf[mu][k] = ldo(U + (long long)(mu * 3 + k) * g.V, unsigned(s) * 16u);
+        lbk[mu][k] = ldo(U + (long long)(mu * 3 + k) * g.V, unsigned(yb[mu]) * 16u);
+      }
+  }
+  constexpr int SF = DAG ? +1 : -1;
+  constexpr int SB = -SF;
+  const float coef = float(L.kappa);
+  const float tm = float(DAG ? -L.mu : L.mu);
+  auto active = [&](int j) {
+    if (gate == 1) return sc[L.rhs_base + r0 + j].active != 0;
+    if (gate == 2) return sc[L.rhs_base + r0 + j].sel != 0;
+    return true;
+  };
+  auto next = [&](int j) {
+    while (j < Gc && !active(j)) ++j;  // uniform over the block
+    return j;
+  };
+  auto stage = [&](int j) {
+    const float4* in = (const float4*)L.in + (long long)(r0 + j) * 6 * Vh;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int ck = wv + 2 * i;
+      if (ck < nck) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+          __builtin_amdgcn_global_load_lds(
+              (const void*)(in + (long long)k * Vh + seo[i]),
+              (__attribute__((address_space(3))) void*)(lds + k * TH_SLOTS + ck * 64), 16, 0, 0);
+      }
+    }
+  };
+  int j = next(0);
+  if (j < Gc) stage(j);
+  while (j < Gc) {
+    const int r = r0 + j;
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's LDS-direct copies have landed
+    __syncthreads();                // and everyone else's
+    const int jn = next(j + 1);
+    double red[3] = {0.0, 0.0, 0.0};
+    if (own) {
+      zf ce[12], ax[12];
+      if (L.cen) {
+        IO<float>::load((const float4*)L.cen + (long long)r * 6 * Vh, Vh, h, ce);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) ce[k] = zf{0.f, 0.f};
+      }
+      zf acc[12];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) acc[k] = zf{0.f, 0.f};
+      hop_lds<0, SF, false, TH_SLOTS>(lds, ns[0], lf[0], acc);
+      hop_lds<0, SB, true, TH_SLOTS>(lds, ns[1], lbk[0], acc);
+      hop_lds<1, SF, false, TH_SLOTS>(lds, ns[2], lf[1], acc);
+      hop_lds<1, SB, true, TH_SLOTS>(lds, ns[3], lbk[1], acc);
+      hop_lds<2, SF, false, TH_SLOTS>(lds, ns[4], lf[2], acc);
+      hop_lds<2, SB, true, TH_SLOTS>(lds, ns[5], lbk[2], acc);
+      hop_lds<3, SF, false, TH_SLOTS>(lds, ns[6], lf[3], acc);
+      hop_lds<3, SB, true, TH_SLOTS>(lds, ns[7], lbk[3], acc);
+      // the epilogue operand is read after the hops (the empty asm keeps the compiler from
+      // hoisting its load): loaded with the centre it holds registers through the hops and
+      // halves the resident waves
+      asm volatile("" ::: "memory");
+      if (STEP == 2 && (EPI == EPI_RHAT || EPI == EPI_RESID))
+        IO<float>::load((const float4*)L.aux + (long long)r * 6 * Vh, Vh, h, ax);
+      zf o[12];
+      if (STEP == 1) finish_odd<float>(ce, acc, coef, tm, o);
+      else finish_site<float, EPI>(ce, acc, coef, tm, ax, red[0], red[1], red[2], o);
+      IO<float>::store((float4*)L.out + (long long)r * 6 * Vh, Vh, h, o);
+    }
+    if (EPI != EPI_NONE) {
+      __shared__ double sh[3 * (TH_BS / 64)];
+      block_sum<3, TH_BS>(red, sh);
+      if (tid == 0) {
+        double* pp = partials + ((long long)(L.rhs_base + r) * B.pstride + tile) * 3;
+        pp[0] = red[0];
+        pp[1] = red[1];
+        pp[2] = red[2];
+      }
+    }
+    if (jn < Gc) {
+      __syncthreads();  // every thread is done with the copy that is overwritten next
+      stage(jn);
     }
     j = jn;
   }
@@ -1121,6 +1359,22 @@ void launch_half_step(hipStream_t s, const DsBatch& b, int step, int epi, RhsSca
   }
 }
 
+template <bool DAG>
+void launch_tile_half(hipStream_t s, const DsBatch& b, int step, int epi, RhsScal* sc,
+                      double* partials, int gate) {
+  dim3 grid(b.nblocks), block(TH_BS);
+  if (step == 1) {
+    hipLaunchKernelGGL((k_dslash_tile_half<DAG, EPI_NONE, 1>), grid, block, 0, s, b, sc, partials, gate);
+    return;
+  }
+  switch (epi) {
+    case EPI_NONE: hipLaunchKernelGGL((k_dslash_tile_half<DAG, EPI_NONE, 2>), grid, block, 0, s, b, sc, partials, gate); break;
+    case EPI_RHAT: hipLaunchKernelGGL((k_dslash_tile_half<DAG, EPI_RHAT, 2>), grid, block, 0, s, b, sc, partials, gate); break;
+    case EPI_TS: hipLaunchKernelGGL((k_dslash_tile_half<DAG, EPI_TS, 2>), grid, block, 0, s, b, sc, partials, gate); break;
+    default: hipLaunchKernelGGL((k_dslash_tile_half<DAG, EPI_RESID, 2>), grid, block, 0, s, b, sc, partials, gate); break;
+  }
+}
+
 template <typename T>
 void launch_half(hipStream_t s, DsBatch& b, int step, int dagger, int epi, RhsScal* sc,
                  double* partials, int nb, int rgroup, int gate) {
@@ -1129,8 +1383,10 @@ void launch_half(hipStream_t s, DsBatch& b, int step, int dagger, int epi, RhsSc
   DBQ_CHECK(step == 2 || epi == EPI_NONE, "dslash (half): epilogues follow step 2");
   DBQ_CHECK(epi == EPI_NONE || (sc && partials), "dslash (half): epilogue needs scalars");
   DBQ_CHECK(gate == 0 || sc, "dslash (half): gating needs scalars");
-  DBQ_CHECK(nb == 1 || nb == 2, "dslash (half): rhs per thread must be 1 or 2");
-  b.nb = nb;
+  const bool tiled = nb == 0;
+  DBQ_CHECK(nb == 1 || nb == 2 || (tiled && sizeof(T) == 4),
+            "dslash (half): rhs per thread must be 1 or 2 (0: LDS-staged tiles, FP32)");
+  b.nb = tiled ? 1 : nb;
   b.rgroup = rgroup;
   long long blk = 0;
   for (int i = 0; i < b.nlat; ++i) {
@@ -1140,13 +1396,24 @@ void launch_half(hipStream_t s, DsBatch& b, int step, int dagger, int epi, RhsSc
     DBQ_CHECK(step == 2 || epi == EPI_NONE, "dslash (half): bad epilogue");
     DBQ_CHECK(!((epi == EPI_RHAT || epi == EPI_RESID) && !L.aux), "dslash (half): null aux");
     L.blk_begin = int(blk);
-    L.nsb = (L.g.V / 2 + DS_BS - 1) / DS_BS;
-    blk += (long long)L.nsb * ((L.nrhs + nb - 1) / nb);
+    if (tiled) {
+      DBQ_CHECK(L.g.T[0] <= 4 && L.g.T[1] <= 4 && L.g.T[2] <= 4 && L.g.T[3] <= 4,
+                "dslash (half): tile larger than 4^4");
+      L.nsb = L.g.V >> (L.g.lTh + 1);
+      const int G = tile_chunk(rgroup, L.nrhs);
+      blk += (long long)L.nsb * ((L.nrhs + G - 1) / G);
+    } else {
+      L.nsb = (L.g.V / 2 + DS_BS - 1) / DS_BS;
+      blk += (long long)L.nsb * ((L.nrhs + nb - 1) / nb);
+    }
     DBQ_CHECK(epi == EPI_NONE || L.nsb <= b.pstride, "dslash (half): partial-sum slots too few");
   }
   DBQ_CHECK(blk > 0 && blk < (1ll << 31), "dslash (half): grid size out of range");
   b.nblocks = int(blk);
-  if (dagger) {
+  if (tiled) {
+    if (dagger) launch_tile_half<true>(s, b, step, epi, sc, partials, gate);
+    else launch_tile_half<false>(s, b, step, epi, sc, partials, gate);
+  } else if (dagger) {
     if (nb == 2) launch_half_step<T, true, 2>(s, b, step, epi, sc, partials, gate);
     else launch_half_step<T, true, 1>(s, b, step, epi, sc, partials, gate);
   } else {

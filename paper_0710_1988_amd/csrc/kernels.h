@@ -140,7 +140,9 @@ double launch_dslash_f32(hipStream_t s, DsBatch& b, int dagger, int epi, RhsScal
 // of one parity): step 1 computes the odd sites, out = D^{-1} (cen + c H_oe in); step 2 the even
 // ones, out = D cen - c H_eo in followed by the epilogue; c = lat.kappa, D = 1 + i t gamma5 with
 // t = lat.mu (-mu for the dagger, whose hops are those of H^dagger); cen may be null in step 1.
-// gate: 0 = every rhs, 1 = the active ones, 2 = the selected ones (needs sc).
+// gate: 0 = every rhs, 1 = the active ones, 2 = the selected ones (needs sc).  nb = 1 or 2 rhs
+// per thread (rgroup as for the full operator), or in FP32 nb = 0 for the LDS-staged tile kernel
+// (rgroup rhs per block, 0 = all).
 void launch_dslash_half_f64(hipStream_t s, DsBatch& b, int step, int dagger, int epi,
                             RhsScal* sc, double* partials, int nb, int rgroup, int gate);
 void launch_dslash_half_f32(hipStream_t s, DsBatch& b, int step, int dagger, int epi,

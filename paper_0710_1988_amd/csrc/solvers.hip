@@ -184,15 +184,18 @@ std::pair<int, int> choose_shape(dbq_ctx* c, bool f32, const DsBatch& b) {
 }
 
 // Launch shape (nb, rg) of the half-lattice kernels for a batch of the reduced operator: nb = 1
-// or 2 rhs per thread, rg as for the site kernel; timed once per (precision, volume, batch size)
-// on step 1 into a scratch output.  DBQ_DS_NB / DBQ_DS_RG force the values (nb clamped to 1, 2).
+// or 2 rhs per thread with rg as for the site kernel, or in FP32 nb = 0 for the LDS-staged tile
+// kernel with rg rhs per block; timed once per (precision, volume, batch size) on step 1 into a
+// scratch output.  DBQ_DS_NB / DBQ_DS_RG force the values.
 std::pair<int, int> choose_shape_half(dbq_ctx* c, bool f32, const DsBatch& b) {
   int maxr = 1;
   for (int i = 0; i < b.nlat; ++i) maxr = std::max(maxr, b.lat[i].nrhs);
   const char* e_nb = std::getenv("DBQ_DS_NB");
   const char* e_rg = std::getenv("DBQ_DS_RG");
   if (e_nb || e_rg) {
-    const int nb = (e_nb && std::atoi(e_nb) == 2) ? 2 : 1;
+    int nb = e_nb ? std::atoi(e_nb) : 1;
+    if (nb != 0 && nb != 2) nb = 1;
+    if (nb == 0 && !f32) nb = 1;
     return {nb, e_rg ? std::max(0, std::atoi(e_rg)) : 0};
   }
   std::vector<std::pair<int, int>> cand;
@@ -201,6 +204,10 @@ std::pair<int, int> choose_shape_half(dbq_ctx* c, bool f32, const DsBatch& b) {
     const int ng = (maxr + nb - 1) / nb;
     for (int rg : {1, 2, 4, 0})
       if (rg < ng) cand.push_back({nb, rg});
+  }
+  if (f32) {
+    for (int g : {1, 2, 3, 4, 6, 0})
+      if (g < maxr) cand.push_back({0, g});
   }
   if (cand.size() == 1) return cand[0];
   int big = 0;
@@ -600,6 +607,9 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
   std::vector<long long> mvb(NR, 0);
   std::vector<int> status(NR, DBQ_NOT_CONVERGED), restarts(NR, 0), relup(NR, 0);
   std::vector<char> done(NR, 0), have_true(NR, 0), stalled(NR, 0);
+  // FP32 iterations that produced a non-finite value: their FP32 correction is dropped, and
+  // zero_start marks those whose FP64 solution is not finite either
+  std::vector<char> discard(NR, 0), zero_start(NR, 0);
   std::vector<double> rrt(NR, 0.0);
   std::memset(hs, 0, sizeof(RhsScal) * NR);
   bool any_x0 = false;
@@ -818,8 +828,13 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
           rrt[j] = q.rr_true;
           have_true[j] = 1;
         } else if (q.flags & F_NAN) {
+          // continued in FP64 like a stall, from the last accumulated solution
           done[j] = 1;
-          status[j] = DBQ_EBREAKDOWN;
+          stalled[j] = 1;
+          discard[j] = 1;
+          zero_start[j] = std::isfinite(q.rr_true) ? 0 : 1;
+          rrt[j] = q.rr_true;
+          have_true[j] = 1;
           Cc.push_back(j);
         } else if (q.flags & F_BREAK) {
           Bk.push_back(j);
@@ -970,7 +985,7 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
   pull();
   bool need = false;
   for (int j = 0; j < NR; ++j) {
-    hs[j].sel = 1;  // accumulate any FP32 correction that is left
+    hs[j].sel = discard[j] ? 0 : 1;  // accumulate any FP32 correction that is left
     hs[j].active = 0;
   }
   push();
@@ -1003,8 +1018,9 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
     o.pad = 0;
   }
 
-  // ---- rhs whose FP32 iteration stalled: continue them in FP64 from their current solution
-  // (same deflation space, remaining MVP budget), gathered per lattice into contiguous buffers
+  // ---- rhs whose FP32 iteration stalled, diverged or broke down with a non-finite value:
+  // continue them in FP64 from their current solution (from zero if that is not finite; same
+  // deflation space, remaining MVP budget), gathered per lattice into contiguous buffers
   if (std::any_of(stalled.begin(), stalled.end(), [](char v) { return v != 0; })) {
     std::vector<dbq_operator> ops2;
     std::vector<const void*> V2, B2;
@@ -1025,8 +1041,11 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
         const size_t jl = size_t(js[q] - base[i]);
         DBQ_HIP(hipMemcpyAsync(bs + q * vb, (const char*)B[i] + jl * vb, vb,
                                hipMemcpyDeviceToDevice, s));
-        DBQ_HIP(hipMemcpyAsync(xs + q * vb, (const char*)X[i] + jl * vb, vb,
-                               hipMemcpyDeviceToDevice, s));
+        if (zero_start[js[q]])
+          DBQ_HIP(hipMemsetAsync(xs + q * vb, 0, vb, s));
+        else
+          DBQ_HIP(hipMemcpyAsync(xs + q * vb, (const char*)X[i] + jl * vb, vb,
+                                 hipMemcpyDeviceToDevice, s));
         used = std::max<int64_t>(used, st[js[q]].matvecs);
       }
       ops2.push_back(ops[i]);

@@ -52,6 +52,26 @@ def test_schur_apply_fp32_matches_oracle(gpu_lib, L, nrhs):
             assert np.all(_odd(lat, out[j]) == 0)
 
 
+@pytest.mark.parametrize("L", LATS)
+@pytest.mark.parametrize("shape", [("0", "1"), ("0", "2"), ("0", "0"), ("1", "1"), ("1", "0"),
+                                   ("2", "0"), ("2", "2")])
+def test_every_schur_fp32_launch_shape_matches_oracle(gpu_lib, monkeypatch, L, shape):
+    """Each FP32 launch shape of the half-lattice kernels: the LDS-staged tile kernel (nb 0) with
+    1, 2 or all rhs per block, and 1 or 2 rhs per thread; 5 rhs leave a ragged last chunk."""
+    monkeypatch.setenv("DBQ_DS_NB", shape[0])
+    monkeypatch.setenv("DBQ_DS_RG", shape[1])
+    lat = W.Lattice(L)
+    U = synth.gauge_field(L, 0.6, 218)
+    psi = synth.gaussian_sources(L, 5, 219)
+    for dagger, mu in ((False, 0.0), (True, 0.031)):
+        out = host(gpu_lib.wilson_apply(L, dev(U), dev(psi), 0.127, mu, dagger, "mixed",
+                                        schur=True))
+        for j in range(5):
+            want = EO.schur_apply(U, lat, 0.127, _even(lat, psi[j]), mu, dagger)
+            assert relerr(_even(lat, out[j]), want) <= 2e-6
+            assert np.all(_odd(lat, out[j]) == 0)
+
+
 def test_schur_apply_full_size_16x16x16x16_batch_of_12_sampled_sites(gpu_lib):
     """16^4, 12 Z2 sources in one FP32 launch pair (the benchmark's shape), checked at 64 sampled
     even sites per source against the oracle's one-site apply."""
@@ -115,12 +135,16 @@ def test_schur_gmresdr_matches_oracle(gpu_lib):
         assert projector_distance(Vg, Vo) <= 1e-6
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec,shape", [("fp64", None), ("mixed", None), ("mixed", ("0", "1")),
+                                         ("mixed", ("0", "0")), ("mixed", ("2", "0"))])
 @pytest.mark.parametrize("dagger", [False, True])
-def test_schur_dbicgstab_batched_matches_oracle(gpu_lib, prec, dagger):
-    """D-BiCGStab(6) on Ahat for 3 Z2 sources in one call: every full solution meets 1e-8 on
-    A x = b (or A^dagger x = b), and agrees with the oracle's deflated solve of the same reduced
-    system to the conditioning of the tolerance."""
+def test_schur_dbicgstab_batched_matches_oracle(gpu_lib, monkeypatch, prec, shape, dagger):
+    """D-BiCGStab(6) on Ahat for 3 Z2 sources in one call (FP32 launch shapes forced or tuned):
+    every full solution meets 1e-8 on A x = b (or A^dagger x = b), and agrees with the oracle's
+    deflated solve of the same reduced system to the conditioning of the tolerance."""
+    if shape is not None:
+        monkeypatch.setenv("DBQ_DS_NB", shape[0])
+        monkeypatch.setenv("DBQ_DS_RG", shape[1])
     L = C["L"]
     lat, U = _setup()
     kappa = C["kappa"]
