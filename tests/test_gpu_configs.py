@@ -200,3 +200,44 @@ def test_c5_shift_sequence_projection_then_deflation(gpu_lib):
         Xh = host(X[0])
         assert max(_true_rel(U, lat, kc, m, Xh, B)) <= 1.0001e-8
         sols.append(Xh)
+
+
+def test_c5_shift_sequence_on_the_reduced_system(gpu_lib):
+    """The 8^4 twisted-mass shift sequence at kappa_c on the even-odd reduced system (as Sec. 4
+    solves it): GMRES-DR(30,10) of Ahat(mu = 0.02), each shift started from the minimal-residual
+    combination of the previous solutions on the new shift's reduced system, mixed D-BiCGStab on
+    Ahat; every full solution meets 1e-8 on A(mu) x = b (oracle residual), and one projection
+    matches the oracle's projection of that reduced system."""
+    from oracle import evenodd as EO
+    L = (8, 8, 8, 8)
+    lat = W.Lattice(L)
+    U = synth.gauge_field(L, 0.6, 105)
+    kc, _, res, st = gpu_lib.kappa_critical(L, dev(U), m=48, k=16, tol=1e-10)
+    assert st == 0
+    mus = [0.001 * 20 ** (j / 7) for j in range(8)][::-1]
+    _, V, _, gst = gpu_lib.gmresdr_first_rhs(L, dev(U), dev(synth.point_source(L)), kc, 30, 10,
+                                             mu=mus[0], tol=1e-8, schur=True)
+    assert gst["status"] == 0
+    B = synth.z2_sources(L, 3, 1105)
+    even = lat.parity == 0
+    sols = []
+    for i, m in enumerate(mus):
+        X0 = None
+        if sols:
+            Q = np.stack(sols, axis=1)
+            X0, r0, r1 = gpu_lib.project_shifts(L, dev(U), kc, m, dev(Q), dev(B), schur=True)
+            assert np.all(r1 <= r0 * (1 + 1e-12))
+            if i == 1:
+                A = EO.schur_operator(U, lat, kc, m)
+                for j in range(B.shape[0]):
+                    Qe = Q[j][:, even].reshape(Q.shape[1], -1).T
+                    bh = EO.schur_source(U, lat, kc, B[j], m)
+                    _, _, io = S.mr_project(A, Qe, bh)
+                    assert abs(r1[j] - io["rnorm_after"]) <= 1e-8 * io["rnorm_before"]
+        X, st, status = gpu_lib.dbicgstab_solve(
+            [dict(L=L, links=dev(U), kappa=kc, mu=m, B=dev(B), V=V, X0=X0, schur=True)],
+            tol=1e-8, prec="mixed", max_mv=100000)
+        assert status == 0, st
+        Xh = host(X[0])
+        assert max(_true_rel(U, lat, kc, m, Xh, B)) <= 1.0001e-8
+        sols.append(Xh)
