@@ -11,6 +11,9 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
                      U = gamma5 V (Sec. 1), set x0 += V y, then run BiCGStab.
 * ``mr_project``  -- Sec. 4: minimal-residual projection of a new shift's initial residual over the
                      solutions Q of previous shifts, x0 += Q d with d minimising ||r0 - A Q d||.
+* ``gmres_proj``  -- GMRES(m)-Proj(k), the comparison method of Sec. 1 and Sec. 3: cycles of
+                     restarted GMRES(m) alternating with a minimal-residual projection over the
+                     right eigenvectors V from GMRES-DR.
 
 All functions take the operator as a callable on flat complex128 vectors.  Statuses:
 OK = 0, NOT_CONVERGED = 1 (the paper's "F"), EBREAKDOWN = -2, ESINGULAR = -3.
@@ -305,6 +308,75 @@ def dbicgstab(A, b, V, g5, tol=1e-8, max_mv=20000, x0=None, dagger=False, cond_m
     x, info = bicgstab(A, b, x0=x, tol=tol, max_mv=max_mv, mv_start=mv - 1)
     info.update(setup_matvecs=k, cond=cond, left_proj=proj)
     return x, info
+
+
+# --------------------------------------------------------------------------- GMRES-Proj
+def gmres_proj(A, b, V, m, tol=1e-8, max_mv=20000, x0=None):
+    """GMRES(m)-Proj(k) (Sec. 1; compared with D-BiCGStab in Sec. 3): for a later right-hand side,
+    alternate a minimal-residual projection over the right eigenvectors V (n x k) -- x += V d,
+    d = argmin ||r - A V d|| -- with one cycle of GMRES(m) (Arnoldi with classical Gram-Schmidt
+    twice from r, x += V_m y with y = argmin ||beta e_1 - Hbar y||, r = V_{m+1}(beta e_1 - Hbar y)).
+    Convergence ||r|| <= tol ||b|| is tested after each projection and each cycle.  W = A V (k
+    products) is setup, reported apart from ``matvecs``.  Returns (x, info) with info =
+    dict(status, matvecs, cycles, setup_matvecs, rel_resid, resid_history)."""
+    b = np.asarray(b, dtype=np.complex128)
+    n = b.size
+    bn = _norm(b)
+    k = V.shape[1]
+    mv = 0
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.complex128)
+    if x0 is not None and np.any(x0 != 0):
+        r = b - A(x)
+        mv += 1
+    else:
+        r = b.copy()
+    W = np.stack([A(V[:, i]) for i in range(k)], axis=1) if k else np.zeros((n, 0), complex)
+    hist = [_norm(r)]
+    cycles = 0
+    status = NOT_CONVERGED
+    while True:
+        if k:
+            d = np.linalg.lstsq(W, r, rcond=None)[0]
+            x = x + V @ d
+            r = r - W @ d
+        rn = _norm(r)
+        hist.append(rn)
+        if rn <= tol * bn:
+            status = OK
+            break
+        if mv >= max_mv:
+            break
+        Vb = np.zeros((n, m + 1), dtype=np.complex128)
+        Hb = np.zeros((m + 1, m), dtype=np.complex128)
+        beta = rn
+        Vb[:, 0] = r / beta
+        for j in range(m):
+            w = A(Vb[:, j])
+            mv += 1
+            Vj = Vb[:, :j + 1]
+            h = Vj.conj().T @ w
+            w = w - Vj @ h
+            h2 = Vj.conj().T @ w
+            w = w - Vj @ h2
+            Hb[:j + 1, j] = h + h2
+            hn = _norm(w)
+            Hb[j + 1, j] = hn
+            Vb[:, j + 1] = w / hn
+        c = np.zeros(m + 1, dtype=np.complex128)
+        c[0] = beta
+        y = np.linalg.lstsq(Hb, c, rcond=None)[0]
+        x = x + Vb[:, :m] @ y
+        r = Vb @ (c - Hb @ y)
+        cycles += 1
+        rn = _norm(r)
+        hist.append(rn)
+        if rn <= tol * bn:
+            status = OK
+            break
+        if mv >= max_mv:
+            break
+    return x, dict(status=status, matvecs=mv, cycles=cycles, setup_matvecs=k,
+                   rel_resid=_norm(r) / bn, resid_history=hist)
 
 
 # --------------------------------------------------------------------------- MR projection

@@ -288,3 +288,55 @@ def test_link_force_matches_finite_differences(mu):
     g5 = lambda v: W.gamma5_flat(v, lat.V)
     lam2 = g5(np.linalg.solve(M5, g5(eta.reshape(-1))))
     assert np.allclose(lam2, lam.reshape(-1), atol=1e-11)
+
+
+# ----------------------------------------------------------------------------- GMRES-Proj
+def test_gmres_proj_first_cycle_is_the_krylov_minimal_residual():
+    """Without eigenvectors one GMRES(m) cycle from x0 = 0 gives the minimal residual over the
+    Krylov space span{b, Ab, ..., A^{m-1} b}, here by least squares on the explicit power basis."""
+    L = (2, 2, 2, 4)
+    lat, U, A = _setup(L, 0.6, 41, 0.12)
+    b = synth.gaussian_sources(L, 1, 42)[0].reshape(-1)
+    m = 5
+    x, info = S.gmres_proj(A, b, np.zeros((b.size, 0), complex), m, tol=1e-30, max_mv=m)
+    K = [b]
+    for _ in range(m - 1):
+        K.append(A(K[-1]))
+    K = np.stack(K, axis=1)
+    AK = np.stack([A(K[:, i]) for i in range(m)], axis=1)
+    y = np.linalg.lstsq(AK, b, rcond=None)[0]
+    r_ref = b - AK @ y
+    assert info["matvecs"] == m and info["cycles"] == 1
+    assert abs(np.linalg.norm(b - A(x)) - np.linalg.norm(r_ref)) <= 1e-10 * np.linalg.norm(b)
+    assert abs(info["rel_resid"] - np.linalg.norm(r_ref) / np.linalg.norm(b)) <= 1e-10
+
+
+def test_gmres_proj_projection_is_exact_on_the_range_of_AV():
+    """If b lies in span(A V) the first minimal-residual projection solves the system outright."""
+    L = (2, 2, 2, 4)
+    lat, U, A = _setup(L, 0.6, 43, 0.12)
+    n = lat.n
+    rng = np.random.default_rng(44)
+    V = np.linalg.qr(rng.standard_normal((n, 4)) + 1j * rng.standard_normal((n, 4)))[0]
+    c = rng.standard_normal(4) + 1j * rng.standard_normal(4)
+    b = np.stack([A(V[:, i]) for i in range(4)], axis=1) @ c
+    x, info = S.gmres_proj(A, b, V, 10, tol=1e-12)
+    assert info["status"] == S.OK and info["matvecs"] == 0 and info["cycles"] == 0
+    assert np.linalg.norm(x - V @ c) <= 1e-12 * np.linalg.norm(V @ c)
+
+
+def test_gmres_proj_matches_dense_solve_and_beats_plain_restarted_gmres():
+    """With GMRES-DR eigenvectors of the small eigenvalues, GMRES(m)-Proj(k) converges to the
+    dense solution in fewer products than GMRES(m) without projection."""
+    L = (4, 4, 4, 4)
+    lat, U, A = _setup(L, 0.3, 101, 0.139)   # near kappa_c = 0.140
+    b1 = synth.point_source(L)[0].reshape(-1)
+    _, V, _, _ = S.gmresdr(A, b1, 20, 6, tol=1e-10)
+    b = synth.z2_sources(L, 1, 1101)[0].reshape(-1)
+    x, info = S.gmres_proj(A, b, V, 20, tol=1e-10)
+    x0, info0 = S.gmres_proj(A, b, np.zeros((b.size, 0), complex), 20, tol=1e-10)
+    assert info["status"] == S.OK and info0["status"] == S.OK
+    assert np.linalg.norm(b - A(x)) <= 1.001e-10 * np.linalg.norm(b)
+    assert info["matvecs"] < info0["matvecs"]
+    assert info["matvecs"] % 20 == 0 and info["setup_matvecs"] == V.shape[1]
+    assert np.linalg.norm(x - x0) <= 1e-8 * np.linalg.norm(x0)
