@@ -225,6 +225,105 @@ def leg_c4(dbq, torch, synth):
     return {"16x16x16x16_gradient_nrhs8": info}
 
 
+def leg_f2(dbq, torch, synth):
+    """The trends of Tables 1-2 on the 16^4 field of the benchmark (kappa = 0.995 kappa_c), on the
+    even-odd reduced system the paper solves: GMRES-DR(k+20, k) on the point source to the
+    first-rhs tolerances L1/L2/L3 = 1e-8/1e-10/1e-14 for k = 10, 20, 30, then FP64 D-BiCGStab(k)
+    on one Z2 source to 1e-8; BiCGStab without deflation for reference.  MVPs = products of the
+    reduced operator."""
+    L = (16, 16, 16, 16)
+    U = torch.from_numpy(synth.gauge_field(L, 0.6, 102)).cuda()
+    kc, _, _, _ = dbq.kappa_critical(L, U, m=96, k=32, tol=1e-8)
+    kap = 0.995 * kc
+    b0 = torch.from_numpy(synth.point_source(L)).cuda()
+    b = torch.from_numpy(synth.z2_sources(L, 1, 1102)).cuda()
+    (_, st0, _), t0 = _timed(torch, lambda: dbq.dbicgstab_solve(
+        [dict(L=L, links=U, kappa=kap, B=b, V=None, schur=True)], tol=1e-8, prec="fp64"))
+    rows = [dict(k=0, first_rhs_tol=None, gmresdr_mvps=0,
+                 bicgstab_mvps=st0[0]["matvecs"], bicgstab_ms=round(t0 * 1e3, 2))]
+    for k in (10, 20, 30):
+        for tol1 in (1e-8, 1e-10, 1e-14):
+            (_, V, th, gst), tg = _timed(torch, lambda: dbq.gmresdr_first_rhs(
+                L, U, b0, kap, k + 20, k, tol=tol1, max_mv=40000, schur=True))
+            (_, st, status), td = _timed(torch, lambda: dbq.dbicgstab_solve(
+                [dict(L=L, links=U, kappa=kap, B=b, V=V, schur=True)], tol=1e-8, prec="fp64"))
+            rows.append(dict(k=k, k_out=int(V.shape[0]), first_rhs_tol=tol1,
+                             gmresdr_mvps=gst["matvecs"], gmresdr_status=gst["status_name"],
+                             gmresdr_s=round(tg, 2), bicgstab_mvps=st[0]["matvecs"],
+                             bicgstab_status=status, bicgstab_ms=round(td * 1e3, 2),
+                             smallest_theta=float(abs(th[0]))))
+            log(f"f2: {rows[-1]}")
+    return {"16x16x16x16_eigvec_accuracy_and_k": dict(kappa_c=kc, kappa=kap, rows=rows)}
+
+
+def leg_f3(dbq, torch, synth):
+    """The comparison of Sec. 3 (Fig. 3) on the 16^4 field of the benchmark at kappa = 0.995
+    kappa_c, on the even-odd reduced system, for one Z2 source to 1e-8 in FP64 with the GMRES-DR(60,20)
+    eigenvectors of the point source (first-rhs tolerance 1e-10): BiCGStab, GMRES(20)-Proj(20),
+    D-BiCGStab(20), and the mixed-precision D-BiCGStab(20) of this library."""
+    L = (16, 16, 16, 16)
+    U = torch.from_numpy(synth.gauge_field(L, 0.6, 102)).cuda()
+    kc, _, _, _ = dbq.kappa_critical(L, U, m=96, k=32, tol=1e-8)
+    kap = 0.995 * kc
+    b0 = torch.from_numpy(synth.point_source(L)).cuda()
+    b = torch.from_numpy(synth.z2_sources(L, 1, 1102)).cuda()
+    _, V, _, gst = dbq.gmresdr_first_rhs(L, U, b0, kap, 60, 20, tol=1e-10, schur=True)
+    rows = {}
+    runs = (("bicgstab", lambda: dbq.dbicgstab_solve(
+                [dict(L=L, links=U, kappa=kap, B=b, V=None, schur=True)], prec="fp64")),
+            ("gmres20_proj20", lambda: dbq.gmres_proj_solve(L, U, kap, b, V, m=20, schur=True,
+                                                            max_mv=40000)),
+            ("gmres20", lambda: dbq.gmres_proj_solve(L, U, kap, b, None, m=20, schur=True,
+                                                     max_mv=40000)),
+            ("dbicgstab20_fp64", lambda: dbq.dbicgstab_solve(
+                [dict(L=L, links=U, kappa=kap, B=b, V=V, schur=True)], prec="fp64")),
+            ("dbicgstab20_mixed", lambda: dbq.dbicgstab_solve(
+                [dict(L=L, links=U, kappa=kap, B=b, V=V, schur=True)], prec="mixed")))
+    for name, fn in runs:
+        fn()
+        (_, st, status), t = _timed(torch, fn)
+        rows[name] = dict(mvps=st[0]["matvecs"], status=status, ms=round(t * 1e3, 2),
+                          rel_true_resid=st[0]["rel_true_resid"])
+        log(f"f3 {name}: {rows[name]}")
+    return {"16x16x16x16_method_comparison": dict(kappa=kap, gmresdr_mvps=gst["matvecs"],
+                                                  runs=rows)}
+
+
+def leg_f4(dbq, torch, synth):
+    """The Table 3 experiment on 16^4 at kappa_c on the even-odd reduced system: 8 twisted masses
+    mu = 0.001 * 20^(j/7), each solved by GMRES-DR(40,10) from the minimal-residual combination of
+    the previous shifts' solutions (all of them, or only the last one), heaviest first and lightest
+    first; total products of the reduced operator per order."""
+    L = (16, 16, 16, 16)
+    U = torch.from_numpy(synth.gauge_field(L, 0.6, 102)).cuda()
+    kc, _, _, _ = dbq.kappa_critical(L, U, m=96, k=32, tol=1e-8)
+    b = torch.from_numpy(synth.z2_sources(L, 1, 1102)).cuda()
+    heavy_first = [0.001 * 20 ** (j / 7) for j in range(8)][::-1]
+    out = dict(kappa=kc, runs=[])
+    for name, mus, keep in (("heavy_to_light_all", heavy_first, 8),
+                            ("light_to_heavy_all", heavy_first[::-1], 8),
+                            ("heavy_to_light_last1", heavy_first, 1),
+                            ("heavy_to_light_none", heavy_first, 0)):
+        sols, per, tot = [], [], 0
+        t = time.perf_counter()
+        for m in mus:
+            x0 = None
+            if sols and keep > 0:
+                Q = torch.stack(sols[-keep:], dim=1)
+                x0, _, _ = dbq.project_shifts(L, U, kc, m, Q, b, schur=True)
+            x, _, _, gst = dbq.gmresdr_first_rhs(L, U, b, kc, 40, 10, mu=m, tol=1e-8,
+                                                 max_mv=40000, x0=x0, schur=True)
+            mv = gst["matvecs"] + (len(sols[-keep:]) if sols and keep > 0 else 0)
+            per.append(dict(mu=m, mvps=mv, status=gst["status_name"]))
+            tot += mv
+            sols.append(x)
+        torch.cuda.synchronize()
+        out["runs"].append(dict(order=name, total_mvps=tot, seconds=round(time.perf_counter() - t, 2),
+                                shifts=per))
+        log(f"f4 {name}: total {tot} MVPs")
+    return {"16x16x16x16_shift_order": out}
+
+
 def leg_c5(dbq, torch, synth, schur=False):
     """Twisted-mass shifts on 24^3 x 48 at kappa_c: 8 masses mu = 0.001 * 20^(j/7) from the
     heaviest, each started from the minimal-residual combination of the previous solutions and
@@ -279,7 +378,10 @@ def main():
     ap.add_argument("--extra", default="",
                     help="comma-separated extra workload legs, outside the timed steps: c3 "
                          "(20^3x32 and the uneven batch), c4 (16^4 gradient), c5 (24^3x48 "
-                         "twisted-mass shifts), c5eo (the same on the even-odd reduced system)")
+                         "twisted-mass shifts), c5eo (the same on the even-odd reduced system), "
+                         "f2 (eigenvector accuracy and k, Tables 1-2 trends), f3 (BiCGStab, "
+                         "GMRES(20)-Proj(20), D-BiCGStab(20), Fig. 3 comparison), f4 (shift order, "
+                         "Table 3 experiment)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB with a plain device copy (a known-size reference "
                          "for hardware byte counters)")
@@ -431,7 +533,8 @@ def main():
         out["even_odd_reduced_system"] = eo
         out["dslash_24x24x24x48"] = dslash_sweep(dbq, torch)
         log(f"dslash sweep: {out['dslash_24x24x24x48']}")
-    legs = {"c3": leg_c3, "c4": leg_c4, "c5": leg_c5, "c5eo": leg_c5eo}
+    legs = {"c3": leg_c3, "c4": leg_c4, "c5": leg_c5, "c5eo": leg_c5eo, "f2": leg_f2,
+            "f3": leg_f3, "f4": leg_f4}
     for name in [x for x in a.extra.split(",") if x]:
         if name not in legs:
             raise SystemExit(f"unknown leg {name}")

@@ -168,6 +168,18 @@ int dbicgstab_solve(dbq_ctx* ctx, const dbq_operator* ops, int32_t nops,
 int project_shifts(dbq_ctx* ctx, const dbq_operator* op_new, const void* Q, int32_t nq,
                    const void* B, void* X0, int32_t nrhs, double* rnorm_before_after);
 
+/* GMRES(m)-Proj(k), the comparison method of Sec. 1 and Sec. 3 for later right-hand sides: a
+ * minimal-residual projection over the right eigenvectors V (x += V d, d = argmin ||r - A V d||)
+ * alternating with cycles of GMRES(m) from the current residual, until ||r|| <= tol ||b|| (tested
+ * after each projection and each cycle) or max_mv products.  FP64, the right-hand sides one after
+ * another.  V: DEVICE complex128 column-major n x k as gmresdr_first_rhs returns it (k = 0: plain
+ * restarted GMRES(m)); B, X: DEVICE complex128 [nrhs][V][12] (X in: x0, out: solution);
+ * per_rhs: HOST stats (matvecs excludes the k products of the setup W = A V; iterations = GMRES
+ * cycles).  Requires 2 <= m <= 128, 0 <= k <= 128.  Accepts op->schur = 1 like dbicgstab_solve. */
+int gmres_proj_solve(dbq_ctx* ctx, const dbq_operator* op, const void* V, int32_t k,
+                     const void* B, void* X, int32_t nrhs, int32_t m, double tol, int64_t max_mv,
+                     dbq_stats* per_rhs);
+
 /* Gradient of L = sum_j Re(eta_j^H A^{-1} b_j) with respect to the links, given the solutions
  * x_j = A^{-1} b_j and the adjoint solutions lambda_j = A^{-H} eta_j (dL = -Re(lambda^H dA x)):
  *   G_mu(y) = kappa * sum_j sum_spin [ lambda(y) ((1-gamma_mu) x(y+mu))^H + x(y) ((1+gamma_mu) lambda(y+mu))^H ].

@@ -263,6 +263,40 @@ def project_shifts(L, links, kappa, mu, Q, B, X0=None, schur=False):
     return X.reshape(B.shape), r[:, 0], r[:, 1]
 
 
+def gmres_proj_solve(L, links, kappa, B, V=None, m=20, mu=0.0, tol=1e-8, max_mv=20000, X0=None,
+                     schur=False):
+    """GMRES(m)-Proj(k) for later right-hand sides B (nrhs, V, 4, 3) with the eigenvectors V
+    (k, V, 4, 3) of ``gmresdr_first_rhs`` (None: plain restarted GMRES(m)); FP64.
+    Returns (X, per-rhs stats list, overall status)."""
+    torch = _torch()
+    L, Vol = _lattice(L)
+    U = _links(links, Vol)
+    Bt = _spinors(B, Vol, "B")
+    X = torch.zeros_like(Bt) if X0 is None else _spinors(X0, Vol, "X0").clone()
+    if X.shape != Bt.shape:
+        raise ValueError("X0 must match B")
+    if not (2 <= int(m) <= 128):
+        raise ValueError("m must be in 2..128")
+    if V is not None:
+        Vd = _spinors(V, Vol, "V")
+        if Vd.shape[0] > 128:
+            raise ValueError("at most 128 eigenvectors")
+        vp, k = Vd.data_ptr(), Vd.shape[0]
+    else:
+        Vd, vp, k = None, None, 0
+    for t in (Bt, X) + ((Vd,) if Vd is not None else ()):
+        if t.device != U.device:
+            raise ValueError("all tensors must be on the links' device")
+    nrhs = Bt.shape[0]
+    stats = (Stats * nrhs)()
+    h = _ctx(U.device)
+    op = _operator(L, U, kappa, mu, schur)
+    st = _abi.load().gmres_proj_solve(h, ctypes.byref(op), vp, int(k), Bt.data_ptr(), X.data_ptr(),
+                                      nrhs, int(m), float(tol), int(max_mv), stats)
+    _check(st, h, ok=(0, 1))
+    return X.reshape(B.shape), [s.as_dict() for s in stats], st
+
+
 def link_force(L, links, kappa, lam, x, kind="su3"):
     """kind 'su3': real (4, V, 8) derivatives along U -> exp(i theta T_a) U;
     kind 'complex': complex (4, V, 3, 3) gradient G with dL = Re sum conj(G) dU."""

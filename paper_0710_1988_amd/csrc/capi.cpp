@@ -143,6 +143,14 @@ int project_shifts(dbq_ctx* c, const dbq_operator* op_new, const void* Q, int32_
   return guarded(c, [&]() { return dbq::mr_project(c, op_new, Q, nq, B, X0, nrhs, rnorm_before_after); });
 }
 
+int gmres_proj_solve(dbq_ctx* c, const dbq_operator* op, const void* V, int32_t k, const void* B,
+                     void* X, int32_t nrhs, int32_t m, double tol, int64_t max_mv,
+                     dbq_stats* per_rhs) {
+  return guarded(c, [&]() {
+    return dbq::gmres_proj(c, op, V, k, B, X, nrhs, m, tol, max_mv, per_rhs);
+  });
+}
+
 int link_force(dbq_ctx* c, const dbq_operator* op, const void* lambda, const void* x,
                int32_t nrhs, int32_t kind, void* F) {
   return guarded(c, [&]() {

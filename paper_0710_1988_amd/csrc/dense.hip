@@ -403,7 +403,7 @@ __global__ __launch_bounds__(NT) void k_cycle(CycleArgs a) {
   __shared__ int s_conv;
   const double2* H = a.Hbar;
 
-  if (a.mode == 0 || a.mode == 1) {
+  if (a.mode == 0 || a.mode == 1 || a.mode == 3) {
     // ---- least squares min || c - Hbar d || by Householder QR
     for (int i = t; i < m1 * m; i += NT) QR[i] = H[i];
     for (int i = t; i < m1; i += NT) gv[i] = a.c[i];
@@ -456,6 +456,7 @@ __global__ __launch_bounds__(NT) void k_cycle(CycleArgs a) {
       zd s = ld2(a.c, r);
       for (int j = 0; j < m; ++j) s = s - ld2(H, r + (long long)j * m1) * ld2(a.d, j);
       st2(rho, r, s);
+      if (a.mode == 3) st2(a.cnew, r, s);
       p += norm2(s);
     }
     const double rn = sqrt(wsum(p));
@@ -465,7 +466,7 @@ __global__ __launch_bounds__(NT) void k_cycle(CycleArgs a) {
       s_conv = (rn <= a.tol_abs) ? 1 : 0;
     }
     __syncthreads();
-    if (a.mode == 0 && s_conv) return;
+    if ((a.mode == 0 && s_conv) || a.mode == 3) return;
   }
 
   // ---- eigenproblem matrix G (m x m)

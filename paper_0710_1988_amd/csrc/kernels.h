@@ -220,12 +220,13 @@ struct CycleArgs {
   const double2* Hbar;  // (m+1) x m column-major, ld = m+1
   const double2* c;     // m+1
   int m, k;
-  int mode;             // 0: GMRES-DR restart, 1: GMRES-DR final vectors, 2: Ritz (largest Re)
+  int mode;             // 0: GMRES-DR restart, 1: GMRES-DR final vectors, 2: Ritz (largest Re),
+                        // 3: least squares only (GMRES(m) cycle; rho = c - Hbar d into cnew)
   double tol_abs;       // convergence threshold on ||rho|| (modes 0, 1)
   double2* d;           // out: m least-squares coefficients (modes 0, 1)
   double2* P;           // out: (m+1) x (k+1) column-major restart / output basis
   double2* Hnew;        // out: (k+1) x k, ld = m+1 (written into the first k columns)
-  double2* cnew;        // out: m+1
+  double2* cnew;        // out: m+1 (mode 3: rho)
   double2* theta;       // out: m eigenvalues sorted
   double* info;         // out: [0] ||rho||, [1] k_out, [2] converged flag, [3] ritz residual of
                         //      theta[0] (mode 2), [4] eigen-solver failure flag

@@ -16,6 +16,8 @@ int kappa_crit(dbq_ctx* c, const int32_t L[4], const void* links, int m, int k, 
                int64_t max_mv, double* kappa_c, double* lambda, double* resid);
 int mr_project(dbq_ctx* c, const dbq_operator* o, const void* Q, int nq, const void* B, void* X0,
                int nrhs, double* rn);
+int gmres_proj(dbq_ctx* c, const dbq_operator* o, const void* V, int k, const void* B, void* X,
+               int nrhs, int m, double tol, int64_t max_mv, dbq_stats* st);
 void force(dbq_ctx* c, const dbq_operator* o, const void* lambda, const void* x, int nrhs,
            int kind, void* F);
 

@@ -1430,6 +1430,172 @@ int mr_project(dbq_ctx* c, const dbq_operator* o, const void* Q, int nq, const v
   return DBQ_OK;
 }
 
+// ============================================================================ GMRES(m)-Proj(k)
+// The comparison method of Sec. 1 and Sec. 3 for later right-hand sides: a minimal-residual
+// projection over the right eigenvectors V from GMRES-DR (d = argmin ||r - A V d||, x += V d; W = A V
+// factorised once as Qw R by classical Gram-Schmidt twice, so a projection is r -= Qw Qw^H r and
+// x += V R^{-1} Qw^H r, no products) alternating with cycles of GMRES(m) from the current r.
+// FP64, right-hand sides one after another.
+int gmres_proj(dbq_ctx* c, const dbq_operator* o, const void* Vin, int k, const void* B, void* X,
+               int nrhs, int m, double tol, int64_t max_mv, dbq_stats* st) {
+  const double t0 = now_s();
+  check_op(o);
+  DBQ_CHECK(B && X && st, "null argument");
+  DBQ_CHECK(k >= 0 && k <= 128, "k must be in 0..128");
+  DBQ_CHECK(k == 0 || Vin, "null eigenvectors");
+  DBQ_CHECK(m >= 2 && m <= 128, "m must be in 2..128");
+  DBQ_CHECK(nrhs >= 1, "nrhs must be >= 1");
+  DBQ_CHECK(tol > 0 && std::isfinite(tol), "tol must be positive");
+  DBQ_CHECK(max_mv >= 1, "max_mv must be >= 1");
+  hipStream_t s = c->stream;
+  WsScope ws(c);
+  Op op = make_op(c, ws, o, true, false);
+  const long long n = op.n(), Vs = op.sites();
+  double2* b64 = ws.get<double2>(size_t(nrhs) * n);
+  double2* x64 = ws.get<double2>(size_t(nrhs) * n);
+  double2* bodd = nullptr;
+  const size_t nwf = norm_work(op.nfull(), nrhs);
+  double* wf = ws.get<double>(nwf);
+  double* dn = ws.get<double>(2 * nrhs + 8);
+  if (op.schur) {
+    double2* bfull = ws.get<double2>(size_t(nrhs) * op.nfull());
+    bodd = ws.get<double2>(size_t(nrhs) * n);
+    pack_spinor_f64(s, op.g, B, bfull, nrhs);
+    norm2_f64(s, bfull, op.nfull(), nrhs, op.nfull(), dn, wf, nwf);
+    schur_rhs(c, ws, op, bfull, b64, bodd, nrhs, 0);
+    pack_even_f64(c, ws, op, X, x64, nrhs);
+  } else {
+    pack_spinor_f64(s, op.g, B, b64, nrhs);
+    pack_spinor_f64(s, op.g, X, x64, nrhs);
+    norm2_f64(s, b64, n, nrhs, n, dn, wf, nwf);
+  }
+  norm2_f64(s, x64, n, nrhs, n, dn + nrhs, wf, nwf);
+  double* hp = (double*)pinned_get(c, sizeof(double) * (2 * nrhs + 16));
+  DBQ_HIP(hipMemcpyAsync(hp, dn, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, s));
+  DBQ_HIP(hipStreamSynchronize(s));
+  std::vector<double> bn(nrhs), xn(nrhs);
+  for (int j = 0; j < nrhs; ++j) {
+    bn[j] = std::sqrt(hp[j]);
+    xn[j] = hp[nrhs + j];
+    DBQ_CHECK(std::isfinite(hp[j]) && std::isfinite(hp[nrhs + j]), "non-finite b or x0");
+  }
+  Arnoldi ar(c, ws, &op, m, 1);
+  const size_t gw = gram_work_elems(n, std::max(k, 1), 1);
+  double* gwork = ws.get<double>(gw);
+  // ---- setup: W = A V (k products), W = Qw R
+  double2 *Vp = nullptr, *Qw = nullptr, *R = nullptr, *z = nullptr, *h1 = nullptr, *h2 = nullptr;
+  if (k > 0) {
+    Vp = ws.get<double2>(size_t(k) * n);
+    Qw = ws.get<double2>(size_t(k) * n);
+    R = ws.get<double2>(size_t(k) * k);
+    z = ws.get<double2>(k);
+    h1 = ws.get<double2>(k);
+    h2 = ws.get<double2>(k);
+    if (op.schur) pack_even_f64(c, ws, op, Vin, Vp, k);
+    else pack_spinor_f64(s, op.g, Vin, Vp, k);
+    const DsBatch bw = make_batch({DsSpec{&op, false, Vp, Qw, nullptr, k, 0}});
+    run_dslash(c, false, bw, 0, EPI_NONE, nullptr, nullptr);
+    zero_f64(s, R, size_t(k) * k);
+    double* nq = dn + 2 * nrhs;
+    for (int q = 0; q < k; ++q) {
+      double2* w = Qw + size_t(q) * n;
+      if (q > 0) {
+        gram_f64(s, Qw, n, q, w, n, 1, n, Vs, 0, h1, gwork, gw);
+        combine_f64(s, Qw, n, q, h1, q, w, n, 1, n, Vs, 0, -1);
+        gram_f64(s, Qw, n, q, w, n, 1, n, Vs, 0, h2, gwork, gw);
+        combine_f64(s, Qw, n, q, h2, q, w, n, 1, n, Vs, 0, -1);
+      }
+      norm2_f64(s, w, n, 1, n, nq, ar.nwork, ar.nw);
+      write_col_f64(s, R, k, q, q, h1, h2, nq, q);
+      scale_f64(s, w, w, n, nq);
+    }
+  }
+  double2* r = ws.get<double2>(n);
+  double* rn2 = dn + 2 * nrhs + 1;
+  for (int j = 0; j < nrhs; ++j) {
+    double2* bj = b64 + size_t(j) * n;
+    double2* xj = x64 + size_t(j) * n;
+    int64_t mv = 0;
+    int cycles = 0;
+    if (xn[j] > 0) {
+      const DsBatch bx = make_batch({DsSpec{&op, false, xj, r, nullptr, 1, 0}});
+      run_dslash(c, false, bx, 0, EPI_NONE, nullptr, nullptr);
+      sub_f64(s, bj, r, r, n);
+      mv += 1;
+    } else {
+      copy_f64(s, bj, r, n);
+    }
+    bool conv = false;
+    double rel = 0.0;
+    if (bn[j] == 0.0) {
+      zero_f64(s, xj, n);
+      conv = true;
+    }
+    while (!conv) {
+      if (k > 0) {
+        gram_f64(s, Qw, n, k, r, n, 1, n, Vs, 0, z, gwork, gw);
+        combine_f64(s, Qw, n, k, z, k, r, n, 1, n, Vs, 0, -1);
+        dense_trsolve_upper(s, R, k, k, z, 1, k);
+        combine_f64(s, Vp, n, k, z, k, xj, n, 1, n, Vs, 0, 1);
+      }
+      norm2_f64(s, r, n, 1, n, rn2, ar.nwork, ar.nw);
+      DBQ_HIP(hipMemcpyAsync(hp, rn2, sizeof(double), hipMemcpyDeviceToHost, s));
+      DBQ_HIP(hipStreamSynchronize(s));
+      rel = std::sqrt(hp[0]) / bn[j];
+      if (!std::isfinite(rel)) throw Error(DBQ_EBREAKDOWN, "GMRES-Proj residual is not finite");
+      if (rel <= tol) {
+        conv = true;
+        break;
+      }
+      if (mv >= max_mv) break;
+      // one GMRES(m) cycle from r
+      scale_f64(s, r, ar.col(0), n, rn2);
+      set_e1_f64(s, ar.cv, m + 1, rn2);
+      ar.extend(0);
+      mv += m;
+      ar.cycle_end(1, 3, tol * bn[j]);
+      combine_f64(s, ar.Vb, n, m, ar.d, m, xj, n, 1, n, Vs, 0, 1);
+      combine_f64(s, ar.Vb, n, m + 1, ar.cnew, m + 1, r, n, 1, n, Vs, 0, 0);
+      ++cycles;
+      DBQ_HIP(hipMemcpyAsync(hp, ar.info, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+      DBQ_HIP(hipStreamSynchronize(s));
+      rel = hp[0] / bn[j];
+      if (!std::isfinite(rel)) throw Error(DBQ_EBREAKDOWN, "GMRES-Proj residual is not finite");
+      if (rel <= tol) {
+        conv = true;
+        break;
+      }
+      if (mv >= max_mv) break;
+    }
+    // true residual for the statistics (not charged)
+    const DsBatch bx = make_batch({DsSpec{&op, false, xj, r, nullptr, 1, 0}});
+    run_dslash(c, false, bx, 0, EPI_NONE, nullptr, nullptr);
+    sub_f64(s, bj, r, r, n);
+    norm2_f64(s, r, n, 1, n, rn2, ar.nwork, ar.nw);
+    DBQ_HIP(hipMemcpyAsync(hp, rn2, sizeof(double), hipMemcpyDeviceToHost, s));
+    DBQ_HIP(hipStreamSynchronize(s));
+    dbq_stats& o2 = st[j];
+    o2.matvecs = mv;
+    o2.iterations = cycles;
+    o2.restarts = 0;
+    o2.reliable_updates = 0;
+    o2.rel_true_resid = bn[j] > 0 ? std::sqrt(hp[0]) / bn[j] : 0.0;
+    o2.status = conv ? DBQ_OK : DBQ_NOT_CONVERGED;
+    o2.pad = 0;
+  }
+  if (op.schur) schur_solution(c, ws, op, x64, bodd, X, nrhs, 0);
+  else unpack_spinor_f64(s, op.g, x64, X, nrhs);
+  DBQ_HIP(hipStreamSynchronize(s));
+  timer_collect(c);
+  const double secs = now_s() - t0;
+  int worst = DBQ_OK;
+  for (int j = 0; j < nrhs; ++j) {
+    st[j].seconds = secs;
+    worst = std::max(worst, int(st[j].status));
+  }
+  return worst;
+}
+
 // ============================================================================ link force
 void force(dbq_ctx* c, const dbq_operator* o, const void* lambda, const void* x, int nrhs,
            int kind, void* F) {

@@ -336,3 +336,57 @@ def test_autograd_matches_finite_differences(gpu_lib):
     fd = (Lval(U, b + h * d) - Lval(U, b - h * d)) / (2 * h)
     an = float(np.real(np.vdot(gb, d)))
     assert abs(fd - an) <= 1e-5 * abs(fd)
+
+
+# ----------------------------------------------------------------------------- GMRES-Proj
+@pytest.mark.parametrize("use_v", [True, False])
+def test_gmres_proj_matches_oracle(gpu_lib, use_v):
+    """GMRES(20)-Proj(6) with the GPU's GMRES-DR eigenvectors (and plain GMRES(20)) on 4^4 near
+    kappa_c: the oracle, given the same eigenvectors, needs the same number of cycles (within one)
+    and reaches the same solution; products are 20 per cycle."""
+    L = (4, 4, 4, 4)
+    lat = W.Lattice(L)
+    U = synth.gauge_field(L, 0.3, 101)
+    kappa = 0.139
+    _, V, _, _ = gpu_lib.gmresdr_first_rhs(L, dev(U), dev(synth.point_source(L)), kappa, 20, 6,
+                                           tol=1e-10)
+    B = synth.z2_sources(L, 2, 1101)
+    X, st, status = gpu_lib.gmres_proj_solve(L, dev(U), kappa, dev(B), V if use_v else None, m=20,
+                                             tol=1e-10, max_mv=4000)
+    assert status == 0
+    A = W.operator(U, lat, kappa)
+    Vh = host(V).reshape(V.shape[0], -1).T if use_v else np.zeros((lat.n, 0), complex)
+    Xh = host(X)
+    for j in range(2):
+        b = B[j].reshape(-1)
+        xo, io = S.gmres_proj(A, b, Vh, 20, tol=1e-10, max_mv=4000)
+        assert io["status"] == S.OK
+        assert st[j]["matvecs"] == 20 * st[j]["iterations"]
+        assert abs(st[j]["iterations"] - io["cycles"]) <= 1
+        assert _true_rel(U, lat, kappa, 0.0, Xh[j].reshape(-1), b) <= 1.0001e-10
+        assert np.linalg.norm(Xh[j].reshape(-1) - xo) <= 1e-7 * np.linalg.norm(xo)
+
+
+def test_gmres_proj_on_the_reduced_system(gpu_lib):
+    """GMRES(20)-Proj(6) on the even-odd reduced system: the full solution meets the tolerance and
+    the oracle's run on the Schur complement with the same eigenvectors takes the same cycles."""
+    from oracle import evenodd as EO
+    L = (4, 4, 4, 4)
+    lat = W.Lattice(L)
+    U = synth.gauge_field(L, 0.3, 101)
+    kappa = 0.139
+    _, V, _, _ = gpu_lib.gmresdr_first_rhs(L, dev(U), dev(synth.point_source(L)), kappa, 20, 6,
+                                           tol=1e-10, schur=True)
+    B = synth.z2_sources(L, 1, 1101)
+    X, st, status = gpu_lib.gmres_proj_solve(L, dev(U), kappa, dev(B), V, m=20, tol=1e-10,
+                                             max_mv=4000, schur=True)
+    assert status == 0
+    assert _true_rel(U, lat, kappa, 0.0, host(X)[0].reshape(-1), B[0].reshape(-1)) <= 1.0001e-10
+    even = lat.parity == 0
+    Ve = host(V).reshape(V.shape[0], lat.V, 4, 3)[:, even].reshape(V.shape[0], -1).T
+    A = EO.schur_operator(U, lat, kappa)
+    bh = EO.schur_source(U, lat, kappa, B[0])
+    _, io = S.gmres_proj(A, bh, Ve, 20, tol=1e-10 * np.linalg.norm(B[0]) / np.linalg.norm(bh),
+                         max_mv=4000)
+    assert io["status"] == S.OK
+    assert abs(st[0]["iterations"] - io["cycles"]) <= 1
