@@ -163,6 +163,17 @@ def even_odd(dbq, torch, L, U, kappa, B, m, k, tol, steps):
     return out
 
 
+def leg_c2eo(dbq, torch, synth):
+    """The benchmark's 16^4 problem (links exp(0.6 iQ) seed 102, kappa = 0.995 kappa_c, 12 Z2
+    sources seed 1102, tol 1e-8) on the even-odd reduced system, as a leg of its own."""
+    L = (16, 16, 16, 16)
+    U = torch.from_numpy(synth.gauge_field(L, 0.6, 102)).cuda()
+    kc, _, _, _ = dbq.kappa_critical(L, U, m=96, k=32, tol=1e-8)
+    B = torch.from_numpy(synth.z2_sources(L, 12, 1102)).cuda()
+    return {"16x16x16x16_nrhs12_even_odd": even_odd(dbq, torch, L, U, 0.995 * kc, B, 60, 20, 1e-8,
+                                                      2)}
+
+
 def synth_point(L):
     import synth
     return synth.point_source(L)
@@ -376,7 +387,8 @@ def main():
     ap.add_argument("--dslash-only", action="store_true",
                     help="only the 24^3 x 48 Dslash bandwidth sweep (one JSON line)")
     ap.add_argument("--extra", default="",
-                    help="comma-separated extra workload legs, outside the timed steps: c3 "
+                    help="comma-separated extra workload legs, outside the timed steps: c2eo "
+                         "(the benchmark problem on the even-odd reduced system), c3 "
                          "(20^3x32 and the uneven batch), c4 (16^4 gradient), c5 (24^3x48 "
                          "twisted-mass shifts), c5eo (the same on the even-odd reduced system), "
                          "f2 (eigenvector accuracy and k, Tables 1-2 trends), f3 (BiCGStab, "
@@ -533,8 +545,8 @@ def main():
         out["even_odd_reduced_system"] = eo
         out["dslash_24x24x24x48"] = dslash_sweep(dbq, torch)
         log(f"dslash sweep: {out['dslash_24x24x24x48']}")
-    legs = {"c3": leg_c3, "c4": leg_c4, "c5": leg_c5, "c5eo": leg_c5eo, "f2": leg_f2,
-            "f3": leg_f3, "f4": leg_f4}
+    legs = {"c2eo": leg_c2eo, "c3": leg_c3, "c4": leg_c4, "c5": leg_c5, "c5eo": leg_c5eo,
+            "f2": leg_f2, "f3": leg_f3, "f4": leg_f4}
     for name in [x for x in a.extra.split(",") if x]:
         if name not in legs:
             raise SystemExit(f"unknown leg {name}")
