@@ -494,10 +494,29 @@ __global__ __launch_bounds__(NT) void k_cycle(CycleArgs a) {
     for (int r = t; r < m; r += NT) st2(G, r + (long long)(m - 1) * m, ld2(G, r + (long long)(m - 1) * m) + h2 * ld2(f, r));
     __syncthreads();
   }
-  hessenberg(G, Z, m);
+  // The Hessenberg reduction and the QR iteration touch the whole matrix after every Givens
+  // rotation: for m <= 64 they run on a copy in LDS (two 64 x 64 complex matrices, 128 KiB)
+  // instead of through the caches.
+  constexpr int LDS_M = 64;
+  __shared__ double2 sGZ[2 * LDS_M * LDS_M];
+  const bool in_lds = m <= LDS_M;
+  double2* Gw = in_lds ? sGZ : G;
+  double2* Zw = in_lds ? sGZ + m * m : Z;
+  if (in_lds) {
+    for (int i = t; i < m * m; i += NT) Gw[i] = G[i];
+    __syncthreads();
+  }
+  hessenberg(Gw, Zw, m);
   __syncthreads();
-  const bool ok = schur(G, Z, m);
+  const bool ok = schur(Gw, Zw, m);
   __syncthreads();
+  if (in_lds) {
+    for (int i = t; i < m * m; i += NT) {
+      G[i] = Gw[i];
+      Z[i] = Zw[i];
+    }
+    __syncthreads();
+  }
   if (t == 0) a.info[4] = ok ? 0.0 : 1.0;
   // ---- sort eigenvalues: |theta| ascending (harmonic) or Re descending (Ritz)
   for (int i = t; i < m; i += NT) {
