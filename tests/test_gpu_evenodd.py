@@ -235,3 +235,21 @@ def test_link_force_rejects_the_reduced_operator(gpu_lib):
     st = _abi.load().link_force(h, ctypes.byref(op), xd.data_ptr(), xd.data_ptr(), 1, 0,
                                 F.data_ptr())
     assert st == -1
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("mixed", 2e-6)])
+def test_schur_apply_full_size_24x48_sampled_sites(gpu_lib, prec, tol):
+    """24^3 x 48 (the twisted-mass lattice), twisted mass and the dagger: every even site computed
+    on the GPU, 256 sampled even sites (first and last included) recomputed by the oracle."""
+    L = (24, 24, 24, 48)
+    lat = W.Lattice(L)
+    U = synth.gauge_field(L, 0.6, 105)
+    psi = synth.z2_sources(L, 1, 1105)
+    out = host(gpu_lib.wilson_apply(L, dev(U), dev(psi), 0.2089, 0.003, True, prec,
+                                    schur=True))[0]
+    ev = np.nonzero(lat.parity == 0)[0]
+    pick = np.sort(np.random.default_rng(6).choice(ev, 256, replace=False))
+    pick[0], pick[-1] = ev[0], ev[-1]
+    want = EO.schur_apply_sites(U, lat, 0.2089, _even(lat, psi[0]), pick, 0.003, True)
+    assert relerr(out[pick], want) <= tol
+    assert np.all(_odd(lat, out) == 0)
