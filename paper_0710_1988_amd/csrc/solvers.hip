@@ -797,7 +797,9 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
     // x64 += x32 and the FP64 residual; the residual's finalize stops the converged ones and the
     // others continue from the replaced residual.  The host only polls for rhs that finished,
     // broke down or ran out of MVPs, at intervals that double up to 32 iterations.
-    int every = 4;
+    // (every = 8: on 16^4 with 12 sources 2, 4, 6 and 8 give the same iterations and products;
+    // 8 launches the gated FP64 residual half as often as 4 and is 1.5% faster per source)
+    int every = 8;
     if (const char* e = std::getenv("DBQ_RELUP_EVERY")) every = std::max(1, std::atoi(e));
     DsBatch bres_dec = bres;
     bres_dec.decide = 1;

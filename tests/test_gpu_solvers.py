@@ -390,3 +390,27 @@ def test_gmres_proj_on_the_reduced_system(gpu_lib):
                          max_mv=4000)
     assert io["status"] == S.OK
     assert abs(st[0]["iterations"] - io["cycles"]) <= 1
+
+
+def test_mixed_solve_beyond_fp32_range_continues_in_fp64(gpu_lib):
+    """Sources scaled by 1e25: the squares in the FP32 iteration's dot products overflow, the
+    iteration reports non-finite values, and every rhs is finished by the FP64 continuation with
+    the same deflation space; the solutions are the scaled FP64 ones."""
+    L = (4, 4, 4, 4)
+    lat = W.Lattice(L)
+    U = synth.gauge_field(L, 0.3, 101)
+    kappa = 0.13
+    _, V, _, _ = gpu_lib.gmresdr_first_rhs(L, dev(U), dev(synth.point_source(L)), kappa, 20, 6,
+                                           tol=1e-10)
+    B = synth.z2_sources(L, 2, 1101)
+    X, st, status = gpu_lib.dbicgstab_solve(
+        [dict(L=L, links=dev(U), kappa=kappa, B=dev(B * 1e25), V=V)], tol=1e-8, prec="mixed")
+    assert status == 0, st
+    X1, st1, status1 = gpu_lib.dbicgstab_solve(
+        [dict(L=L, links=dev(U), kappa=kappa, B=dev(B), V=V)], tol=1e-10, prec="fp64")
+    assert status1 == 0
+    Xh, X1h = host(X[0]), host(X1[0])
+    for j in range(2):
+        b = (B[j] * 1e25).reshape(-1)
+        assert _true_rel(U, lat, kappa, 0.0, Xh[j].reshape(-1), b) <= 1.0001e-8
+        assert np.linalg.norm(Xh[j] - 1e25 * X1h[j]) <= 1e-6 * np.linalg.norm(1e25 * X1h[j])
