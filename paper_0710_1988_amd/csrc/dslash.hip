@@ -1393,7 +1393,6 @@ void launch_half(hipStream_t s, DsBatch& b, int step, int dagger, int epi, RhsSc
     DsLat& L = b.lat[i];
     DBQ_CHECK(L.g.V % 2 == 0, "dslash (half): odd volume");
     DBQ_CHECK(L.in && L.out, "dslash (half): null vector");
-    DBQ_CHECK(step == 2 || epi == EPI_NONE, "dslash (half): bad epilogue");
     DBQ_CHECK(!((epi == EPI_RHAT || epi == EPI_RESID) && !L.aux), "dslash (half): null aux");
     L.blk_begin = int(blk);
     if (tiled) {
