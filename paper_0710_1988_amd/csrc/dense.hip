@@ -274,20 +274,27 @@ __device__ bool schur(double2* G, double2* Z, int n) {
           x = ld2(G, kk + (long long)(kk - 1) * n);
           y = ld2(G, (kk + 1) + (long long)(kk - 1) * n);
         }
-        const double ax = cabs_(x), rho = hypot(ax, cabs_(y));
+        // c = |x| / rho, s = (x / |x|) conj(y) / rho, rho = sqrt(|x|^2 + |y|^2): two square roots
+        // and two reciprocals that do not depend on each other (the entries are far from the
+        // range limits, so no hypot-style scaling is needed; this chain is the critical path of
+        // every rotation)
+        const double nx = x.re * x.re + x.im * x.im, ny = y.re * y.re + y.im * y.im;
         double c;
         zd s;
-        if (rho == 0.0) {
+        if (nx + ny == 0.0) {
           c = 1.0;
           s = zd{0.0, 0.0};
-        } else if (ax == 0.0) {
+        } else if (nx == 0.0) {
           c = 0.0;
           s = zd{1.0, 0.0};
         } else {
-          c = ax / rho;
-          const zd ph{x.re / ax, x.im / ax};
+          const double ax = sqrt(nx);
+          const double irho = 1.0 / sqrt(nx + ny);
+          const double iax = 1.0 / ax;
+          c = ax * irho;
+          const zd ph{x.re * iax, x.im * iax};
           s = ph * conj(y);
-          s = zd{s.re / rho, s.im / rho};
+          s = zd{s.re * irho, s.im * irho};
         }
         s_c = c;
         s_s = make_double2(s.re, s.im);
