@@ -33,28 +33,31 @@ HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "dslash_f32_batched_16x16x16x16_nrhs12_counters.md")
 KERNEL_SOURCES = ("paper_0710_1988_amd/csrc/dslash.hip", "paper_0710_1988_amd/csrc/kernels.h",
                   "paper_0710_1988_amd/csrc/common.h")
+UPDATE_SOURCES = ("paper_0710_1988_amd/csrc/bicg.hip", "paper_0710_1988_amd/csrc/kernels.h",
+                  "paper_0710_1988_amd/csrc/common.h")
 
 
-def kernel_digest():
+def kernel_digest(files=KERNEL_SOURCES):
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def counter_traffic():
-    """Scaled FETCH_SIZE + WRITE_SIZE bytes per FP32 Dslash launch from the committed counter
+def counter_traffic(key="DSLASH_F32_TRAFFIC_BYTES_PER_LAUNCH", digest_key="KERNEL_SOURCE_SHA256",
+                    files=KERNEL_SOURCES):
+    """Scaled FETCH_SIZE + WRITE_SIZE bytes per launch of one kernel from the committed counter
     summary, or None when the summary is missing or the kernel sources changed since."""
     try:
         txt = open(COUNTERS).read()
     except OSError:
         return None, "no counter summary"
-    m_t = re.search(r"^DSLASH_F32_TRAFFIC_BYTES_PER_LAUNCH = (\d+)", txt, re.M)
-    m_h = re.search(r"^KERNEL_SOURCE_SHA256 = ([0-9a-f]{64})", txt, re.M)
+    m_t = re.search(r"^" + key + r" = (\d+)", txt, re.M)
+    m_h = re.search(r"^" + digest_key + r" = ([0-9a-f]{64})", txt, re.M)
     if not (m_t and m_h):
         return None, "counter summary incomplete"
-    if m_h.group(1) != kernel_digest():
+    if m_h.group(1) != kernel_digest(files):
         return None, "kernel sources changed since the counters were taken"
     return float(m_t.group(1)), "profiles/" + os.path.basename(COUNTERS)
 
@@ -465,6 +468,7 @@ def main():
     dbq.set_timing(False)
     ms32, n32, by32 = dbq.kernel_time(1)
     ms64, n64, by64 = dbq.kernel_time(0)
+    msu, nu, byu = dbq.kernel_time(2)
     ms_step = (t1 - t0) * 1e3 / a.steps
     worst = max(s["rel_true_resid"] for s in stats)
     ok = all(s["status"] == 0 for s in stats)
@@ -474,6 +478,10 @@ def main():
     avg_us = ms32 / max(n32, 1) * 1e3
     ach = by32 / max(n32, 1) / (avg_us * 1e-6) / 1e9 if n32 else 0.0
     traffic, traffic_src = counter_traffic()
+    u_us = msu / max(nu, 1) * 1e3
+    u_ach = byu / max(nu, 1) / (u_us * 1e-6) / 1e9 if nu else 0.0
+    u_traffic, u_src = counter_traffic("UPDATE_F32_TRAFFIC_BYTES_PER_LAUNCH",
+                                       "UPDATE_SOURCE_SHA256", UPDATE_SOURCES)
     out = {
         "metric": METRIC,
         "value": round(ms_step / nrhs, 4),
@@ -504,6 +512,17 @@ def main():
                                "12 rhs per launch; working set MALL-resident at 16^4)",
                      "avg_launch_us": round(avg_us, 2), "launches": n32,
                      "algorithmic_MB_per_launch": round(by32 / max(n32, 1) / 1e6, 2)},
+        # the second-largest kernel of the step by time (the Dslash launches take the most)
+        "roofline_update_step": {"bound": "hbm", "achieved": round(u_ach, 1),
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": round(u_ach / HBM_PEAK_GBS, 4),
+                                 "traffic": None if u_traffic is None else round(u_traffic),
+                                 "traffic_source": u_src,
+                                 "kernel": "FP32 BiCGStab update k_bicg_step XR (x += alpha p + "
+                                           "omega s, r = s - omega t, <rhat, r>, |r|^2; 7 vector "
+                                           "passes per active rhs)",
+                                 "avg_launch_us": round(u_us, 2), "launches": nu,
+                                 "algorithmic_MB_per_launch": round(byu / max(nu, 1) / 1e6, 2)},
         "fp64_dslash_in_step": {"launches": n64,
                                 "avg_launch_us": round(ms64 / max(n64, 1) * 1e3, 2)},
         "setup": {"kappa_c_s": round(t_kc, 3), "gmresdr_s": round(t_gd, 3),

@@ -124,7 +124,8 @@ __global__ __launch_bounds__(BL_BS) void k_bicg_step(VecSet vs, E* __restrict__ 
                                                      E* __restrict__ p, const E* __restrict__ v,
                                                      const E* __restrict__ t,
                                                      RhsScal* __restrict__ sc,
-                                                     double* __restrict__ partials) {
+                                                     double* __restrict__ partials,
+                                                     unsigned long long* __restrict__ acct) {
   typedef typename ET<E>::R R;
   constexpr int NC = ET<E>::NC;
   const int lb = xcd_block(blockIdx.x, vs.nblocks);
@@ -132,6 +133,9 @@ __global__ __launch_bounds__(BL_BS) void k_bicg_step(VecSet vs, E* __restrict__ 
   const int rhs = bm.x, ch = bm.y;
   const bool act = sc[rhs].active != 0;
   double red[3] = {0.0, 0.0, 0.0};
+  // byte accounting (timing only): reads x, p, s, t, rhat and writes x, r of an active rhs
+  if (OP == BI_XR && acct && act && ch == 0 && threadIdx.x == 0)
+    atomicAdd(acct, 7ull * (unsigned long long)vs.nelem[rhs] * sizeof(E));
   if (act) {
     const long long base = vs.off[rhs];
     const int ne = vs.nelem[rhs];
@@ -379,22 +383,20 @@ __global__ __launch_bounds__(BL_BS) void k_xacc(VecSet vs, VecSet vs64, double2*
 
 template <typename E>
 void step(hipStream_t s, int op, const VecSet& vs, E* x, E* r, const E* rhat, E* p, const E* v,
-          const E* t, RhsScal* sc, double* partials) {
+          const E* t, RhsScal* sc, double* partials, unsigned long long* acct) {
   dim3 g(vs.nblocks), b(BL_BS);
   switch (op) {
     case BI_P:
       hipLaunchKernelGGL((k_bicg_step<E, BI_P>), g, b, 0, s, vs, x, r, rhat, p, v, t, sc,
-                         partials);
+                         partials, nullptr);
       break;
     case BI_S:
       hipLaunchKernelGGL((k_bicg_step<E, BI_S>), g, b, 0, s, vs, x, r, rhat, p, v, t, sc,
-                         partials);
+                         partials, nullptr);
       break;
     default:
       hipLaunchKernelGGL((k_bicg_step<E, BI_XR>), g, b, 0, s, vs, x, r, rhat, p, v, t, sc,
-                         partials);
-      DBQ_HIP(hipGetLastError());
-      hipLaunchKernelGGL(k_fin_xr, dim3(fin_blocks(vs)), b, 0, s, vs, sc, partials);
+                         partials, acct);
       break;
   }
   DBQ_HIP(hipGetLastError());
@@ -405,12 +407,16 @@ void step(hipStream_t s, int op, const VecSet& vs, E* x, E* r, const E* rhat, E*
 void bicg_step_f64(hipStream_t s, int op, const VecSet& vs, double2* x, double2* r,
                    const double2* rhat, double2* p, const double2* v, const double2* t,
                    RhsScal* sc, double* partials) {
-  step<double2>(s, op, vs, x, r, rhat, p, v, t, sc, partials);
+  step<double2>(s, op, vs, x, r, rhat, p, v, t, sc, partials, nullptr);
 }
 void bicg_step_f32(hipStream_t s, int op, const VecSet& vs, float4* x, float4* r,
                    const float4* rhat, float4* p, const float4* v, const float4* t,
-                   RhsScal* sc, double* partials) {
-  step<float4>(s, op, vs, x, r, rhat, p, v, t, sc, partials);
+                   RhsScal* sc, double* partials, unsigned long long* acct) {
+  step<float4>(s, op, vs, x, r, rhat, p, v, t, sc, partials, acct);
+}
+void bicg_fin_xr(hipStream_t s, const VecSet& vs, RhsScal* sc, const double* partials) {
+  hipLaunchKernelGGL(k_fin_xr, dim3(fin_blocks(vs)), dim3(BL_BS), 0, s, vs, sc, partials);
+  DBQ_HIP(hipGetLastError());
 }
 
 void bicg_aux_f64(hipStream_t s, int op, const VecSet& vs, const double2* r64, double2* r,

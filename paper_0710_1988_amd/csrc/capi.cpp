@@ -174,7 +174,7 @@ int dbq_set_timing(dbq_ctx* c, int32_t on) {
 int dbq_kernel_time(dbq_ctx* c, int32_t kind, double* total_ms, int64_t* launches,
                     double* algorithmic_bytes) {
   return guarded(c, [&]() {
-    DBQ_CHECK(kind == 0 || kind == 1, "kind must be 0 or 1");
+    DBQ_CHECK(kind >= 0 && kind <= 2, "kind must be 0, 1 or 2");
     DBQ_CHECK(total_ms && launches && algorithmic_bytes, "null argument");
     dbq::timer_collect(c);
     *total_ms = c->timers[kind].ms;

@@ -111,10 +111,10 @@ void timer_collect(dbq_ctx* c) {
     t.ev.clear();
   }
   if (c->acct) {
-    unsigned long long v[2];
+    unsigned long long v[3];
     DBQ_HIP(hipMemcpyAsync(v, c->acct, sizeof(v), hipMemcpyDeviceToHost, c->stream));
     DBQ_HIP(hipStreamSynchronize(c->stream));
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < 3; ++k) {
       c->timers[k].bytes += double(v[k] - c->acct_seen[k]);
       c->acct_seen[k] = v[k];
     }

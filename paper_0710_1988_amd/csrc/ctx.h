@@ -25,7 +25,8 @@ struct dbq_ctx {
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
 
-  // ---- timing of Dslash launches (kind 0 = FP64, 1 = FP32)
+  // ---- timing of kernel launches: kind 0 = Dslash FP64, 1 = Dslash FP32, 2 = the FP32
+  //      BiCGStab x/r update with its inner products (the XR step)
   bool timing = false;
   struct Timer {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;  // recorded, not yet read
@@ -33,15 +34,15 @@ struct dbq_ctx {
     double ms = 0;
     int64_t n = 0;
     double bytes = 0;
-  } timers[2];
+  } timers[3];
 
 
-  // ---- device accumulators for the algorithmic bytes of gated Dslash launches (timing only):
-  //      [kind] bytes so far, [8 + 8 * kind + lattice] id of the last launch that counted the
-  //      lattice's links.  acct_seen = the accumulator values already added to the timers.
+  // ---- device accumulators for the algorithmic bytes of gated launches (timing only):
+  //      [kind] bytes so far (kinds 0-2), [8 + 8 * kind + lattice] id of the last Dslash launch
+  //      that counted the lattice's links.  acct_seen = the values already added to the timers.
   unsigned long long* acct = nullptr;
   unsigned long long acct_seq = 0;
-  unsigned long long acct_seen[2] = {0, 0};
+  unsigned long long acct_seen[3] = {0, 0, 0};
 
   // ---- Dslash launch shape chosen by timing, keyed by (fp32, V, nrhs): (rhs per thread,
   //      rhs groups per site sweep)

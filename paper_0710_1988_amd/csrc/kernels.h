@@ -162,9 +162,13 @@ enum BicgOp : int { BI_P = 0, BI_S = 1, BI_XR = 2 };
 void bicg_step_f64(hipStream_t s, int op, const VecSet& vs, double2* x, double2* r,
                    const double2* rhat, double2* p, const double2* v, const double2* t,
                    RhsScal* sc, double* partials);
+// BI_XR launches only the update (its inner products into partials): bicg_fin_xr follows.
+// acct (timing only, may be null): the XR step adds its algorithmic bytes (7 vector passes per
+// active rhs) to *acct.
+void bicg_fin_xr(hipStream_t s, const VecSet& vs, RhsScal* sc, const double* partials);
 void bicg_step_f32(hipStream_t s, int op, const VecSet& vs, float4* x, float4* r,
                    const float4* rhat, float4* p, const float4* v, const float4* t,
-                   RhsScal* sc, double* partials);
+                   RhsScal* sc, double* partials, unsigned long long* acct = nullptr);
 // init: r (FP64) -> working r (copy or narrowed), rhat = r, p = v = 0, x32 = 0 (mixed),
 //       rho = ||r||^2 ... ; mode 0: all rhs with active != 0; uses `sel` when only_sel
 enum BicgAux : int { AX_INIT = 0, AX_RESTART = 1, AX_REPLACE = 2 };

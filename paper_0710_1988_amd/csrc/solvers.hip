@@ -748,13 +748,20 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
       run_dslash(c, true, bv, dagger, EPI_RHAT, sc, partials);
       bicg_step_f32(s, BI_S, vs32, x32, r32, rhat32, p32, v32, t32, sc, partials);
       run_dslash(c, true, bt, dagger, EPI_TS, sc, partials);
-      bicg_step_f32(s, BI_XR, vs32, x32, r32, rhat32, p32, v32, t32, sc, partials);
+      // the update kernel alone is timed (kind 2), its bytes counted on the device
+      hipEvent_t e0;
+      timer_begin(c, 2, &e0);
+      bicg_step_f32(s, BI_XR, vs32, x32, r32, rhat32, p32, v32, t32, sc, partials,
+                    c->timing ? c->acct + 2 : nullptr);
+      timer_end(c, 2, e0, 0.0);
+      bicg_fin_xr(s, vs32, sc, partials);
     } else {
       bicg_step_f64(s, BI_P, vs64, x64, r64, rhat, p, v, t, sc, partials);
       run_dslash(c, false, bv, dagger, EPI_RHAT, sc, partials);
       bicg_step_f64(s, BI_S, vs64, x64, r64, rhat, p, v, t, sc, partials);
       run_dslash(c, false, bt, dagger, EPI_TS, sc, partials);
       bicg_step_f64(s, BI_XR, vs64, x64, r64, rhat, p, v, t, sc, partials);
+      bicg_fin_xr(s, vs64, sc, partials);
     }
   };
 
