@@ -380,7 +380,8 @@ def set_timing(on, device=None):
     torch = _torch()
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
     h = _ctx(dev)
-    _check(_abi.load().dbq_set_timing(h, int(bool(on))), h, ok=(0,))
+    # on: False/0 off, True/1 every launch, N > 1 every N-th launch of each kernel class
+    _check(_abi.load().dbq_set_timing(h, int(on)), h, ok=(0,))
 
 
 def reset_timing(device=None):

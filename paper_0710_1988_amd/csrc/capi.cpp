@@ -166,7 +166,9 @@ int kappa_critical(dbq_ctx* c, const int32_t L[4], const void* links, int32_t m,
 
 int dbq_set_timing(dbq_ctx* c, int32_t on) {
   return guarded(c, [&]() {
+    DBQ_CHECK(on >= 0, "timing: on must be >= 0");
     c->timing = on != 0;
+    c->timing_sample = on > 1 ? on : 1;
     return DBQ_OK;
   });
 }
@@ -191,6 +193,7 @@ int dbq_reset_timing(dbq_ctx* c) {
       t.ms = 0;
       t.n = 0;
       t.bytes = 0;
+      t.calls = 0;
     }
     return DBQ_OK;
   });

@@ -71,6 +71,7 @@ void timer_begin(dbq_ctx* c, int kind, hipEvent_t* ev_out) {
   *ev_out = nullptr;
   if (!c->timing) return;
   auto& t = c->timers[kind];
+  if ((t.calls++ % c->timing_sample) != 0) return;
   hipEvent_t e;
   if (!t.spare.empty()) {
     e = t.spare.back();

@@ -28,12 +28,14 @@ struct dbq_ctx {
   // ---- timing of kernel launches: kind 0 = Dslash FP64, 1 = Dslash FP32, 2 = the FP32
   //      BiCGStab x/r update with its inner products (the XR step)
   bool timing = false;
+  int timing_sample = 1;  // every timing_sample-th launch of a class is timed
   struct Timer {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;  // recorded, not yet read
     std::vector<hipEvent_t> spare;
     double ms = 0;
     int64_t n = 0;
     double bytes = 0;
+    int64_t calls = 0;  // launches seen; every TIMING_SAMPLE-th one is timed
   } timers[3];
 
 
@@ -71,7 +73,9 @@ struct WsScope {
   std::vector<size_t> taken;
 };
 
-// timing brackets around one Dslash launch
+// Timing brackets around one launch; every c->timing_sample-th launch of a class is timed (each
+// pair of events adds a few microseconds to the stream).  ev_out is null for a launch that is
+// not sampled (timer_end then ignores it).
 void timer_begin(dbq_ctx* c, int kind, hipEvent_t* ev_out);
 void timer_end(dbq_ctx* c, int kind, hipEvent_t ev_begin, double bytes);
 void timer_collect(dbq_ctx* c);

@@ -307,8 +307,11 @@ void run_dslash(dbq_ctx* c, bool f32, const DsBatch& b0, int dagger, int epi, Rh
   const int kind = f32 ? 1 : 0;
   DsBatch b = b0;
   b.acct = DsAcct{};
-  // a gated launch (scalars given) skips inactive rhs: its bytes are counted on the device
-  const bool dev_acct = c->timing && sc != nullptr && epi != EPI_NONE;
+  hipEvent_t e0;
+  timer_begin(c, kind, &e0);  // null unless this launch is a timed sample
+  // a gated launch (scalars given) skips inactive rhs: the bytes of a timed one are counted on
+  // the device
+  const bool dev_acct = e0 != nullptr && sc != nullptr && epi != EPI_NONE;
   if (dev_acct) {
     b.acct.bytes = c->acct + kind;
     b.acct.tags = c->acct + 8 + 8 * kind;
@@ -320,8 +323,6 @@ void run_dslash(dbq_ctx* c, bool f32, const DsBatch& b0, int dagger, int epi, Rh
   // residual launches select few rhs: with all rhs groups of a site block adjacent, the selected
   // ones still cover every XCD (chunks of rhs groups would put one rhs on one or two XCDs)
   const int rg = (epi == EPI_RESID && shape.first > 0) ? 0 : shape.second;
-  hipEvent_t e0;
-  timer_begin(c, kind, &e0);
   const double bytes =
       f32 ? launch_dslash_f32(c->stream, b, dagger, epi, sc, partials, shape.first, rg)
           : launch_dslash_f64(c->stream, b, dagger, epi, sc, partials, shape.first, rg);
@@ -752,7 +753,7 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
       hipEvent_t e0;
       timer_begin(c, 2, &e0);
       bicg_step_f32(s, BI_XR, vs32, x32, r32, rhat32, p32, v32, t32, sc, partials,
-                    c->timing ? c->acct + 2 : nullptr);
+                    e0 ? c->acct + 2 : nullptr);
       timer_end(c, 2, e0, 0.0);
       bicg_fin_xr(s, vs32, sc, partials);
     } else {
