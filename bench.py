@@ -521,8 +521,8 @@ def main():
                                  "traffic": None if u_traffic is None else round(u_traffic),
                                  "traffic_source": u_src,
                                  "kernel": "FP32 BiCGStab update k_bicg_step XR (x += alpha p + "
-                                           "omega s, r = s - omega t, <rhat, r>, |r|^2; 7 vector "
-                                           "passes per active rhs)",
+                                           "omega s, r = s - omega t, p = r + beta (p - omega v), "
+                                           "|r|^2; 8 vector passes per active rhs)",
                                  "avg_launch_us": round(u_us, 2), "launches": nu,
                                  "algorithmic_MB_per_launch": round(byu / max(nu, 1) / 1e6, 2)},
         "fp64_dslash_in_step": {"launches": n64,

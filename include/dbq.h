@@ -200,11 +200,11 @@ int kappa_critical(dbq_ctx* ctx, const int32_t L[4], const void* links, int32_t 
 
 /* Instrumentation: with timing on (dbq_set_timing with on = N >= 1), every N-th launch of each
  * class -- the Dslash launches of the full operator inside the library and the FP32 BiCGStab
- * update steps (x += alpha p + omega s, r = s - omega t with <rhat, r> and ||r||^2) -- is
+ * update steps (x += alpha p + omega s, r = s - omega t, p = r + beta (p - omega v) with ||r||^2) -- is
  * bracketed with HIP events on the context stream (a pair of events adds a few microseconds to
  * the stream; an odd N samples alternating epilogues alike); on = 0 turns timing off.
  * dbq_kernel_time returns the accumulated milliseconds, the number of timed launches and their
- * algorithmic HBM bytes for one class (0 = Dslash FP64, 1 = Dslash FP32, 2 = FP32 update step: 7
+ * algorithmic HBM bytes for one class (0 = Dslash FP64, 1 = Dslash FP32, 2 = FP32 update step: 8
  * vector passes per active rhs) since the last reset. */
 int dbq_set_timing(dbq_ctx* ctx, int32_t on);
 int dbq_kernel_time(dbq_ctx* ctx, int32_t kind, double* total_ms, int64_t* launches,

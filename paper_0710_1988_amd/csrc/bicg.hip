@@ -1,9 +1,13 @@
 // Fused BiCGStab vector updates and inner products for a batch of right-hand sides (Sec. 2 runs
 // BiCGStab after the deflation step; Sec. 1 motivates it as a non-restarted method).
 //
-// One iteration:  BI_P (p = r + beta (p - omega v)),  Dslash v = A p with <rhat, v> -> alpha,
-// BI_S (r <- s = r - alpha v),  Dslash t = A s with <t, s>, <t, t> -> omega,
-// BI_XR (x += alpha p + omega s; r = s - omega t; <rhat, r>, ||r||^2 -> rho, beta, tests).
+// One iteration:  Dslash v = A p with <rhat, v> -> alpha,  BI_S (r <- s = r - alpha v),
+// Dslash t = A s with <t, s>, <t, t>, <rhat, t>, <rhat, s> -> omega, the next rho = <rhat, s> -
+// omega <rhat, t> and beta,  BI_XR (x += alpha p + omega s; r = s - omega t;
+// p = r + beta (p - omega v); ||r||^2 -> tests).  Folding the search-direction update into the
+// XR pass saves a launch and three vector passes per iteration (the epilogue reads rhat, the XR
+// pass v, instead of rhat in XR and r, p, v, p in a separate pass); a reliable update replaces
+// rho by <rhat, r> of the FP64 residual.
 // The scalars live in RhsScal on the device.  Each streaming kernel stores one partial sum per
 // block; a small follow-up launch combines them per right-hand side in a fixed order, so the
 // results do not depend on block scheduling and no device-scope fence stalls the stream.
@@ -83,18 +87,18 @@ __device__ __forceinline__ void store_partial(const VecSet& vs, double* partials
   }
 }
 
-// end of an iteration: rho_new = <rhat, r>, rr = ||r||^2
-__device__ void fin_xr(RhsScal& q, double a0, double a1, double a2) {
+// end of an iteration: rr = ||r||^2; rho takes the value the <t, s> epilogue prepared
+__device__ void fin_xr(RhsScal& q, double a2) {
   if (!q.active) return;
   q.iters += 1;
   q.since += 1;
   q.rr = a2;
-  if (!fin(a0) || !fin(a1) || !fin(a2)) {
+  if (!fin(a2)) {
     q.flags |= F_NAN;
     q.active = 0;
     return;
   }
-  const zd rn{a0, a1};
+  const zd rn = q.rho_next;
   if (a2 <= q.stop2) q.flags |= F_CONV;
   if (q.delta2 > 0.0) {
     if (a2 > q.rr_max) q.rr_max = a2;
@@ -106,10 +110,6 @@ __device__ void fin_xr(RhsScal& q, double a0, double a1, double a2) {
   }
   if (norm2(rn) <= 1e-28 * q.rhat2 * a2) q.flags |= F_BREAK;
   if (q.flags & F_OMEGA0) q.flags |= F_BREAK;
-  if (q.omega.re != 0.0 || q.omega.im != 0.0)
-    q.beta = cdiv(rn, q.rho) * cdiv(q.alpha, q.omega);
-  else
-    q.beta = zd{0.0, 0.0};
   q.rho_prev = q.rho;
   q.rho = rn;
   if (q.flags & (F_CONV | F_RELIABLE | F_BREAK | F_NAN)) q.active = 0;
@@ -133,9 +133,9 @@ __global__ __launch_bounds__(BL_BS) void k_bicg_step(VecSet vs, E* __restrict__ 
   const int rhs = bm.x, ch = bm.y;
   const bool act = sc[rhs].active != 0;
   double red[3] = {0.0, 0.0, 0.0};
-  // byte accounting (timing only): reads x, p, s, t, rhat and writes x, r of an active rhs
+  // byte accounting (timing only): reads x, p, s, t, v and writes x, r, p of an active rhs
   if (OP == BI_XR && acct && act && ch == 0 && threadIdx.x == 0)
-    atomicAdd(acct, 7ull * (unsigned long long)vs.nelem[rhs] * sizeof(E));
+    atomicAdd(acct, 8ull * (unsigned long long)vs.nelem[rhs] * sizeof(E));
   if (act) {
     const long long base = vs.off[rhs];
     const int ne = vs.nelem[rhs];
@@ -146,15 +146,7 @@ __global__ __launch_bounds__(BL_BS) void k_bicg_step(VecSet vs, E* __restrict__ 
       const int idx = ch * BL_CHUNK + e * BL_BS + threadIdx.x;
       if (idx < ne) {
         const long long i = base + idx;
-        if (OP == BI_P) {
-          cx<R> rr[NC], pp[NC], vv[NC];
-          ET<E>::ld(r, i, rr);
-          ET<E>::ld(p, i, pp);
-          ET<E>::ld(v, i, vv);
-#pragma unroll
-          for (int c = 0; c < NC; ++c) pp[c] = rr[c] + be * (pp[c] - om * vv[c]);
-          ET<E>::st(p, i, pp);
-        } else if (OP == BI_S) {
+        if (OP == BI_S) {
           cx<R> rr[NC], vv[NC];
           ET<E>::ld(r, i, rr);
           ET<E>::ld(v, i, vv);
@@ -162,24 +154,23 @@ __global__ __launch_bounds__(BL_BS) void k_bicg_step(VecSet vs, E* __restrict__ 
           for (int c = 0; c < NC; ++c) rr[c] = rr[c] - al * vv[c];
           ET<E>::st(r, i, rr);
         } else {
-          cx<R> xx[NC], pp[NC], ss[NC], tt[NC], hh[NC];
+          cx<R> xx[NC], pp[NC], ss[NC], tt[NC], vv[NC];
           ET<E>::ld(x, i, xx);
           ET<E>::ld(p, i, pp);
           ET<E>::ld(r, i, ss);
           ET<E>::ld(t, i, tt);
-          ET<E>::ld(rhat, i, hh);
+          ET<E>::ld(v, i, vv);
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
             xx[c] = xx[c] + al * pp[c] + om * ss[c];
             ss[c] = ss[c] - om * tt[c];
-            const zd a{double(hh[c].re), double(hh[c].im)}, b{double(ss[c].re), double(ss[c].im)};
-            const zd d = cmulc(a, b);
-            red[0] += d.re;
-            red[1] += d.im;
-            red[2] += b.re * b.re + b.im * b.im;
+            pp[c] = ss[c] + be * (pp[c] - om * vv[c]);
+            const double br = double(ss[c].re), bi = double(ss[c].im);
+            red[2] += br * br + bi * bi;
           }
           ET<E>::st(x, i, xx);
           ET<E>::st(r, i, ss);
+          ET<E>::st(p, i, pp);
         }
       }
     }
@@ -190,7 +181,7 @@ __global__ __launch_bounds__(BL_BS) void k_bicg_step(VecSet vs, E* __restrict__ 
 // Partial sums are combined in a separate launch (see the Dslash epilogue for why).
 __global__ __launch_bounds__(BL_BS) void k_fin_xr(VecSet vs, RhsScal* __restrict__ sc,
                                                   const double* __restrict__ partials) {
-  reduce_rhs(vs, partials, [&](int j, double a0, double a1, double a2) { fin_xr(sc[j], a0, a1, a2); });
+  reduce_rhs(vs, partials, [&](int j, double, double, double a2) { fin_xr(sc[j], a2); });
 }
 
 __device__ void fin_aux(int op, RhsScal& q, double a0, double a1, double a2);
@@ -247,16 +238,16 @@ __device__ void fin_aux(int op, RhsScal& q, double a0, double a1, double a2) {
   } else {  // AX_REPLACE
     if (!q.sel) return;
     const zd rn{a0, a1};
-    if (q.omega.re != 0.0 || q.omega.im != 0.0)
-      q.beta = cdiv(rn, q.rho_prev) * cdiv(q.alpha, q.omega);
-    else
-      q.beta = zd{0.0, 0.0};
+    // The search direction p = r + beta d (d = p_prev - omega v) was formed with the beta of
+    // the FP32 rho; the one of the replaced residual is r_new + (rn / rho) beta d, so the replace
+    // kernel that follows takes p <- r_new + c (p - r_old) with c = rn / rho, held in beta until
+    // the next <t, s> epilogue sets beta again.  sel stays set for that kernel.
+    q.beta = (q.rho.re != 0.0 || q.rho.im != 0.0) ? cdiv(rn, q.rho) : zd{0.0, 0.0};
     q.rho = rn;
     q.rr = a2;
     q.rr_max = a2;
     q.flags = 0;
     q.active = 1;
-    q.sel = 0;
     q.since = 0;
     if (norm2(rn) <= 1e-28 * q.rhat2 * a2) {
       q.flags = F_BREAK;
@@ -286,8 +277,8 @@ __global__ __launch_bounds__(BL_BS) void k_aux64(VecSet vs, const double2* __res
       if (idx >= ne) continue;
       const long long i = base + idx;
       if (OP == AX_REPLACE) {
+        // sums only: the replace kernel writes r and p once c is known
         const double2 a = r64[i];
-        r[i] = a;
         const double2 h = rhat[i];
         red[0] += h.x * a.x + h.y * a.y;
         red[1] += h.x * a.y - h.y * a.x;
@@ -295,8 +286,7 @@ __global__ __launch_bounds__(BL_BS) void k_aux64(VecSet vs, const double2* __res
       } else {
         const double2 a = r[i];
         rhat[i] = a;
-        p[i] = make_double2(0.0, 0.0);
-        v[i] = make_double2(0.0, 0.0);
+        p[i] = a;
         red[2] += a.x * a.x + a.y * a.y;
       }
     }
@@ -329,20 +319,19 @@ __global__ __launch_bounds__(BL_BS) void k_aux32(VecSet vs, VecSet vs64,
       if (OP == AX_RESTART) {
         const float4 a = r[i];
         rhat[i] = a;
-        p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-        v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        p[i] = a;
         red[2] += double(a.x) * a.x + double(a.y) * a.y + double(a.z) * a.z + double(a.w) * a.w;
       } else {
         const double2 d0 = r64[base64 + 2 * (long long)idx];
         const double2 d1 = r64[base64 + 2 * (long long)idx + 1];
         const float4 a = make_float4(float(d0.x), float(d0.y), float(d1.x), float(d1.y));
-        r[i] = a;
         if (OP == AX_INIT) {
+          r[i] = a;
           rhat[i] = a;
-          p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-          v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+          p[i] = a;
           x32[i] = make_float4(0.f, 0.f, 0.f, 0.f);
         } else {
+          // sums of the narrowed residual only: the replace kernel writes r and p
           const float4 h = rhat[i];
           red[0] += double(h.x) * a.x + double(h.y) * a.y + double(h.z) * a.z + double(h.w) * a.w;
           red[1] += double(h.x) * a.y - double(h.y) * a.x + double(h.z) * a.w - double(h.w) * a.z;
@@ -352,6 +341,77 @@ __global__ __launch_bounds__(BL_BS) void k_aux32(VecSet vs, VecSet vs64,
     }
   }
   store_partial(vs, partials, rhs, ch, red);
+}
+
+// Second pass of a residual replacement: r <- r_new, p <- r_new + c (p - r_old) with c = rn / rho
+// (in beta) for the selected rhs.  FP32 vectors take r_new narrowed from the FP64 residual.
+template <typename E>
+__device__ __forceinline__ void repl_elem(E* r, E* p, long long i, const cx<typename ET<E>::R> (&a)[ET<E>::NC],
+                                          cx<typename ET<E>::R> c) {
+  typedef typename ET<E>::R R;
+  constexpr int NC = ET<E>::NC;
+  cx<R> o[NC], q[NC];
+  ET<E>::ld(r, i, o);
+  ET<E>::ld(p, i, q);
+#pragma unroll
+  for (int k = 0; k < NC; ++k) q[k] = a[k] + c * (q[k] - o[k]);
+  ET<E>::st(r, i, a);
+  ET<E>::st(p, i, q);
+}
+
+__global__ __launch_bounds__(BL_BS) void k_repl64(VecSet vs, const double2* __restrict__ r64,
+                                                  double2* __restrict__ r, double2* __restrict__ p,
+                                                  const RhsScal* __restrict__ sc) {
+  const int lb = xcd_block(blockIdx.x, vs.nblocks);
+  const int2 bm = vs.blk[lb];
+  const int rhs = bm.x, ch = bm.y;
+  if (!sc[rhs].sel) return;
+  const long long base = vs.off[rhs];
+  const int ne = vs.nelem[rhs];
+  const zd c = sc[rhs].beta;
+  for (int e = 0; e < BL_EPT; ++e) {
+    const int idx = ch * BL_CHUNK + e * BL_BS + threadIdx.x;
+    if (idx >= ne) continue;
+    const long long i = base + idx;
+    const double2 d = r64[i];
+    const zd a[1] = {zd{d.x, d.y}};
+    repl_elem<double2>(r, p, i, a, c);
+  }
+}
+
+__global__ __launch_bounds__(BL_BS) void k_repl32(VecSet vs, VecSet vs64,
+                                                  const double2* __restrict__ r64,
+                                                  float4* __restrict__ r, float4* __restrict__ p,
+                                                  const RhsScal* __restrict__ sc) {
+  const int lb = xcd_block(blockIdx.x, vs.nblocks);
+  const int2 bm = vs.blk[lb];
+  const int rhs = bm.x, ch = bm.y;
+  if (!sc[rhs].sel) return;
+  const long long base = vs.off[rhs];
+  const long long base64 = vs64.off[rhs];
+  const int ne = vs.nelem[rhs];
+  const zf c = narrow<float>(sc[rhs].beta);
+  for (int e = 0; e < BL_EPT; ++e) {
+    const int idx = ch * BL_CHUNK + e * BL_BS + threadIdx.x;
+    if (idx >= ne) continue;
+    const long long i = base + idx;
+    const double2 d0 = r64[base64 + 2 * (long long)idx];
+    const double2 d1 = r64[base64 + 2 * (long long)idx + 1];
+    const zf a[2] = {zf{float(d0.x), float(d0.y)}, zf{float(d1.x), float(d1.y)}};
+    repl_elem<float4>(r, p, i, a, c);
+  }
+}
+
+// ends a replacement: no rhs stays selected
+__global__ __launch_bounds__(BL_BS) void k_clear_sel(int nrhs, RhsScal* __restrict__ sc) {
+  const int j = blockIdx.x * BL_BS + threadIdx.x;
+  if (j < nrhs) sc[j].sel = 0;
+}
+
+void launch_clear_sel(hipStream_t s, const VecSet& vs, RhsScal* sc) {
+  hipLaunchKernelGGL(k_clear_sel, dim3((vs.nrhs + BL_BS - 1) / BL_BS), dim3(BL_BS), 0, s, vs.nrhs,
+                     sc);
+  DBQ_HIP(hipGetLastError());
 }
 
 __global__ __launch_bounds__(BL_BS) void k_xacc(VecSet vs, VecSet vs64, double2* __restrict__ x64,
@@ -386,10 +446,6 @@ void step(hipStream_t s, int op, const VecSet& vs, E* x, E* r, const E* rhat, E*
           const E* t, RhsScal* sc, double* partials, unsigned long long* acct) {
   dim3 g(vs.nblocks), b(BL_BS);
   switch (op) {
-    case BI_P:
-      hipLaunchKernelGGL((k_bicg_step<E, BI_P>), g, b, 0, s, vs, x, r, rhat, p, v, t, sc,
-                         partials, nullptr);
-      break;
     case BI_S:
       hipLaunchKernelGGL((k_bicg_step<E, BI_S>), g, b, 0, s, vs, x, r, rhat, p, v, t, sc,
                          partials, nullptr);
@@ -431,7 +487,12 @@ void bicg_aux_f64(hipStream_t s, int op, const VecSet& vs, const double2* r64, d
   DBQ_HIP(hipGetLastError());
   if (op == AX_INIT) launch_fin_aux<AX_INIT>(s, vs, sc, partials);
   else if (op == AX_RESTART) launch_fin_aux<AX_RESTART>(s, vs, sc, partials);
-  else launch_fin_aux<AX_REPLACE>(s, vs, sc, partials);
+  else {
+    launch_fin_aux<AX_REPLACE>(s, vs, sc, partials);
+    hipLaunchKernelGGL(k_repl64, g, b, 0, s, vs, r64, r, p, sc);
+    DBQ_HIP(hipGetLastError());
+    launch_clear_sel(s, vs, sc);
+  }
 }
 
 void bicg_aux_f32(hipStream_t s, int op, const VecSet& vs32, const VecSet& vs64,
@@ -450,7 +511,12 @@ void bicg_aux_f32(hipStream_t s, int op, const VecSet& vs32, const VecSet& vs64,
   DBQ_HIP(hipGetLastError());
   if (op == AX_INIT) launch_fin_aux<AX_INIT>(s, vs32, sc, partials);
   else if (op == AX_RESTART) launch_fin_aux<AX_RESTART>(s, vs32, sc, partials);
-  else launch_fin_aux<AX_REPLACE>(s, vs32, sc, partials);
+  else {
+    launch_fin_aux<AX_REPLACE>(s, vs32, sc, partials);
+    hipLaunchKernelGGL(k_repl32, g, b, 0, s, vs32, vs64, r64, r, p, sc);
+    DBQ_HIP(hipGetLastError());
+    launch_clear_sel(s, vs32, sc);
+  }
 }
 
 void bicg_xacc(hipStream_t s, const VecSet& vs32, const VecSet& vs64, double2* x64, float4* x32,

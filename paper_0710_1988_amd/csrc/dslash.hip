@@ -313,16 +313,30 @@ __device__ void finalize(const DsBatch& B, RhsScal* sc, const double* partials) 
     for (int i = 1; i < B.nlat; ++i)
       if (rhs >= B.lat[i].rhs_base) l = i;
     const int nsb = B.lat[l].nsb;
-    double a0 = 0, a1 = 0, a2 = 0;
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, a6 = 0;
     const double* pp = partials + (long long)rhs * B.pstride * 3;
+    const double* px = partials + (long long)B.nrhs_total * B.pstride * 3 +
+                       (long long)rhs * B.pstride * 4;
     for (int j = lane; j < nsb; j += 64) {
       a0 += pp[3 * j];
       a1 += pp[3 * j + 1];
       a2 += pp[3 * j + 2];
+      if (EPI == EPI_TS) {
+        a3 += px[4 * j];
+        a4 += px[4 * j + 1];
+        a5 += px[4 * j + 2];
+        a6 += px[4 * j + 3];
+      }
     }
     a0 = wave_sum(a0);
     a1 = wave_sum(a1);
     a2 = wave_sum(a2);
+    if (EPI == EPI_TS) {
+      a3 = wave_sum(a3);
+      a4 = wave_sum(a4);
+      a5 = wave_sum(a5);
+      a6 = wave_sum(a6);
+    }
     if (lane == 0) {
       RhsScal& q = sc[rhs];
       if (EPI == EPI_RHAT) {
@@ -340,16 +354,25 @@ __device__ void finalize(const DsBatch& B, RhsScal* sc, const double* partials) 
           }
         }
       } else if (EPI == EPI_TS) {
+        // omega = <t, s> / |t|^2; the next rho = <rhat, s - omega t> = <rhat, s> - omega
+        // <rhat, t> (both sums taken from the vectors, so no rounding carries over from earlier
+        // iterations; <rhat, s> is small but not zero); beta = (rho_next / rho)(alpha / omega)
+        // lets the update step form the next search direction in the same pass
         if (q.active) {
-          if (!finite_d(a0) || !finite_d(a1) || !finite_d(a2)) {
+          if (!finite_d(a0) || !finite_d(a1) || !finite_d(a2) || !finite_d(a3) ||
+              !finite_d(a4) || !finite_d(a5) || !finite_d(a6)) {
             q.flags |= F_NAN;
             q.active = 0;
-          } else if (a2 == 0.0) {
-            q.omega = zd{0.0, 0.0};
+          } else if (a2 == 0.0 || (a0 == 0.0 && a1 == 0.0)) {
+            q.omega = zd{a2 == 0.0 ? 0.0 : a0 / a2, a2 == 0.0 ? 0.0 : a1 / a2};
             q.flags |= F_OMEGA0;
+            q.rho_next = zd{0.0, 0.0};
+            q.beta = zd{0.0, 0.0};
           } else {
             q.omega = zd{a0 / a2, a1 / a2};
-            if (a0 == 0.0 && a1 == 0.0) q.flags |= F_OMEGA0;
+            const zd rt{a3, a4}, rs{a5, a6};
+            q.rho_next = rs - q.omega * rt;
+            q.beta = cdiv(q.rho_next, q.rho) * cdiv(q.alpha, q.omega);
           }
         }
       } else if (EPI == EPI_RESID) {
@@ -410,12 +433,13 @@ __device__ __forceinline__ void chain(int (&c)[4], int& s, cx<T> (&acc)[NB][12])
 
 // The site's result psi - kappa*acc + i*t*gamma5*psi (t = mu, or -mu for the dagger) and the
 // epilogue's contributions to the per-block sums: RESID replaces the result by aux - result and
-// adds its norm, RHAT adds <aux, result>, TS adds <result, psi> and |result|^2 (aux, the
-// epilogue operand at the site, is read only by RESID and RHAT).
+// adds its norm, RHAT adds <aux, result>, TS adds <result, psi>, |result|^2, <aux, result> and
+// <aux, psi> (aux, the epilogue operand at the site: b for RESID, rhat for RHAT and TS).  rd holds
+// DS_NSUM running sums.
 template <typename T, int EPI>
 __device__ __forceinline__ void finish_site(const cx<T> (&psi)[12], const cx<T> (&acc)[12], T kap,
-                                            T tm, const cx<T> (&aux)[12], double& r0,
-                                            double& r1, double& r2, cx<T> (&o)[12]) {
+                                            T tm, const cx<T> (&aux)[12], double* rd,
+                                            cx<T> (&o)[12]) {
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
     // gamma5 = diag(1,1,-1,-1) over spins
@@ -430,24 +454,55 @@ __device__ __forceinline__ void finish_site(const cx<T> (&psi)[12], const cx<T> 
       o[k] = aux[k] - o[k];
       nn = fma(o[k].re, o[k].re, fma(o[k].im, o[k].im, nn));
     }
-    r0 += double(nn);
+    rd[0] += double(nn);
   } else if (EPI == EPI_RHAT) {
     cx<T> d{T(0), T(0)};
 #pragma unroll
     for (int k = 0; k < 12; ++k) cmacc(d, aux[k], o[k]);
-    r0 += double(d.re);
-    r1 += double(d.im);
+    rd[0] += double(d.re);
+    rd[1] += double(d.im);
   } else if (EPI == EPI_TS) {
-    cx<T> d{T(0), T(0)};
+    cx<T> d{T(0), T(0)}, h{T(0), T(0)}, g{T(0), T(0)};
     T nn = T(0);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       cmacc(d, o[k], psi[k]);
+      cmacc(h, aux[k], o[k]);
+      cmacc(g, aux[k], psi[k]);
       nn = fma(o[k].re, o[k].re, fma(o[k].im, o[k].im, nn));
     }
-    r0 += double(d.re);
-    r1 += double(d.im);
-    r2 += double(nn);
+    rd[0] += double(d.re);
+    rd[1] += double(d.im);
+    rd[2] += double(nn);
+    rd[3] += double(h.re);
+    rd[4] += double(h.im);
+    rd[5] += double(g.re);
+    rd[6] += double(g.im);
+  }
+}
+
+// <rhat, t> and <rhat, s> of the <t, s> epilogue go to a second partial-sum region after the
+// first (nrhs_total x pstride slots of 3 doubles), 4 doubles per slot
+__device__ __forceinline__ double* ts_extra(const DsBatch& B, double* partials, long long rhs,
+                                            long long slot) {
+  return partials + (long long)B.nrhs_total * B.pstride * 3 + (rhs * B.pstride + slot) * 4;
+}
+
+// stores the block's sums of one rhs: 3 into the first region, the TS epilogue's other 4 into
+// the second
+template <int EPI>
+__device__ __forceinline__ void store_sums(const DsBatch& B, double* partials, long long rhs,
+                                           long long slot, const double* rd) {
+  double* pp = partials + (rhs * B.pstride + slot) * 3;
+  pp[0] = rd[0];
+  pp[1] = rd[1];
+  pp[2] = rd[2];
+  if (EPI == EPI_TS) {
+    double* px = ts_extra(B, partials, rhs, slot);
+    px[0] = rd[3];
+    px[1] = rd[4];
+    px[2] = rd[5];
+    px[3] = rd[6];
   }
 }
 
@@ -511,9 +566,9 @@ void k_dslash(DsBatch B, RhsScal* __restrict__ sc, double* __restrict__ partials
   const int s = sb * DS_BS + threadIdx.x;
   const bool in_range = s < V;
 #endif
-  double red[NB * 3];
+  double red[NB * DS_NSUM];
 #pragma unroll
-  for (int i = 0; i < NB * 3; ++i) red[i] = 0.0;
+  for (int i = 0; i < NB * DS_NSUM; ++i) red[i] = 0.0;
   if (any && in_range) {
     const SE* in = (const SE*)L.in + r0 * rstride;
     SE* out = (SE*)L.out + r0 * rstride;
@@ -541,25 +596,21 @@ void k_dslash(DsBatch B, RhsScal* __restrict__ sc, double* __restrict__ partials
       cx<T> psi[12];
       IO<T>::load(in + j * rstride, V, s, psi);
       cx<T> ax[12];
-      if (EPI == EPI_RHAT || EPI == EPI_RESID)
+      if (EPI != EPI_NONE)
         IO<T>::load((const SE*)L.aux + (r0 + j) * rstride, V, s, ax);
       cx<T> o[12];
-      finish_site<T, EPI>(psi, acc[j], kap, tm, ax, red[3 * j], red[3 * j + 1], red[3 * j + 2],
-                          o);
+      finish_site<T, EPI>(psi, acc[j], kap, tm, ax, red + DS_NSUM * j, o);
       IO<T>::store(out + j * rstride, V, s, o);
     }
   }
   if (EPI != EPI_NONE) {
-    __shared__ double sh[NB * 3 * (DS_BS / 64)];
-    block_sum<NB * 3, DS_BS>(red, sh);
+    __shared__ double sh[NB * DS_NSUM * (DS_BS / 64)];
+    block_sum<NB * DS_NSUM, DS_BS>(red, sh);
     if (threadIdx.x == 0) {
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
         if (j >= nval) break;
-        double* pp = partials + ((long long)(L.rhs_base + r0 + j) * B.pstride + sb) * 3;
-        pp[0] = red[3 * j];
-        pp[1] = red[3 * j + 1];
-        pp[2] = red[3 * j + 2];
+        store_sums<EPI>(B, partials, L.rhs_base + r0 + j, sb, red + DS_NSUM * j);
       }
     }
   }
@@ -628,9 +679,9 @@ void k_dslash_half(DsBatch B, RhsScal* __restrict__ sc, double* __restrict__ par
     any = any || a;
   }
   const int h = sb * DS_BS + threadIdx.x;
-  double red[NB * 3];
+  double red[NB * DS_NSUM];
 #pragma unroll
-  for (int i = 0; i < NB * 3; ++i) red[i] = 0.0;
+  for (int i = 0; i < NB * DS_NSUM; ++i) red[i] = 0.0;
   if (any && h < Vh) {
     const SE* in = (const SE*)L.in + r0 * rstride;
     SE* out = (SE*)L.out + r0 * rstride;
@@ -667,25 +718,21 @@ void k_dslash_half(DsBatch B, RhsScal* __restrict__ sc, double* __restrict__ par
         finish_odd<T>(ce, acc[j], coef, tm, o);
       } else {
         cx<T> ax[12];
-        if (EPI == EPI_RHAT || EPI == EPI_RESID)
+        if (EPI != EPI_NONE)
           IO<T>::load((const SE*)L.aux + (r0 + j) * rstride, Vh, h, ax);
-        finish_site<T, EPI>(ce, acc[j], coef, tm, ax, red[3 * j], red[3 * j + 1],
-                            red[3 * j + 2], o);
+        finish_site<T, EPI>(ce, acc[j], coef, tm, ax, red + DS_NSUM * j, o);
       }
       IO<T>::store(out + j * rstride, Vh, h, o);
     }
   }
   if (EPI != EPI_NONE) {
-    __shared__ double sh[NB * 3 * (DS_BS / 64)];
-    block_sum<NB * 3, DS_BS>(red, sh);
+    __shared__ double sh[NB * DS_NSUM * (DS_BS / 64)];
+    block_sum<NB * DS_NSUM, DS_BS>(red, sh);
     if (threadIdx.x == 0) {
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
         if (j >= nval) break;
-        double* pp = partials + ((long long)(L.rhs_base + r0 + j) * B.pstride + sb) * 3;
-        pp[0] = red[3 * j];
-        pp[1] = red[3 * j + 1];
-        pp[2] = red[3 * j + 2];
+        store_sums<EPI>(B, partials, L.rhs_base + r0 + j, sb, red + DS_NSUM * j);
       }
     }
   }
@@ -973,9 +1020,11 @@ __global__ __launch_bounds__(DS_BS) void k_dslash_tile(DsBatch B, RhsScal* __res
     __syncthreads();                // and everyone else's
     const int jn = next(j + 1);
     zf ax[12];
-    if (own && (EPI == EPI_RHAT || EPI == EPI_RESID))
+    if (own && EPI != EPI_NONE)
       IO<float>::load((const float4*)L.aux + (long long)r * 6 * V, V, s, ax);
-    double red[3] = {0.0, 0.0, 0.0};
+    double red[DS_NSUM];
+#pragma unroll
+    for (int i = 0; i < DS_NSUM; ++i) red[i] = 0.0;
     if (own) {
       zf acc[12];
 #pragma unroll
@@ -991,17 +1040,14 @@ __global__ __launch_bounds__(DS_BS) void k_dslash_tile(DsBatch B, RhsScal* __res
       zf psi[12];
       lds_spinor<TL_SLOTS>(buf, tid, psi);
       zf o[12];
-      finish_site<float, EPI>(psi, acc, kap, tm, ax, red[0], red[1], red[2], o);
+      finish_site<float, EPI>(psi, acc, kap, tm, ax, red, o);
       IO<float>::store((float4*)L.out + (long long)r * 6 * V, V, s, o);
     }
     if (EPI != EPI_NONE) {
-      __shared__ double sh[3 * (DS_BS / 64)];
-      block_sum<3, DS_BS>(red, sh);
+      __shared__ double sh[DS_NSUM * (DS_BS / 64)];
+      block_sum<DS_NSUM, DS_BS>(red, sh);
       if (tid == 0) {
-        double* pp = partials + ((long long)(L.rhs_base + r) * B.pstride + tile) * 3;
-        pp[0] = red[0];
-        pp[1] = red[1];
-        pp[2] = red[2];
+        store_sums<EPI>(B, partials, L.rhs_base + r, tile, red);
       }
     }
     if (jn < Gc) {
@@ -1197,7 +1243,9 @@ __global__ __launch_bounds__(TH_BS) void k_dslash_tile_half(DsBatch B, RhsScal* 
     __builtin_amdgcn_s_waitcnt(0);  // this wave's LDS-direct copies have landed
     __syncthreads();                // and everyone else's
     const int jn = next(j + 1);
-    double red[3] = {0.0, 0.0, 0.0};
+    double red[DS_NSUM];
+#pragma unroll
+    for (int i = 0; i < DS_NSUM; ++i) red[i] = 0.0;
     if (own) {
       zf ce[12], ax[12];
       if (L.cen) {
@@ -1221,21 +1269,19 @@ __global__ __launch_bounds__(TH_BS) void k_dslash_tile_half(DsBatch B, RhsScal* 
       // hoisting its load): loaded with the centre it holds registers through the hops and
       // halves the resident waves
       asm volatile("" ::: "memory");
-      if (STEP == 2 && (EPI == EPI_RHAT || EPI == EPI_RESID))
+      if (STEP == 2 && EPI != EPI_NONE)
         IO<float>::load((const float4*)L.aux + (long long)r * 6 * Vh, Vh, h, ax);
       zf o[12];
       if (STEP == 1) finish_odd<float>(ce, acc, coef, tm, o);
-      else finish_site<float, EPI>(ce, acc, coef, tm, ax, red[0], red[1], red[2], o);
+      else
+        finish_site<float, EPI>(ce, acc, coef, tm, ax, red, o);
       IO<float>::store((float4*)L.out + (long long)r * 6 * Vh, Vh, h, o);
     }
     if (EPI != EPI_NONE) {
-      __shared__ double sh[3 * (TH_BS / 64)];
-      block_sum<3, TH_BS>(red, sh);
+      __shared__ double sh[DS_NSUM * (TH_BS / 64)];
+      block_sum<DS_NSUM, TH_BS>(red, sh);
       if (tid == 0) {
-        double* pp = partials + ((long long)(L.rhs_base + r) * B.pstride + tile) * 3;
-        pp[0] = red[0];
-        pp[1] = red[1];
-        pp[2] = red[2];
+        store_sums<EPI>(B, partials, L.rhs_base + r, tile, red);
       }
     }
     if (jn < Gc) {
@@ -1331,7 +1377,7 @@ double launch(hipStream_t s, DsBatch& b, int dagger, int epi, RhsScal* sc, doubl
     const double V = b.lat[i].g.V;
     bytes += V * IO<T>::link_bytes();
     bytes += V * b.lat[i].nrhs * 2.0 * IO<T>::spinor_bytes();
-    if (epi == EPI_RHAT || epi == EPI_RESID) bytes += V * b.lat[i].nrhs * IO<T>::spinor_bytes();
+    if (epi != EPI_NONE) bytes += V * b.lat[i].nrhs * IO<T>::spinor_bytes();
   }
   return bytes;
 }

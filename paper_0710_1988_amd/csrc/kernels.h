@@ -29,6 +29,7 @@ enum : int {
 
 struct RhsScal {
   zd rho, rho_prev, alpha, omega, beta;
+  zd rho_next;     // <rhat, r> of the iteration in progress (<rhat, s> - omega <rhat, t>)
   zd dot;          // last <rhat, v>
   double rr;       // recursive ||r||^2
   double rr_true;  // last FP64 ||b - A x||^2
@@ -57,6 +58,9 @@ constexpr int STALL_ITERS = 250;
 // ----------------------------------------------------------------------------- batches
 constexpr int MAXLAT = 8;
 constexpr int DS_BS = 256;  // Dslash threads per block = sites per block
+// running sums per rhs in a Dslash epilogue (the <t, s> one uses all 7: <t, s>, |t|^2,
+// <rhat, t>, <rhat, s>); the partials hold 3 per slot, then 4 per slot in a second region
+constexpr int DS_NSUM = 7;
 
 struct DsLat {
   Geom g;
@@ -154,17 +158,20 @@ inline int ds_partial_slots(const Geom& g) {
 void launch_ds_finalize(hipStream_t s, const DsBatch& b, int epi, RhsScal* sc,
                         const double* partials);
 // spinor vectors moved per processed rhs-site for an epilogue (in, out, and the epilogue operand)
-inline int ds_spinor_passes(int epi) { return (epi == EPI_RHAT || epi == EPI_RESID) ? 3 : 2; }
+inline int ds_spinor_passes(int epi) { return epi != EPI_NONE ? 3 : 2; }
 
 // ----------------------------------------------------------------------------- bicg.hip
-enum BicgOp : int { BI_P = 0, BI_S = 1, BI_XR = 2 };
+// BI_S: r <- s = r - alpha v.  BI_XR: x += alpha p + omega s, r = s - omega t and the next
+// search direction p = r + beta (p - omega v) in one pass (beta from the <t, s> epilogue), with
+// ||r||^2 into the partials.
+enum BicgOp : int { BI_S = 1, BI_XR = 2 };
 // FP64 vectors (double2 elements) or FP32 vectors (float4 elements)
 void bicg_step_f64(hipStream_t s, int op, const VecSet& vs, double2* x, double2* r,
                    const double2* rhat, double2* p, const double2* v, const double2* t,
                    RhsScal* sc, double* partials);
 // BI_XR launches only the update (its inner products into partials): bicg_fin_xr follows.
-// acct (timing only, may be null): the XR step adds its algorithmic bytes (7 vector passes per
-// active rhs) to *acct.
+// acct (timing only, may be null): the XR step adds its algorithmic bytes (8 vector passes per
+// active rhs: x, p, s, t, v read, x, r, p written) to *acct.
 void bicg_fin_xr(hipStream_t s, const VecSet& vs, RhsScal* sc, const double* partials);
 void bicg_step_f32(hipStream_t s, int op, const VecSet& vs, float4* x, float4* r,
                    const float4* rhat, float4* p, const float4* v, const float4* t,

@@ -569,7 +569,8 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
   // ---- scratch for reductions
   int pstride = std::max(vs64.pstride, mixed ? vs32.pstride : 1);
   for (int i = 0; i < nops; ++i) pstride = std::max(pstride, ds_partial_slots(op[i].g));
-  double* partials = ws.get<double>(size_t(NR) * pstride * 3);
+  // 3 doubles per slot, and 4 more for <rhat, t> and <rhat, s> of the <t, s> epilogue
+  double* partials = ws.get<double>(size_t(NR) * pstride * DS_NSUM);
   RhsScal* sc = ws.get<RhsScal>(NR);
   // pinned host area: scalars | norms | cond
   const size_t pin_bytes = sizeof(RhsScal) * NR + sizeof(double) * (2 * NR + MAXLAT) + 256;
@@ -714,11 +715,11 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
     if (mixed) {
       const long long o = off32[base[i]];
       sv.push_back(DsSpec{&op[i], true, p32 + o, v32 + o, rhat32 + o, nrhs[i], base[i]});
-      stt.push_back(DsSpec{&op[i], true, r32 + o, t32 + o, nullptr, nrhs[i], base[i]});
+      stt.push_back(DsSpec{&op[i], true, r32 + o, t32 + o, rhat32 + o, nrhs[i], base[i]});
     } else {
       const long long o = off64[base[i]];
       sv.push_back(DsSpec{&op[i], false, p + o, v + o, rhat + o, nrhs[i], base[i]});
-      stt.push_back(DsSpec{&op[i], false, r64 + o, t + o, nullptr, nrhs[i], base[i]});
+      stt.push_back(DsSpec{&op[i], false, r64 + o, t + o, rhat + o, nrhs[i], base[i]});
     }
   }
   const DsBatch bv = make_batch(sv), bt = make_batch(stt);
@@ -745,7 +746,6 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
 
   auto iterate = [&]() {
     if (mixed) {
-      bicg_step_f32(s, BI_P, vs32, x32, r32, rhat32, p32, v32, t32, sc, partials);
       run_dslash(c, true, bv, dagger, EPI_RHAT, sc, partials);
       bicg_step_f32(s, BI_S, vs32, x32, r32, rhat32, p32, v32, t32, sc, partials);
       run_dslash(c, true, bt, dagger, EPI_TS, sc, partials);
@@ -757,7 +757,6 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
       timer_end(c, 2, e0, 0.0);
       bicg_fin_xr(s, vs32, sc, partials);
     } else {
-      bicg_step_f64(s, BI_P, vs64, x64, r64, rhat, p, v, t, sc, partials);
       run_dslash(c, false, bv, dagger, EPI_RHAT, sc, partials);
       bicg_step_f64(s, BI_S, vs64, x64, r64, rhat, p, v, t, sc, partials);
       run_dslash(c, false, bt, dagger, EPI_TS, sc, partials);
