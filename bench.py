@@ -506,6 +506,8 @@ def main():
         "worst_rel_true_resid": worst,
         "all_converged": ok,
         "mvps_per_source": mv_mixed,
+        "reliable_updates_per_source": float(np.mean([x["reliable_updates"] for x in stats])),
+        "fp64_continued_sources": int(sum(x["fp64_continued"] for x in stats)),
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic),

@@ -85,7 +85,8 @@ typedef struct {
   double rel_true_resid;    /* ||b - A x|| / ||b|| in FP64 at exit */
   double seconds;           /* wall time of the call (shared by all rhs of a call) */
   int32_t status;           /* dbq_status of this right-hand side */
-  int32_t pad;
+  int32_t fp64_continued;   /* mixed precision: 1 if the FP32 iteration stalled, diverged or
+                               overflowed and the FP64 solver finished this rhs, else 0 */
 } dbq_stats;
 
 /* Context: hip_stream is a hipStream_t (NULL = the null stream).  The stream must live as long

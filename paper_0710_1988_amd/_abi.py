@@ -34,7 +34,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("matvecs", ctypes.c_int64), ("iterations", ctypes.c_int64),
                 ("restarts", ctypes.c_int64), ("reliable_updates", ctypes.c_int64),
                 ("rel_true_resid", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("status", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("status", ctypes.c_int32), ("fp64_continued", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"} | {

@@ -1024,7 +1024,7 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
     o.reliable_updates = relup[j] + hs[j].nrel;
     o.rel_true_resid = hs[j].bb > 0 ? std::sqrt(rrt[j] / hs[j].bb) : 0.0;
     o.status = status[j];
-    o.pad = 0;
+    o.fp64_continued = 0;
   }
 
   // ---- rhs whose FP32 iteration stalled, diverged or broke down with a non-finite value:
@@ -1084,6 +1084,7 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
         o.restarts += r.restarts;
         o.rel_true_resid = r.rel_true_resid;
         o.status = r.status;
+        o.fp64_continued = 1;
       }
     }
     DBQ_HIP(hipStreamSynchronize(s));
@@ -1300,7 +1301,7 @@ int gmresdr(dbq_ctx* c, const dbq_operator* o, const void* b, void* x, int m, in
   st->rel_true_resid = std::sqrt(hp[0]) / bn;
   st->seconds = now_s() - t0;
   st->status = conv ? DBQ_OK : DBQ_NOT_CONVERGED;
-  st->pad = 0;
+  st->fp64_continued = 0;
   return st->status;
 }
 
@@ -1590,7 +1591,7 @@ int gmres_proj(dbq_ctx* c, const dbq_operator* o, const void* Vin, int k, const 
     o2.reliable_updates = 0;
     o2.rel_true_resid = bn[j] > 0 ? std::sqrt(hp[0]) / bn[j] : 0.0;
     o2.status = conv ? DBQ_OK : DBQ_NOT_CONVERGED;
-    o2.pad = 0;
+    o2.fp64_continued = 0;
   }
   if (op.schur) schur_solution(c, ws, op, x64, bodd, X, nrhs, 0);
   else unpack_spinor_f64(s, op.g, x64, X, nrhs);
