@@ -362,6 +362,7 @@ def leg_c5(dbq, torch, synth, schur=False):
             prec="mixed", max_mv=40000))
         shifts.append(dict(mu=m, solve_s=round(t, 3), status=status,
                            mvps_per_source=float(np.mean([x["matvecs"] for x in st])),
+                           fp64_continued=int(sum(x["fp64_continued"] for x in st)),
                            worst_rel_true_resid=max(x["rel_true_resid"] for x in st),
                            mr_resid_before_after=None if r0 is None else
                            [float(np.mean(r0)), float(np.mean(r1))]))
