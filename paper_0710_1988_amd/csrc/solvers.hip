@@ -804,9 +804,10 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
     // x64 += x32 and the FP64 residual; the residual's finalize stops the converged ones and the
     // others continue from the replaced residual.  The host only polls for rhs that finished,
     // broke down or ran out of MVPs, at intervals that double up to 32 iterations.
-    // (every = 8: on 16^4 with 12 sources 2, 4, 6 and 8 give the same iterations and products;
-    // 8 launches the gated FP64 residual half as often as 4 and is 1.5% faster per source)
-    int every = 8;
+    // (every = 16: a flagged rhs idles until the next check, so the interval changes no
+    // iteration or product count; on 16^4 with 6 x 12 sources 8 -> 16 is 0.7% faster per source,
+    // 24 and 32 are 3% slower than 16: the last rhs of a batch waits longer for its check)
+    int every = 16;
     if (const char* e = std::getenv("DBQ_RELUP_EVERY")) every = std::max(1, std::atoi(e));
     DsBatch bres_dec = bres;
     bres_dec.decide = 1;
