@@ -6,8 +6,8 @@
 // omega <rhat, t> and beta,  BI_XR (x += alpha p + omega s; r = s - omega t;
 // p = r + beta (p - omega v); ||r||^2 -> tests).  Folding the search-direction update into the
 // XR pass saves a launch and three vector passes per iteration (the epilogue reads rhat, the XR
-// pass v, instead of rhat in XR and r, p, v, p in a separate pass); a reliable update replaces
-// rho by <rhat, r> of the FP64 residual.
+// pass v, instead of rhat in XR and r, p, v, p in a separate pass).  A reliable update restarts
+// the recursion from the FP64 residual: r = rhat = p = b - A x, rho = ||r||^2.
 // The scalars live in RhsScal on the device.  Each streaming kernel stores one partial sum per
 // block; a small follow-up launch combines them per right-hand side in a fixed order, so the
 // results do not depend on block scheduling and no device-scope fence stalls the stream.
@@ -235,24 +235,16 @@ __device__ void fin_aux(int op, RhsScal& q, double a0, double a1, double a2) {
     q.active = 1;
     q.sel = 0;
     q.since = 0;
-  } else {  // AX_REPLACE
+  } else {  // AX_REPLACE: the recursion restarts from the FP64 residual (rhat = p = r)
     if (!q.sel) return;
-    const zd rn{a0, a1};
-    // The search direction p = r + beta d (d = p_prev - omega v) was formed with the beta of
-    // the FP32 rho; the one of the replaced residual is r_new + (rn / rho) beta d, so the replace
-    // kernel that follows takes p <- r_new + c (p - r_old) with c = rn / rho, held in beta until
-    // the next <t, s> epilogue sets beta again.  sel stays set for that kernel.
-    q.beta = (q.rho.re != 0.0 || q.rho.im != 0.0) ? cdiv(rn, q.rho) : zd{0.0, 0.0};
-    q.rho = rn;
+    q.rho = zd{a2, 0.0};
+    q.rhat2 = a2;
     q.rr = a2;
     q.rr_max = a2;
     q.flags = 0;
     q.active = 1;
+    q.sel = 0;
     q.since = 0;
-    if (norm2(rn) <= 1e-28 * q.rhat2 * a2) {
-      q.flags = F_BREAK;
-      q.active = 0;
-    }
   }
 }
 
@@ -277,11 +269,10 @@ __global__ __launch_bounds__(BL_BS) void k_aux64(VecSet vs, const double2* __res
       if (idx >= ne) continue;
       const long long i = base + idx;
       if (OP == AX_REPLACE) {
-        // sums only: the replace kernel writes r and p once c is known
         const double2 a = r64[i];
-        const double2 h = rhat[i];
-        red[0] += h.x * a.x + h.y * a.y;
-        red[1] += h.x * a.y - h.y * a.x;
+        r[i] = a;
+        rhat[i] = a;
+        p[i] = a;
         red[2] += a.x * a.x + a.y * a.y;
       } else {
         const double2 a = r[i];
@@ -325,93 +316,16 @@ __global__ __launch_bounds__(BL_BS) void k_aux32(VecSet vs, VecSet vs64,
         const double2 d0 = r64[base64 + 2 * (long long)idx];
         const double2 d1 = r64[base64 + 2 * (long long)idx + 1];
         const float4 a = make_float4(float(d0.x), float(d0.y), float(d1.x), float(d1.y));
-        if (OP == AX_INIT) {
-          r[i] = a;
-          rhat[i] = a;
-          p[i] = a;
-          x32[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-        } else {
-          // sums of the narrowed residual only: the replace kernel writes r and p
-          const float4 h = rhat[i];
-          red[0] += double(h.x) * a.x + double(h.y) * a.y + double(h.z) * a.z + double(h.w) * a.w;
-          red[1] += double(h.x) * a.y - double(h.y) * a.x + double(h.z) * a.w - double(h.w) * a.z;
-        }
+        // init, or a replacement that restarts from the narrowed FP64 residual
+        r[i] = a;
+        rhat[i] = a;
+        p[i] = a;
+        if (OP == AX_INIT) x32[i] = make_float4(0.f, 0.f, 0.f, 0.f);
         red[2] += double(a.x) * a.x + double(a.y) * a.y + double(a.z) * a.z + double(a.w) * a.w;
       }
     }
   }
   store_partial(vs, partials, rhs, ch, red);
-}
-
-// Second pass of a residual replacement: r <- r_new, p <- r_new + c (p - r_old) with c = rn / rho
-// (in beta) for the selected rhs.  FP32 vectors take r_new narrowed from the FP64 residual.
-template <typename E>
-__device__ __forceinline__ void repl_elem(E* r, E* p, long long i, const cx<typename ET<E>::R> (&a)[ET<E>::NC],
-                                          cx<typename ET<E>::R> c) {
-  typedef typename ET<E>::R R;
-  constexpr int NC = ET<E>::NC;
-  cx<R> o[NC], q[NC];
-  ET<E>::ld(r, i, o);
-  ET<E>::ld(p, i, q);
-#pragma unroll
-  for (int k = 0; k < NC; ++k) q[k] = a[k] + c * (q[k] - o[k]);
-  ET<E>::st(r, i, a);
-  ET<E>::st(p, i, q);
-}
-
-__global__ __launch_bounds__(BL_BS) void k_repl64(VecSet vs, const double2* __restrict__ r64,
-                                                  double2* __restrict__ r, double2* __restrict__ p,
-                                                  const RhsScal* __restrict__ sc) {
-  const int lb = xcd_block(blockIdx.x, vs.nblocks);
-  const int2 bm = vs.blk[lb];
-  const int rhs = bm.x, ch = bm.y;
-  if (!sc[rhs].sel) return;
-  const long long base = vs.off[rhs];
-  const int ne = vs.nelem[rhs];
-  const zd c = sc[rhs].beta;
-  for (int e = 0; e < BL_EPT; ++e) {
-    const int idx = ch * BL_CHUNK + e * BL_BS + threadIdx.x;
-    if (idx >= ne) continue;
-    const long long i = base + idx;
-    const double2 d = r64[i];
-    const zd a[1] = {zd{d.x, d.y}};
-    repl_elem<double2>(r, p, i, a, c);
-  }
-}
-
-__global__ __launch_bounds__(BL_BS) void k_repl32(VecSet vs, VecSet vs64,
-                                                  const double2* __restrict__ r64,
-                                                  float4* __restrict__ r, float4* __restrict__ p,
-                                                  const RhsScal* __restrict__ sc) {
-  const int lb = xcd_block(blockIdx.x, vs.nblocks);
-  const int2 bm = vs.blk[lb];
-  const int rhs = bm.x, ch = bm.y;
-  if (!sc[rhs].sel) return;
-  const long long base = vs.off[rhs];
-  const long long base64 = vs64.off[rhs];
-  const int ne = vs.nelem[rhs];
-  const zf c = narrow<float>(sc[rhs].beta);
-  for (int e = 0; e < BL_EPT; ++e) {
-    const int idx = ch * BL_CHUNK + e * BL_BS + threadIdx.x;
-    if (idx >= ne) continue;
-    const long long i = base + idx;
-    const double2 d0 = r64[base64 + 2 * (long long)idx];
-    const double2 d1 = r64[base64 + 2 * (long long)idx + 1];
-    const zf a[2] = {zf{float(d0.x), float(d0.y)}, zf{float(d1.x), float(d1.y)}};
-    repl_elem<float4>(r, p, i, a, c);
-  }
-}
-
-// ends a replacement: no rhs stays selected
-__global__ __launch_bounds__(BL_BS) void k_clear_sel(int nrhs, RhsScal* __restrict__ sc) {
-  const int j = blockIdx.x * BL_BS + threadIdx.x;
-  if (j < nrhs) sc[j].sel = 0;
-}
-
-void launch_clear_sel(hipStream_t s, const VecSet& vs, RhsScal* sc) {
-  hipLaunchKernelGGL(k_clear_sel, dim3((vs.nrhs + BL_BS - 1) / BL_BS), dim3(BL_BS), 0, s, vs.nrhs,
-                     sc);
-  DBQ_HIP(hipGetLastError());
 }
 
 __global__ __launch_bounds__(BL_BS) void k_xacc(VecSet vs, VecSet vs64, double2* __restrict__ x64,
@@ -487,12 +401,7 @@ void bicg_aux_f64(hipStream_t s, int op, const VecSet& vs, const double2* r64, d
   DBQ_HIP(hipGetLastError());
   if (op == AX_INIT) launch_fin_aux<AX_INIT>(s, vs, sc, partials);
   else if (op == AX_RESTART) launch_fin_aux<AX_RESTART>(s, vs, sc, partials);
-  else {
-    launch_fin_aux<AX_REPLACE>(s, vs, sc, partials);
-    hipLaunchKernelGGL(k_repl64, g, b, 0, s, vs, r64, r, p, sc);
-    DBQ_HIP(hipGetLastError());
-    launch_clear_sel(s, vs, sc);
-  }
+  else launch_fin_aux<AX_REPLACE>(s, vs, sc, partials);
 }
 
 void bicg_aux_f32(hipStream_t s, int op, const VecSet& vs32, const VecSet& vs64,
@@ -511,12 +420,7 @@ void bicg_aux_f32(hipStream_t s, int op, const VecSet& vs32, const VecSet& vs64,
   DBQ_HIP(hipGetLastError());
   if (op == AX_INIT) launch_fin_aux<AX_INIT>(s, vs32, sc, partials);
   else if (op == AX_RESTART) launch_fin_aux<AX_RESTART>(s, vs32, sc, partials);
-  else {
-    launch_fin_aux<AX_REPLACE>(s, vs32, sc, partials);
-    hipLaunchKernelGGL(k_repl32, g, b, 0, s, vs32, vs64, r64, r, p, sc);
-    DBQ_HIP(hipGetLastError());
-    launch_clear_sel(s, vs32, sc);
-  }
+  else launch_fin_aux<AX_REPLACE>(s, vs32, sc, partials);
 }
 
 void bicg_xacc(hipStream_t s, const VecSet& vs32, const VecSet& vs64, double2* x64, float4* x32,

@@ -176,8 +176,9 @@ void bicg_fin_xr(hipStream_t s, const VecSet& vs, RhsScal* sc, const double* par
 void bicg_step_f32(hipStream_t s, int op, const VecSet& vs, float4* x, float4* r,
                    const float4* rhat, float4* p, const float4* v, const float4* t,
                    RhsScal* sc, double* partials, unsigned long long* acct = nullptr);
-// init: r (FP64) -> working r (copy or narrowed), rhat = r, p = v = 0, x32 = 0 (mixed),
-//       rho = ||r||^2 ... ; mode 0: all rhs with active != 0; uses `sel` when only_sel
+// AX_INIT (rhs with active != 0): working r = r64 (copy or narrowed), rhat = p = r, x32 = 0
+// (mixed); AX_RESTART (sel != 0): rhat = p = r; AX_REPLACE (sel != 0): r = rhat = p = r64, the
+// FP64 residual (narrowed in FP32).  Each sets rho = ||r||^2 through its finalize.
 enum BicgAux : int { AX_INIT = 0, AX_RESTART = 1, AX_REPLACE = 2 };
 void bicg_aux_f64(hipStream_t s, int op, const VecSet& vs, const double2* r64, double2* r,
                   double2* rhat, double2* p, double2* v, RhsScal* sc, double* partials);

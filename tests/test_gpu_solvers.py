@@ -406,9 +406,10 @@ def test_mixed_solve_beyond_fp32_range_continues_in_fp64(gpu_lib):
     X, st, status = gpu_lib.dbicgstab_solve(
         [dict(L=L, links=dev(U), kappa=kappa, B=dev(B * 1e25), V=V)], tol=1e-8, prec="mixed")
     assert status == 0, st
+    assert [s["fp64_continued"] for s in st] == [1, 1], st
     X1, st1, status1 = gpu_lib.dbicgstab_solve(
         [dict(L=L, links=dev(U), kappa=kappa, B=dev(B), V=V)], tol=1e-10, prec="fp64")
-    assert status1 == 0
+    assert status1 == 0 and [s["fp64_continued"] for s in st1] == [0, 0]
     Xh, X1h = host(X[0]), host(X1[0])
     for j in range(2):
         b = (B[j] * 1e25).reshape(-1)
