@@ -620,9 +620,12 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
     q.bb = hn[j];
     q.stop2 = tol * tol * hn[j];
     // reliable update (FP64 residual, then a restart of the FP32 recursion from it) when ||r||
-    // drops by 100x: on 16^4 x 72 sources this needs 15% fewer products than replacing r at 10x
-    // drops and keeping rhat and p, and the C5 twisted-mass shifts stop stagnating in FP32
-    q.delta2 = mixed ? 1e-4 : 0.0;
+    // drops by 1000x.  Against replacing r at 10x drops and keeping rhat and p, restarts stop
+    // the FP32 recursion from stagnating on the twisted-mass shifts at kappa_c and save products
+    // on 16^4.  Measured drop factors 30 / 100 / 300 / 1000, ms per source on 16^4 x 72 sources:
+    // 13.1 / 12.6 / 12.8 / 12.1; 20^3 x 32 x 24: 47.9 / 42.6 / 39.2 / 39.6; seconds for the
+    // mu = 0.0015 shift on 24^3 x 48 x 12: 11.6 / 12.7 / 11.6 / 14.5
+    q.delta2 = mixed ? 1e-6 : 0.0;
     q.sel = hn[NR + j] > 0.0 ? 1 : 0;
     if (q.sel) {
       any_x0 = true;
