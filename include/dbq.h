@@ -145,6 +145,10 @@ int gmresdr_first_rhs(dbq_ctx* ctx, const dbq_operator* op, const void* b, void*
  * V[i]: DEVICE complex128 column-major n_i x k[i] (k[i] = 0: no deflation, plain BiCGStab).
  * B[i]: DEVICE complex128 [nrhs[i]][V_i][12]; X[i]: same shape, in: x0, out: solution.
  * per_rhs: HOST array of sum(nrhs) stats, in operator order.  prec: dbq_prec.
+ * DBQ_MIXED runs the BiCGStab recursion in FP32 and, whenever its residual norm has fallen 1000x
+ * (or after 500 iterations without that), computes b - A x in FP64 and restarts the recursion
+ * from it (rhat = p = r); a right-hand side on which the FP32 recursion stalls, diverges or
+ * overflows is finished by the FP64 solver (per_rhs[j].fp64_continued = 1).
  * With schur = 1 (the same for every operator of the call) V[i] holds eigenvectors of Ahat as
  * full vectors with zero odd sites (as gmresdr_first_rhs returns them), the iteration runs on
  * Ahat, and X[i] receives the full solution; rel_true_resid is ||bhat - Ahat x_e|| / ||b||, which
