@@ -415,3 +415,28 @@ def test_mixed_solve_beyond_fp32_range_continues_in_fp64(gpu_lib):
         b = (B[j] * 1e25).reshape(-1)
         assert _true_rel(U, lat, kappa, 0.0, Xh[j].reshape(-1), b) <= 1.0001e-8
         assert np.linalg.norm(Xh[j] - 1e25 * X1h[j]) <= 1e-6 * np.linalg.norm(1e25 * X1h[j])
+
+
+def test_mixed_solve_reaches_a_tolerance_below_fp32_precision(gpu_lib):
+    """8^4 near kappa_c to a relative residual of 1e-10, below what an FP32 recursion can resolve:
+    the mixed solve gets there through several FP64 reliable updates, each restarting the FP32
+    recursion from the FP64 residual, without the FP64 fallback; the oracle's FP64 residual of
+    every solution confirms the tolerance."""
+    L = (8, 8, 8, 8)
+    lat = W.Lattice(L)
+    U = synth.gauge_field(L, 0.6, 1031)
+    kc, _, _, st = gpu_lib.kappa_critical(L, dev(U), m=48, k=16, tol=1e-10)
+    assert st == 0
+    kap = 0.99 * kc
+    _, V, _, gst = gpu_lib.gmresdr_first_rhs(L, dev(U), dev(synth.point_source(L)), kap, 40, 20,
+                                             tol=1e-10)
+    assert gst["status"] == 0
+    B = synth.z2_sources(L, 4, 2031)
+    X, stats, status = gpu_lib.dbicgstab_solve(
+        [dict(L=L, links=dev(U), kappa=kap, B=dev(B), V=V)], tol=1e-10, prec="mixed")
+    assert status == 0, stats
+    assert all(s["fp64_continued"] == 0 and s["reliable_updates"] >= 3 for s in stats), stats
+    Xh = host(X[0])
+    for j in range(4):
+        rel = _true_rel(U, lat, kap, 0.0, Xh[j].reshape(-1), B[j].reshape(-1))
+        assert rel <= 1.0001e-10, (j, rel)
