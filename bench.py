@@ -404,7 +404,7 @@ def main():
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the solve of "
-              "independent sources would shard over GPUs with no communication; see DESIGN.md)",
+              "independent sources would shard over GPUs, each GPU solving its own sources with its own copy of the deflation vectors)",
               file=sys.stderr)
         sys.exit(2)
 
