@@ -403,9 +403,9 @@ def main():
                          "for hardware byte counters)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the solve of "
-              "independent sources would shard over GPUs, each GPU solving its own sources with its own copy of the deflation vectors)",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (the solve of "
+              "independent sources would shard over GPUs, each GPU solving its own sources with "
+              "its own copy of the deflation vectors)", file=sys.stderr)
         sys.exit(2)
 
     import torch
