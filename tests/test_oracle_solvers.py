@@ -215,6 +215,63 @@ def test_dbicgstab_adjoint_roles_swap():
 
 
 # ----------------------------------------------------------------------------- MR projection
+def test_gmresdr_from_nonzero_x0_matches_dense_solve():
+    """GMRES-DR started from x0 != 0 (as in the Sec. 4 shift sequence) solves A x = b, not a
+    problem with the sign of r0 flipped: the solution matches a dense solve to the conditioning
+    of the tolerance; the initial residual costs one product, so matvecs = 1 + m + (m-k)(c-1).
+    From x0 = x* + 1e-3 e the start sits near the solution: fewer cycles than from zero reach
+    x* (a flipped r0 = A x0 - b would land at 2 x0 - x*, an error of 2e-3 ||e||)."""
+    L = (2, 2, 2, 4)
+    lat, U, A = _setup(L, 0.6, 41, 0.16, 0.02)
+    M = W.dense_matrix(U, lat, 0.16, 0.02)
+    b = synth.z2_sources(L, 1, 42)[0].reshape(-1)
+    xe = np.linalg.solve(M, b)
+    cond = np.linalg.cond(M)
+    x0 = synth.gaussian_sources(L, 1, 43)[0].reshape(-1)
+    x, V, th, info = S.gmresdr(A, b, 12, 4, tol=1e-10, x0=x0)
+    assert info["status"] == S.OK
+    assert info["matvecs"] == 1 + 12 + 8 * (info["cycles"] - 1)
+    assert np.linalg.norm(x - xe) <= 1e-10 * cond * np.linalg.norm(xe)
+    assert np.linalg.norm(b - M @ x) <= 1.0001e-10 * np.linalg.norm(b)
+    e = synth.gaussian_sources(L, 1, 44)[0].reshape(-1)
+    xs = xe + 1e-3 * e / np.linalg.norm(e) * np.linalg.norm(xe)
+    x, _, _, info = S.gmresdr(A, b, 12, 4, tol=1e-8, x0=xs)
+    _, _, _, info0 = S.gmresdr(A, b, 12, 4, tol=1e-8)
+    assert info["status"] == S.OK and info["cycles"] < info0["cycles"]
+    assert info["matvecs"] == 1 + 12 + 8 * (info["cycles"] - 1)
+    assert np.linalg.norm(x - xe) <= 1e-8 * cond * np.linalg.norm(xe)
+
+
+def test_mr_projection_from_nonzero_x0_matches_lstsq():
+    """The Sec. 4 projection from x0 != 0: d minimises ||(b - A x0) - A Q d|| (checked against
+    lstsq on the dense matrix), x = x0 + Q d, the returned residual is b - A x, the reported
+    initial norm is ||b - A x0||, and the products are 1 (for r0) + nq."""
+    L = (4, 2, 2, 2)
+    lat = W.Lattice(L)
+    U = synth.gauge_field(L, 0.6, 27)
+    b = synth.z2_sources(L, 1, 28)[0].reshape(-1)
+    mus = [0.05, 0.03, 0.02]
+    Q = np.stack([np.linalg.solve(W.dense_matrix(U, lat, 0.15, m), b) for m in mus], axis=1)
+    Mn = W.dense_matrix(U, lat, 0.15, 0.01)
+    A = W.operator(U, lat, 0.15, 0.01)
+    x0 = 0.5 * Q[:, -1] + 0.1 * synth.gaussian_sources(L, 1, 29)[0].reshape(-1)
+    x, r, info = S.mr_project(A, Q, b, x0=x0)
+    r0 = b - Mn @ x0
+    d_ls = np.linalg.lstsq(Mn @ Q, r0, rcond=None)[0]
+    assert info["matvecs"] == 1 + 3
+    assert abs(info["rnorm_before"] - np.linalg.norm(r0)) <= 1e-12 * np.linalg.norm(r0)
+    assert np.linalg.norm(info["d"] - d_ls) <= 1e-8 * np.linalg.norm(d_ls)
+    assert np.linalg.norm(x - (x0 + Q @ d_ls)) <= 1e-8 * np.linalg.norm(x)
+    assert np.linalg.norm(r - (b - Mn @ x)) <= 1e-11 * np.linalg.norm(b)
+    assert info["rnorm_after"] <= info["rnorm_before"]
+    # starting from x0 gives the residual of the best x in x0 + span(Q), which is at most the
+    # residual of the projection from zero over span(Q) when x0 lies in span(Q)
+    x0q = Q @ np.array([0.2, -0.1, 0.7])
+    _, r_q, _ = S.mr_project(A, Q, b, x0=x0q)
+    _, r_z, _ = S.mr_project(A, Q, b)
+    assert abs(np.linalg.norm(r_q) - np.linalg.norm(r_z)) <= 1e-10 * np.linalg.norm(b)
+
+
 def test_mr_projection_minimises_residual():
     L = (4, 2, 2, 2)
     lat = W.Lattice(L)
