@@ -114,6 +114,27 @@ int dbq_geometry_host(const int32_t L[4], int32_t* lex_of_eo, int32_t* nbr);
  * only; DBQ_EINVAL for odd or < 2 extents. */
 int dbq_site_tile(const int32_t L[4], int32_t* T);
 
+/* Processing order of the LDS-staged FP32 Dslash over (tile, rhs chunk) pairs, for inspection
+ * (host only).  A launch with nchunks chunks of right-hand sides runs ntiles * nchunks blocks,
+ * ntiles = prod_mu L_mu / T_mu (tiles of dbq_site_tile, numbered lexicographically); logical
+ * block b (blocks reach the eight XCDs in contiguous ranges of b) processes tile[b] and chunk[b].
+ * order 0: tiles in lexicographic order, the chunks of one tile adjacent; order 1: the tile grid
+ * cut in halves along x, y and z into eight regions taken one after the other, tiles
+ * lexicographic inside a region, chunks adjacent; order 2: the regions of order 1, inside a
+ * region every tile for one chunk before the next chunk.  tile, chunk: HOST int32
+ * [ntiles * nchunks].  DBQ_EINVAL for odd extents, nchunks < 1 or another order. */
+int dbq_tile_schedule_host(const int32_t L[4], int32_t nchunks, int32_t order, int32_t* tile,
+                           int32_t* chunk);
+
+/* Streaming probe of the practical HBM ceiling: kind 0 copies bytes from src to dst, kind 1 reads
+ * src (writing one float per block to dst, 2048 floats), kind 2 fills dst;
+ * hand-written float4 kernels, launched reps times after one warm-up on the context stream,
+ * timed with HIP events.  src, dst: DEVICE, bytes a multiple of 16.  *ms (HOST) = average
+ * milliseconds per launch; bytes moved per launch: 2 x bytes (copy) or bytes (read, fill).
+ * Synchronises the stream. */
+int dbq_stream_probe(dbq_ctx* ctx, const void* src, void* dst, int64_t bytes, int32_t kind,
+                     int32_t reps, double* ms);
+
 /* out = A(mu) in (dagger = 0) or A(mu)^dagger in (dagger = 1) for nrhs right-hand sides
  * (Sec. 1 operator; the matrix-vector product every solver in the paper is costed in); with
  * op->schur = 1, out_e = Ahat in_e (or its dagger) and out_o = 0.

@@ -20,7 +20,8 @@ from ._abi import DBQ_FP64, DBQ_MIXED, Stats, Operator
 
 __all__ = ["DbqError", "wilson_apply", "gmresdr_first_rhs", "dbicgstab_solve", "project_shifts",
            "link_force", "kappa_critical", "geometry", "geometry_host", "site_tile", "set_timing",
-           "kernel_time", "reset_timing", "version", "library_path", "DeflatedSolve"]
+           "kernel_time", "reset_timing", "version", "library_path", "DeflatedSolve",
+           "tile_schedule_host", "stream_probe"]
 
 
 class DbqError(RuntimeError):
@@ -374,6 +375,46 @@ def site_tile(L):
     if st != 0:
         raise DbqError(st, "dbq_site_tile failed")
     return tuple(int(v) for v in T)
+
+
+def tile_schedule_host(L, nchunks, order):
+    """(tile, chunk) visited by each logical block of an LDS-tile Dslash launch with ``nchunks``
+    chunks of right-hand sides in tile order ``order`` (0, 1 or 2), as numpy int32 arrays."""
+    L, V = _lattice(L)
+    T = site_tile(L)
+    nt = (L[0] // T[0]) * (L[1] // T[1]) * (L[2] // T[2]) * (L[3] // T[3])
+    tile = np.empty(nt * int(nchunks), dtype=np.int32)
+    chunk = np.empty(nt * int(nchunks), dtype=np.int32)
+    PI = ctypes.POINTER(ctypes.c_int32)
+    st = _abi.load().dbq_tile_schedule_host((ctypes.c_int32 * 4)(*L), int(nchunks), int(order),
+                                            tile.ctypes.data_as(PI), chunk.ctypes.data_as(PI))
+    if st != 0:
+        raise DbqError(st, "dbq_tile_schedule_host failed")
+    return tile, chunk
+
+
+def stream_probe(src, dst, kind=0, reps=10):
+    """Average milliseconds of the library's hand-written streaming kernel over ``src``/``dst``
+    (device tensors of equal byte size): kind 0 copy, 1 read (dst receives per-block sums),
+    2 fill dst."""
+    torch = _torch()
+    if not (isinstance(dst, torch.Tensor) and dst.is_cuda and dst.is_contiguous()):
+        raise ValueError("dst must be a contiguous GPU tensor")
+    nbytes = dst.numel() * dst.element_size()
+    if kind != 2:
+        if not (isinstance(src, torch.Tensor) and src.is_cuda and src.is_contiguous()):
+            raise ValueError("src must be a contiguous GPU tensor")
+        nbytes = src.numel() * src.element_size()
+        if kind == 0 and dst.numel() * dst.element_size() < nbytes:
+            raise ValueError("dst smaller than src")
+        if kind == 1 and dst.numel() * dst.element_size() < 4 * 2048:
+            raise ValueError("dst must hold one float per block (8 KiB)")
+    h = _ctx(dst.device)
+    ms = ctypes.c_double(0)
+    sp = ctypes.c_void_p(src.data_ptr() if kind != 2 else 0)
+    _check(_abi.load().dbq_stream_probe(h, sp, ctypes.c_void_p(dst.data_ptr()), int(nbytes),
+                                        int(kind), int(reps), ctypes.byref(ms)), h, ok=(0,))
+    return ms.value
 
 
 def set_timing(on, device=None):

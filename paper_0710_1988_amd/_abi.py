@@ -21,7 +21,7 @@ EXPORTED = ["dbq_create", "dbq_destroy", "dbq_last_error", "dbq_set_stream", "db
             "dbq_geometry_host", "dbq_site_tile", "wilson_apply", "gmresdr_first_rhs", "dbicgstab_solve",
             "project_shifts", "gmres_proj_solve", "link_force", "kappa_critical", "dbq_set_timing",
             "dbq_kernel_time",
-            "dbq_reset_timing", "dbq_version"]
+            "dbq_reset_timing", "dbq_version", "dbq_tile_schedule_host", "dbq_stream_probe"]
 
 
 class Operator(ctypes.Structure):
@@ -78,6 +78,8 @@ def load():
         "dbq_kernel_time": ([P, I32, PD, ctypes.POINTER(I64), PD], ctypes.c_int),
         "dbq_reset_timing": ([P], ctypes.c_int),
         "dbq_version": ([], ctypes.c_char_p),
+        "dbq_tile_schedule_host": ([PI32, I32, I32, PI32, PI32], ctypes.c_int),
+        "dbq_stream_probe": ([P, P, P, I64, I32, I32, PD], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)

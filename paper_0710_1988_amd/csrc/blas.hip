@@ -2,6 +2,8 @@
 // U = gamma5 V), the minimal-residual projection over previous solutions (Sec. 4) and the
 // Gram-Schmidt steps of GMRES-DR's Arnoldi process.  All of them stream long vectors once and
 // are bound by HBM bandwidth; the gamma5 of the left vectors is a sign folded into the loads.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace dbq {
@@ -124,6 +126,160 @@ void gram_impl(hipStream_t s, const double2* A, long long lda, int na, const dou
   DBQ_HIP(hipGetLastError());
   hipLaunchKernelGGL((k_gram_final<TA, TB>), dim3(unsigned(ntA * ntB)), dim3(G_BS), 0, s, work,
                      nchunks, ntA, ntB, na, nb, C);
+  DBQ_HIP(hipGetLastError());
+}
+
+// ---- Gram products with several columns on both sides, on FP64 matrix cores.
+// The complex product conj(a) b over the interleaved (re, im) doubles of the two vectors is two
+// real inner products: Re = sum_k a[k] b[k] and Im = sum_k a[k] b'[k] with b' = (im, -re) per
+// element.  v_mfma_f64_16x16x4f64 accumulates a 16 x 16 block D += X Y over 4 values of k, where
+// lane l supplies X[l % 16][l / 16] and Y[l / 16][l % 16] and holds D[l / 16 + 4 v][l % 16] in
+// its accumulator value v (rows interleaved across the lane groups; checked on the device).  The order of k inside a sum is free, so lane group q = l / 16
+// of a wave takes the four doubles k0 + 4q .. k0 + 4q + 3 of a 16-double chunk of every column
+// (a contiguous 32-byte load; the four groups cover one 128-byte line of each column) and feeds
+// them to four successive instructions.  A wave keeps the whole (16 TA) x (16 TB) product of its
+// chunks in accumulators, so each element of every column is read once per launch (the tiled
+// FMA kernel reads each chunk once per 8 x 4 tile).  Chunks never straddle the gamma5 sign
+// boundary at 12 V doubles (V, a product of four even extents, is a multiple of 16).
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int GM_BS = 256;           // 4 waves
+constexpr int GM_CHUNK = 16;         // doubles per column per wave step
+constexpr int GM_MAX_BLOCKS = 512;
+
+template <int TA, int TB>
+__global__ __launch_bounds__(GM_BS) void k_gram_mfma(const double* __restrict__ A, long long lda,
+                                                     int na, const double* __restrict__ B,
+                                                     long long ldb, int nb, long long n2,
+                                                     long long half2, int g5,
+                                                     double* __restrict__ work) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int q = lane >> 4, r = lane & 15;
+  f64x4 accR[TA][TB], accI[TA][TB];
+#pragma unroll
+  for (int a = 0; a < TA; ++a)
+#pragma unroll
+    for (int b = 0; b < TB; ++b) {
+      accR[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+      accI[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    }
+  // column of each tile this lane reads (rows past na / nb read a valid column and are dropped
+  // by the final reduction)
+  const double* ap[TA];
+  const double* bp[TB];
+#pragma unroll
+  for (int a = 0; a < TA; ++a) ap[a] = A + (long long)min(16 * a + r, na - 1) * lda;
+#pragma unroll
+  for (int b = 0; b < TB; ++b) bp[b] = B + (long long)min(16 * b + r, nb - 1) * ldb;
+  const long long nchunks = (n2 + GM_CHUNK - 1) / GM_CHUNK;
+  const long long stride = (long long)gridDim.x * (GM_BS / 64);
+  for (long long ch = (long long)blockIdx.x * (GM_BS / 64) + wv; ch < nchunks; ch += stride) {
+    const long long k0 = ch * GM_CHUNK + 4 * q;
+    double av[TA][4], bv[TB][4];
+    if (k0 + 4 <= n2) {
+#pragma unroll
+      for (int a = 0; a < TA; ++a) {
+        const double2 u = *(const double2*)(ap[a] + k0);
+        const double2 w = *(const double2*)(ap[a] + k0 + 2);
+        av[a][0] = u.x; av[a][1] = u.y; av[a][2] = w.x; av[a][3] = w.y;
+      }
+#pragma unroll
+      for (int b = 0; b < TB; ++b) {
+        const double2 u = *(const double2*)(bp[b] + k0);
+        const double2 w = *(const double2*)(bp[b] + k0 + 2);
+        bv[b][0] = u.x; bv[b][1] = u.y; bv[b][2] = w.x; bv[b][3] = w.y;
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const bool in = k0 + t < n2;
+#pragma unroll
+        for (int a = 0; a < TA; ++a) av[a][t] = in ? ap[a][k0 + t] : 0.0;
+#pragma unroll
+        for (int b = 0; b < TB; ++b) bv[b][t] = in ? bp[b][k0 + t] : 0.0;
+      }
+    }
+    if (g5 && ((k0 / half2) & 1)) {
+#pragma unroll
+      for (int a = 0; a < TA; ++a)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) av[a][t] = -av[a][t];
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+#pragma unroll
+      for (int b = 0; b < TB; ++b) {
+        // b' = (im, -re): the partner double of k0 + t, negated when t is odd
+        const double bi = (t & 1) ? -bv[b][t - 1] : bv[b][t + 1];
+#pragma unroll
+        for (int a = 0; a < TA; ++a) {
+          accR[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a][t], bv[b][t], accR[a][b], 0, 0, 0);
+          accI[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a][t], bi, accI[a][b], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // the four waves' products summed in LDS in wave order, then stored as this block's partial
+  // [a][b][re, im][16 rows][16 columns]
+  constexpr int NV = TA * TB * 2 * 256;
+  __shared__ double sh[NV];
+  for (int w = 0; w < GM_BS / 64; ++w) {
+    if (wv == w) {
+#pragma unroll
+      for (int a = 0; a < TA; ++a)
+#pragma unroll
+        for (int b = 0; b < TB; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int o = (a * TB + b) * 512 + (q + 4 * v) * 16 + r;
+            if (w == 0) {
+              sh[o] = accR[a][b][v];
+              sh[o + 256] = accI[a][b][v];
+            } else {
+              sh[o] += accR[a][b][v];
+              sh[o + 256] += accI[a][b][v];
+            }
+          }
+    }
+    __syncthreads();
+  }
+  double* out = work + (long long)blockIdx.x * NV;
+  for (int v = threadIdx.x; v < NV; v += GM_BS) out[v] = sh[v];
+}
+
+// C[i + j na] = sum over the blocks' partials, in block order: one thread per output value
+template <int TA, int TB>
+__global__ __launch_bounds__(256) void k_gram_mfma_final(const double* __restrict__ work,
+                                                         int nblocks, int na, int nb,
+                                                         double2* __restrict__ C) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= na * nb) return;
+  const int i = t % na, j = t / na;
+  const int a = i >> 4, b = j >> 4;
+  const int o = (a * TB + b) * 512 + (i & 15) * 16 + (j & 15);
+  constexpr int NV = TA * TB * 2 * 256;
+  double re = 0.0, im = 0.0;
+  for (int k = 0; k < nblocks; ++k) {
+    re += work[(long long)k * NV + o];
+    im += work[(long long)k * NV + o + 256];
+  }
+  C[i + (long long)j * na] = make_double2(re, im);
+}
+
+template <int TA, int TB>
+void gram_mfma_impl(hipStream_t s, const double2* A, long long lda, int na, const double2* B,
+                    long long ldb, int nb, long long n, long long V, int g5, double2* C,
+                    double* work, size_t work_elems) {
+  const long long n2 = 2 * n;
+  const long long nchunks = (n2 + GM_CHUNK - 1) / GM_CHUNK;
+  const int nblocks = int(std::min<long long>(GM_MAX_BLOCKS, (nchunks + 3) / 4));
+  constexpr int NV = TA * TB * 2 * 256;
+  DBQ_CHECK(size_t(nblocks) * NV <= work_elems, "gram: workspace too small");
+  DBQ_CHECK(na >= 1 && na <= 16 * TA && nb >= 1 && nb <= 16 * TB, "gram: tile count");
+  hipLaunchKernelGGL((k_gram_mfma<TA, TB>), dim3(nblocks), dim3(GM_BS), 0, s, (const double*)A,
+                     2 * lda, na, (const double*)B, 2 * ldb, nb, n2, 12 * V, g5, work);
+  DBQ_HIP(hipGetLastError());
+  hipLaunchKernelGGL((k_gram_mfma_final<TA, TB>), dim3((na * nb + 255) / 256), dim3(256), 0, s,
+                     work, nblocks, na, nb, C);
   DBQ_HIP(hipGetLastError());
 }
 
@@ -284,30 +440,59 @@ void zero_f64(hipStream_t s, double2* x, long long n) {
 
 size_t gram_work_elems(long long n, int na, int nb) {
   const long long nchunks = (n + G_CHUNK - 1) / G_CHUNK;
-  // the larger of the two tilings
+  // the largest of the tilings
   const long long t1 = nchunks * ((na + 7) / 8) * ((nb + 3) / 4) * 8 * 4 * 2;
   const long long t2 = nchunks * ((na + 15) / 16) * 16 * 2;
-  return size_t(t1 > t2 ? t1 : t2);
+  const long long t3 = (long long)GM_MAX_BLOCKS * 3 * 3 * 2 * 256;
+  return size_t(std::max(t1, std::max(t2, t3)));
+}
+
+// DBQ_GRAM_MFMA=0 keeps the FMA kernel for every shape (for comparison)
+static bool gram_mfma_enabled() {
+  const char* e = std::getenv("DBQ_GRAM_MFMA");
+  return !(e && std::atoi(e) == 0);
 }
 
 void gram_f64(hipStream_t s, const double2* A, long long lda, int na, const double2* B,
               long long ldb, int nb, long long n, long long V, int g5, double2* C, double* work,
               size_t work_elems) {
   if (na <= 0 || nb <= 0) return;
-  if (nb == 1)
+  if (nb == 1) {
     gram_impl<16, 1>(s, A, lda, na, B, ldb, nb, n, V, g5, C, work, work_elems);
-  else
-    gram_impl<8, 4>(s, A, lda, na, B, ldb, nb, n, V, g5, C, work, work_elems);
+    return;
+  }
+  const int ta = (na + 15) / 16, tb = (nb + 15) / 16;
+  if (ta <= 3 && tb <= 3 && gram_mfma_enabled()) {
+    // (16 ta) x (16 tb) accumulator tiles per wave, na and nb up to 48
+    switch (ta * 4 + tb) {
+      case 5: gram_mfma_impl<1, 1>(s, A, lda, na, B, ldb, nb, n, V, g5, C, work, work_elems); return;
+      case 6: gram_mfma_impl<1, 2>(s, A, lda, na, B, ldb, nb, n, V, g5, C, work, work_elems); return;
+      case 7: gram_mfma_impl<1, 3>(s, A, lda, na, B, ldb, nb, n, V, g5, C, work, work_elems); return;
+      case 9: gram_mfma_impl<2, 1>(s, A, lda, na, B, ldb, nb, n, V, g5, C, work, work_elems); return;
+      case 10: gram_mfma_impl<2, 2>(s, A, lda, na, B, ldb, nb, n, V, g5, C, work, work_elems); return;
+      case 11: gram_mfma_impl<2, 3>(s, A, lda, na, B, ldb, nb, n, V, g5, C, work, work_elems); return;
+      case 13: gram_mfma_impl<3, 1>(s, A, lda, na, B, ldb, nb, n, V, g5, C, work, work_elems); return;
+      case 14: gram_mfma_impl<3, 2>(s, A, lda, na, B, ldb, nb, n, V, g5, C, work, work_elems); return;
+      default: gram_mfma_impl<3, 3>(s, A, lda, na, B, ldb, nb, n, V, g5, C, work, work_elems); return;
+    }
+  }
+  gram_impl<8, 4>(s, A, lda, na, B, ldb, nb, n, V, g5, C, work, work_elems);
 }
 
 void combine_f64(hipStream_t s, const double2* A, long long lda, int na, const double2* M, int ldm,
                  double2* Y, long long ldy, int nb, long long n, long long V, int g5, int beta) {
   if (nb <= 0) return;
   if (na <= 0 && beta != 0) return;
-  constexpr int TB = 8;
-  dim3 grid(nb256(n), (nb + TB - 1) / TB);
-  hipLaunchKernelGGL((k_combine<TB>), grid, dim3(256), 0, s, A, lda, na, M, ldm, Y, ldy, nb, n, V,
-                     g5, beta);
+  // up to 16 columns of Y per pass over A (one pass for the 12-source projection)
+  if (nb <= 8) {
+    dim3 grid(nb256(n), 1);
+    hipLaunchKernelGGL((k_combine<8>), grid, dim3(256), 0, s, A, lda, na, M, ldm, Y, ldy, nb, n, V,
+                       g5, beta);
+  } else {
+    dim3 grid(nb256(n), (nb + 15) / 16);
+    hipLaunchKernelGGL((k_combine<16>), grid, dim3(256), 0, s, A, lda, na, M, ldm, Y, ldy, nb, n,
+                       V, g5, beta);
+  }
   DBQ_HIP(hipGetLastError());
 }
 

@@ -56,6 +56,7 @@ int dbq_destroy(dbq_ctx* c) {
   for (auto& b : c->pool) (void)hipFree(b.p);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->acct) (void)hipFree(c->acct);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (auto& t : c->timers) {
     for (auto& pr : t.ev) {
       (void)hipEventDestroy(pr.first);
@@ -114,6 +115,29 @@ int dbq_geometry_host(const int32_t L[4], int32_t* lex_of_eo, int32_t* nbr) {
     nbr[7 * g.V + s] = dbq::eo_neighbour<3, -1>(g, c);
   }
   return DBQ_OK;
+}
+
+int dbq_tile_schedule_host(const int32_t L[4], int32_t nchunks, int32_t order, int32_t* tile,
+                           int32_t* chunk) {
+  if (!L || !tile || !chunk || nchunks < 1 || order < 0 || order > 2) return DBQ_EINVAL;
+  for (int i = 0; i < 4; ++i)
+    if (L[i] < 2 || L[i] % 2) return DBQ_EINVAL;
+  const dbq::Geom g = dbq::make_geom(L);
+  const int ntiles = g.NT[0] * g.NT[1] * g.NT[2] * g.NT[3];
+  for (int loc = 0; loc < ntiles * nchunks; ++loc) {
+    int tc[4];
+    dbq::tile_of_block(g, loc, nchunks, order, tc, tile[loc], chunk[loc]);
+  }
+  return DBQ_OK;
+}
+
+int dbq_stream_probe(dbq_ctx* c, const void* src, void* dst, int64_t bytes, int32_t kind,
+                     int32_t reps, double* ms) {
+  return guarded(c, [&]() {
+    DBQ_CHECK(ms, "null argument");
+    *ms = dbq::stream_probe(c, src, dst, bytes, kind, reps);
+    return DBQ_OK;
+  });
 }
 
 int wilson_apply(dbq_ctx* c, const dbq_operator* op, const void* in, void* out, int32_t nrhs,

@@ -200,6 +200,65 @@ __host__ __device__ __forceinline__ int eo_neighbour(const Geom& g, const int c[
   return eo_of_coords(g, d);
 }
 
+// Order in which the blocks of a tile launch visit (tile, rhs chunk) pairs; memory holds the
+// tiles lexicographically in every case, and a block's partial sums go to its tile's slot, so
+// the order changes no result.  Blocks reach the XCDs in contiguous ranges of the logical index
+// (xcd_block), and one XCD's L2 serves a staged face to the block of the neighbouring tile only
+// if that block runs on the same XCD while the face is still cached.
+//   0: tiles lexicographic, the rhs chunks of one tile adjacent.  The t-neighbour of a tile is a
+//      whole t-slice of tiles away, far more than the blocks resident on one XCD.
+//   1: the tile grid is cut in halves along x, y and z into eight regions (one per XCD when the
+//      tile counts are even); inside a region tiles run lexicographically, so the t-neighbour is
+//      one region slice away, and the chunks of a tile are adjacent.
+//   2: the regions of 1, and inside a region every tile for one rhs chunk before the next chunk
+//      (neighbouring tiles then stage the same rhs at the same time).
+__host__ __device__ __forceinline__ void tile_of_block(const Geom& g, int loc, int nch, int order,
+                                              int (&tc)[4], int& tile, int& chunk) {
+  if (order == 0) {
+    tile = loc / nch;
+    chunk = loc - tile * nch;
+    const uint32_t q1 = g.dNT0.div(uint32_t(tile));
+    const uint32_t q2 = g.dNT1.div(q1);
+    const uint32_t q3 = g.dNT2.div(q2);
+    tc[0] = int(uint32_t(tile) - q1 * uint32_t(g.NT[0]));
+    tc[1] = int(q1 - q2 * uint32_t(g.NT[1]));
+    tc[2] = int(q2 - q3 * uint32_t(g.NT[2]));
+    tc[3] = int(q3);
+    return;
+  }
+  int s[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) s[d] = (g.NT[d] + 1) >> 1;
+  int base = 0, rho = 0, e[3] = {s[0], s[1], s[2]};
+  // region rho = a + 2b + 4c takes the upper half in x if a, in y if b, in z if c; the block
+  // index is uniform, so this search is scalar
+  for (rho = 0; rho < 8; ++rho) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) e[d] = ((rho >> d) & 1) ? g.NT[d] - s[d] : s[d];
+    const int n = e[0] * e[1] * e[2] * g.NT[3] * nch;
+    if (loc < base + n) break;
+    base += n;
+  }
+  const int nt = e[0] * e[1] * e[2] * g.NT[3];
+  const int local = loc - base;
+  int tl;
+  if (order == 1) {
+    tl = local / nch;
+    chunk = local - tl * nch;
+  } else {
+    chunk = local / nt;
+    tl = local - chunk * nt;
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int q = tl / e[d];
+    tc[d] = (((rho >> d) & 1) ? s[d] : 0) + (tl - q * e[d]);
+    tl = q;
+  }
+  tc[3] = tl;
+  tile = tc[0] + g.NT[0] * (tc[1] + g.NT[1] * (tc[2] + g.NT[2] * tc[3]));
+}
+
 // ----------------------------------------------------------------------------- launch helpers
 // Workgroups are dispatched round-robin over the 8 XCDs of an MI355X, each with its own L2.
 // Renumber so that each XCD receives one contiguous range of logical blocks (neighbouring

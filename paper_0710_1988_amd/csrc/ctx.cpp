@@ -94,9 +94,34 @@ void timer_end(dbq_ctx* c, int kind, hipEvent_t ev_begin, double bytes) {
     DBQ_HIP(hipEventCreate(&e));
   }
   DBQ_HIP(hipEventRecord(e, c->stream));
+  if (c->cap_timers) {
+    // inside a capture: the pair is recorded by every replay of the graph
+    c->cap_timers->push_back({kind, ev_begin, e, bytes});
+    return;
+  }
   t.ev.push_back({ev_begin, e});
   t.bytes += bytes;
   t.n += 1;
+}
+
+void graph_timers_add(dbq_ctx* c, const std::vector<dbq_ctx::GraphTimer>& g) {
+  for (const auto& gt : g) {
+    DBQ_HIP(hipEventSynchronize(gt.end));
+    float ms = 0;
+    DBQ_HIP(hipEventElapsedTime(&ms, gt.begin, gt.end));
+    auto& t = c->timers[gt.kind];
+    t.ms += ms;
+    t.n += 1;
+    t.bytes += gt.bytes;
+  }
+}
+
+void graph_timers_release(dbq_ctx* c, std::vector<dbq_ctx::GraphTimer>& g) {
+  for (const auto& gt : g) {
+    c->timers[gt.kind].spare.push_back(gt.begin);
+    c->timers[gt.kind].spare.push_back(gt.end);
+  }
+  g.clear();
 }
 
 void timer_collect(dbq_ctx* c) {

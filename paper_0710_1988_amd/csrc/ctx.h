@@ -40,15 +40,29 @@ struct dbq_ctx {
 
 
   // ---- device accumulators for the algorithmic bytes of gated launches (timing only):
-  //      [kind] bytes so far (kinds 0-2), [8 + 8 * kind + lattice] id of the last Dslash launch
-  //      that counted the lattice's links.  acct_seen = the values already added to the timers.
+  //      [kind] bytes so far (kinds 0-2), [8 + 8 * kind + lattice] set while a Dslash launch has
+  //      counted the lattice's links.  acct_seen = the values already added to the timers.
   unsigned long long* acct = nullptr;
-  unsigned long long acct_seq = 0;
   unsigned long long acct_seen[3] = {0, 0, 0};
 
-  // ---- Dslash launch shape chosen by timing, keyed by (fp32, V, nrhs): (rhs per thread,
-  //      rhs groups per site sweep)
-  std::map<std::tuple<int, int, int>, std::pair<int, int>> ds_tune;
+  // ---- graph capture of the solver's inner iteration blocks: a private stream to capture on
+  //      (the caller's stream may be the null stream, which cannot be captured) and, while a
+  //      capture is open, the timed launch pairs recorded into the graph instead of the timers
+  hipStream_t cap_stream = nullptr;
+  struct GraphTimer {
+    int kind;
+    hipEvent_t begin, end;
+    double bytes;  // host-counted algorithmic bytes (0 when the device counts them)
+  };
+  std::vector<GraphTimer>* cap_timers = nullptr;
+  // odd-site scratch of the reduced operator's first half step, owned by a solve that captures
+  // its iterations (a graph replays the pointers it was captured with); null: taken per launch
+  void* schur_tmp = nullptr;
+  size_t schur_tmp_bytes = 0;
+
+  // ---- Dslash launch shape chosen by timing, keyed by (kind, V, nrhs): rhs per thread (0: LDS
+  //      tile kernel), rhs groups per site sweep (rhs per block for tiles), tile order
+  std::map<std::tuple<int, int, int>, std::tuple<int, int, int>> ds_tune;
 };
 
 namespace dbq {
@@ -79,5 +93,9 @@ struct WsScope {
 void timer_begin(dbq_ctx* c, int kind, hipEvent_t* ev_out);
 void timer_end(dbq_ctx* c, int kind, hipEvent_t ev_begin, double bytes);
 void timer_collect(dbq_ctx* c);
+// after a replay of a graph has completed: add the durations of the launches timed inside it
+void graph_timers_add(dbq_ctx* c, const std::vector<dbq_ctx::GraphTimer>& g);
+// return a graph's timing events to the spare lists
+void graph_timers_release(dbq_ctx* c, std::vector<dbq_ctx::GraphTimer>& g);
 
 }  // namespace dbq

@@ -291,11 +291,12 @@ __device__ __forceinline__ bool finite_d(double v) { return isfinite(v); }
 
 // Byte accounting of a gated launch (timing only), done by the blocks of the first site block or
 // tile of a lattice: each rhs they process adds its spinor traffic, the first one of the lattice
-// in this launch (launch-id tag) also the links.
+// in this launch (its tag still clear) also the links.  The launch's finalize clears the tags
+// again, so a graph that replays the launch counts its links on every replay.
 __device__ __forceinline__ void account(const DsBatch& B, int l) {
   unsigned long long by = (unsigned long long)B.lat[l].g.V *
                           (unsigned long long)(B.acct.spinor_passes * B.acct.spinor_bytes);
-  if (atomicMax(B.acct.tags + l, B.acct.id) < B.acct.id)
+  if (atomicExch(B.acct.tags + l, 1ull) == 0ull)
     by += (unsigned long long)B.lat[l].g.V * (unsigned long long)B.acct.link_bytes;
   atomicAdd(B.acct.bytes, by);
 }
@@ -304,6 +305,8 @@ __device__ __forceinline__ void account(const DsBatch& B, int l) {
 // by one wavefront over its site blocks in a fixed order.
 template <int EPI>
 __device__ void finalize(const DsBatch& B, RhsScal* sc, const double* partials) {
+  // the accounted Dslash launch before this one has finished: clear its link tags
+  if (B.acct.tags && blockIdx.x == 0 && threadIdx.x < B.nlat) B.acct.tags[threadIdx.x] = 0ull;
   const int lane = threadIdx.x & 63;
   constexpr int NW = DS_BS / 64;
   const int w = blockIdx.x * NW + (threadIdx.x >> 6);
@@ -924,23 +927,13 @@ __global__ __launch_bounds__(DS_BS) void k_dslash_tile(DsBatch B, RhsScal* __res
   const Geom& g = L.g;
   const int G = tile_chunk(B.rgroup, L.nrhs);
   const int nch = (L.nrhs + G - 1) / G;
-  const int loc = lb - L.blk_begin;
-  const int tile = loc / nch;  // chunks of one tile are adjacent blocks (they share the links)
-  const int r0 = (loc - tile * nch) * G;
+  int tc[4], tile, chunk;
+  tile_of_block(g, lb - L.blk_begin, nch, B.torder, tc, tile, chunk);
+  const int r0 = chunk * G;
   const int Gc = min(G, L.nrhs - r0);
   const int V = g.V;
   const TileGeo tg = tile_geo(g);
   const int nslots = tg.fbase[7] + (tg.vt >> g.lT[3]);
-  int tc[4];
-  {
-    const uint32_t q1 = g.dNT0.div(uint32_t(tile));
-    const uint32_t q2 = g.dNT1.div(q1);
-    const uint32_t q3 = g.dNT2.div(q2);
-    tc[0] = int(uint32_t(tile) - q1 * uint32_t(g.NT[0]));
-    tc[1] = int(q1 - q2 * uint32_t(g.NT[1]));
-    tc[2] = int(q2 - q3 * uint32_t(g.NT[2]));
-    tc[3] = int(q3);
-  }
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   // LDS-direct copies: wave wv fills the 64-slot chunks wv, wv + 4, wv + 8 of every component
   const int nck = (nslots + 63) >> 6;
@@ -1151,23 +1144,13 @@ __global__ __launch_bounds__(TH_BS) void k_dslash_tile_half(DsBatch B, RhsScal* 
   const Geom& g = L.g;
   const int G = tile_chunk(B.rgroup, L.nrhs);
   const int nch = (L.nrhs + G - 1) / G;
-  const int loc = lb - L.blk_begin;
-  const int tile = loc / nch;
-  const int r0 = (loc - tile * nch) * G;
+  int tc[4], tile, chunk;
+  tile_of_block(g, lb - L.blk_begin, nch, B.torder, tc, tile, chunk);
+  const int r0 = chunk * G;
   const int Gc = min(G, L.nrhs - r0);
   const int Vh = g.V >> 1;
   const TileGeo tg = tile_geo_half(g);
   const int nslots = tg.fbase[7] + ((tg.vt >> g.lT[3]) >> 1);
-  int tc[4];
-  {
-    const uint32_t q1 = g.dNT0.div(uint32_t(tile));
-    const uint32_t q2 = g.dNT1.div(q1);
-    const uint32_t q3 = g.dNT2.div(q2);
-    tc[0] = int(uint32_t(tile) - q1 * uint32_t(g.NT[0]));
-    tc[1] = int(q1 - q2 * uint32_t(g.NT[1]));
-    tc[2] = int(q2 - q3 * uint32_t(g.NT[2]));
-    tc[3] = int(q3);
-  }
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   // LDS-direct copies: wave wv fills the 64-slot chunks wv, wv + 2, wv + 4 of every component
   const int nck = (nslots + 63) >> 6;

@@ -73,18 +73,18 @@ struct DsLat {
   const void* cen;  // half-lattice kernels: the output parity's own input, or null
   int nrhs;
   int rhs_base;     // global rhs index of this lattice's first rhs
-  int nsb;          // site blocks per rhs
+  int nsb;          // site blocks (tiles) per rhs
   int blk_begin;    // first logical block of this lattice
   double kappa, mu;
 };
 
-// Optional accounting of the algorithmic bytes of a gated launch, done by its finalize launch
-// (which sees which right-hand sides the Dslash processed): each processed rhs adds its spinor
-// traffic, and the first processed rhs of each lattice adds the lattice's links.
+// Optional accounting of the algorithmic bytes of a gated launch, done inside the Dslash by the
+// blocks of each lattice's first tile or site block: each processed rhs adds its spinor traffic,
+// and the first processed rhs of each lattice adds the lattice's links.
 struct DsAcct {
   unsigned long long* bytes;  // device accumulator, or null for no accounting
-  unsigned long long* tags;   // device, MAXLAT entries: id of the last launch that counted links
-  unsigned long long id;      // this launch's id, larger than every earlier one
+  unsigned long long* tags;   // device, MAXLAT entries: nonzero once this launch counted the
+                              // lattice's links (cleared by the launch's finalize)
   int spinor_passes;          // spinor vectors read or written per processed rhs-site
   int spinor_bytes;           // bytes of one spinor at one site
   int link_bytes;             // bytes of the links of one site
@@ -98,6 +98,7 @@ struct DsBatch {
   int pstride;     // partial-sum slots per rhs
   int nb;          // right-hand sides per thread (1, 2 or 4), set by the launcher
   int rgroup;      // thread rhs-groups sharing a sweep over the site blocks, set by the launcher
+  int torder;      // LDS tile kernels: order in which blocks visit the tiles (see tile_of_block)
   DsAcct acct;     // zero unless the caller accounts bytes of a gated launch
   int decide;      // RESID finalize also decides convergence / replacement (device loop)
   int schur;       // the lattices' operator is the even-odd reduced one (half vectors)

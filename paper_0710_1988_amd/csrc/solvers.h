@@ -20,5 +20,7 @@ int gmres_proj(dbq_ctx* c, const dbq_operator* o, const void* V, int k, const vo
                int nrhs, int m, double tol, int64_t max_mv, dbq_stats* st);
 void force(dbq_ctx* c, const dbq_operator* o, const void* lambda, const void* x, int nrhs,
            int kind, void* F);
+// average milliseconds of one streaming probe launch (probe.hip)
+double stream_probe(dbq_ctx* c, const void* src, void* dst, long long bytes, int kind, int reps);
 
 }  // namespace dbq

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <vector>
 
 #include "ctx.h"
@@ -106,32 +107,49 @@ DsBatch make_batch(const std::vector<DsSpec>& v) {
   return b;
 }
 
-// Launch shape of the Dslash for a batch: (nb, rg) = right-hand sides per thread (1, 2, 4) and
-// how many of those thread groups sweep the site blocks together (1, 2, 4 or all), or, in FP32,
-// nb = 0 for the LDS-staged tile kernel with rg rhs per block (1, 2, 3, 4, 6 or all).  Timed once
-// per (precision, volume, batch size) in this context on a scratch output (the operator input is
-// only read).  DBQ_DS_NB / DBQ_DS_RG force the values.
-std::pair<int, int> choose_shape(dbq_ctx* c, bool f32, const DsBatch& b) {
-  int maxr = 1;
-  for (int i = 0; i < b.nlat; ++i) maxr = std::max(maxr, b.lat[i].nrhs);
+// Launch shape of the Dslash: nb = right-hand sides per thread of the site kernel (1, 2, 4), or in
+// FP32 0 for the LDS-staged tile kernel; rg = for the site kernel how many of those thread groups
+// sweep the site blocks together (1, 2, 4 or 0 = all), for the tile kernel the rhs per block
+// (1, 2, 3, 4, 6 or 0 = all); order = the tile kernel's block-to-tile order (tile_of_block).
+struct Shape {
+  int nb = 1, rg = 0, order = 0;
+};
+
+// Forced shape from DBQ_DS_NB / DBQ_DS_RG / DBQ_TILE_ORDER, if any of them is set.
+bool forced_shape(bool f32, bool half, Shape& sh) {
   const char* e_nb = std::getenv("DBQ_DS_NB");
   const char* e_rg = std::getenv("DBQ_DS_RG");
-  if (e_nb || e_rg) {
-    int nb = e_nb ? std::atoi(e_nb) : 1;
-    if (nb != 0 && nb != 1 && nb != 2 && nb != 4) nb = 1;
-    if (nb == 0 && !f32) nb = 1;
-    return {nb, e_rg ? std::max(0, std::atoi(e_rg)) : 0};
-  }
-  std::vector<std::pair<int, int>> cand;
+  const char* e_to = std::getenv("DBQ_TILE_ORDER");
+  if (!e_nb && !e_rg && !e_to) return false;
+  int nb = e_nb ? std::atoi(e_nb) : (f32 ? 0 : 1);
+  if (half ? (nb != 0 && nb != 2) : (nb != 0 && nb != 1 && nb != 2 && nb != 4)) nb = 1;
+  if (nb == 0 && !f32) nb = 1;
+  sh.nb = nb;
+  sh.rg = e_rg ? std::max(0, std::atoi(e_rg)) : 0;
+  sh.order = e_to ? std::min(2, std::max(0, std::atoi(e_to))) : 0;
+  return true;
+}
+
+// The timed candidates are every (nb, rg) above and, for the tile kernel, each tile order.  Timed
+// once per (precision, volume, batch size) in this context on a scratch output (the operator
+// input is only read).
+Shape choose_shape(dbq_ctx* c, bool f32, const DsBatch& b) {
+  int maxr = 1;
+  for (int i = 0; i < b.nlat; ++i) maxr = std::max(maxr, b.lat[i].nrhs);
+  Shape forced;
+  if (forced_shape(f32, false, forced)) return forced;
+  std::vector<Shape> cand;
   for (int nb : {1, 2, 4}) {
     if (nb > maxr || (!f32 && nb == 4)) continue;
     const int ng = (maxr + nb - 1) / nb;
     for (int rg : {1, 2, 4, 0})
-      if (rg < ng) cand.push_back({nb, rg});  // 0 (all) covers rg >= ng
+      if (rg < ng) cand.push_back(Shape{nb, rg, 0});  // 0 (all) covers rg >= ng
   }
   if (f32) {
     for (int g : {1, 2, 3, 4, 6, 0})
-      if (g < maxr) cand.push_back({0, g});
+      if (g < maxr)
+        for (int o : {0, 1, 2})
+          if (o < 2 || (g != 0 && g < maxr)) cand.push_back(Shape{0, g, o});
   }
   if (cand.size() == 1) return cand[0];
   int big = 0;
@@ -139,7 +157,8 @@ std::pair<int, int> choose_shape(dbq_ctx* c, bool f32, const DsBatch& b) {
     if ((long long)b.lat[i].g.V * b.lat[i].nrhs > (long long)b.lat[big].g.V * b.lat[big].nrhs) big = i;
   const auto key = std::make_tuple(f32 ? 1 : 0, b.lat[big].g.V, b.lat[big].nrhs);
   auto it = c->ds_tune.find(key);
-  if (it != c->ds_tune.end()) return it->second;
+  if (it != c->ds_tune.end())
+    return Shape{std::get<0>(it->second), std::get<1>(it->second), std::get<2>(it->second)};
   WsScope ws(c);
   DsBatch t;
   std::memset(&t, 0, sizeof(t));
@@ -155,14 +174,15 @@ std::pair<int, int> choose_shape(dbq_ctx* c, bool f32, const DsBatch& b) {
   hipEvent_t e0, e1;
   DBQ_HIP(hipEventCreate(&e0));
   DBQ_HIP(hipEventCreate(&e1));
-  std::pair<int, int> best = cand[0];
+  Shape best = cand[0];
   float best_ms = 1e30f;
   for (const auto& sh : cand) {
+    t.torder = sh.order;
     for (int rep = 0; rep < 2; ++rep) {  // warm-up, then timed
       DBQ_HIP(hipEventRecord(e0, c->stream));
       for (int k = 0; k < 3; ++k) {
-        if (f32) launch_dslash_f32(c->stream, t, 0, EPI_NONE, nullptr, nullptr, sh.first, sh.second);
-        else launch_dslash_f64(c->stream, t, 0, EPI_NONE, nullptr, nullptr, sh.first, sh.second);
+        if (f32) launch_dslash_f32(c->stream, t, 0, EPI_NONE, nullptr, nullptr, sh.nb, sh.rg);
+        else launch_dslash_f64(c->stream, t, 0, EPI_NONE, nullptr, nullptr, sh.nb, sh.rg);
       }
       DBQ_HIP(hipEventRecord(e1, c->stream));
     }
@@ -170,8 +190,9 @@ std::pair<int, int> choose_shape(dbq_ctx* c, bool f32, const DsBatch& b) {
     float ms = 0;
     DBQ_HIP(hipEventElapsedTime(&ms, e0, e1));
     if (std::getenv("DBQ_DEBUG"))
-      std::fprintf(stderr, "[dbq] tune %s V=%d nrhs=%d nb=%d rg=%d: %.1f us\n",
-                   f32 ? "fp32" : "fp64", t.lat[0].g.V, maxr, sh.first, sh.second, ms * 1e3f / 3);
+      std::fprintf(stderr, "[dbq] tune %s V=%d nrhs=%d nb=%d rg=%d order=%d: %.1f us\n",
+                   f32 ? "fp32" : "fp64", t.lat[0].g.V, maxr, sh.nb, sh.rg, sh.order,
+                   ms * 1e3f / 3);
     if (ms < best_ms) {
       best_ms = ms;
       best = sh;
@@ -179,35 +200,31 @@ std::pair<int, int> choose_shape(dbq_ctx* c, bool f32, const DsBatch& b) {
   }
   DBQ_HIP(hipEventDestroy(e0));
   DBQ_HIP(hipEventDestroy(e1));
-  c->ds_tune[key] = best;
+  c->ds_tune[key] = std::make_tuple(best.nb, best.rg, best.order);
   return best;
 }
 
-// Launch shape (nb, rg) of the half-lattice kernels for a batch of the reduced operator: nb = 1
-// or 2 rhs per thread with rg as for the site kernel, or in FP32 nb = 0 for the LDS-staged tile
-// kernel with rg rhs per block; timed once per (precision, volume, batch size) on step 1 into a
-// scratch output.  DBQ_DS_NB / DBQ_DS_RG force the values.
-std::pair<int, int> choose_shape_half(dbq_ctx* c, bool f32, const DsBatch& b) {
+// Launch shape of the half-lattice kernels for a batch of the reduced operator: nb = 1 or 2 rhs
+// per thread with rg as for the site kernel, or in FP32 nb = 0 for the LDS-staged tile kernel
+// with rg rhs per block and a tile order; timed once per (precision, volume, batch size) on step
+// 1 into a scratch output.  DBQ_DS_NB / DBQ_DS_RG / DBQ_TILE_ORDER force the values.
+Shape choose_shape_half(dbq_ctx* c, bool f32, const DsBatch& b) {
   int maxr = 1;
   for (int i = 0; i < b.nlat; ++i) maxr = std::max(maxr, b.lat[i].nrhs);
-  const char* e_nb = std::getenv("DBQ_DS_NB");
-  const char* e_rg = std::getenv("DBQ_DS_RG");
-  if (e_nb || e_rg) {
-    int nb = e_nb ? std::atoi(e_nb) : 1;
-    if (nb != 0 && nb != 2) nb = 1;
-    if (nb == 0 && !f32) nb = 1;
-    return {nb, e_rg ? std::max(0, std::atoi(e_rg)) : 0};
-  }
-  std::vector<std::pair<int, int>> cand;
+  Shape forced;
+  if (forced_shape(f32, true, forced)) return forced;
+  std::vector<Shape> cand;
   for (int nb : {1, 2}) {
     if (nb > maxr) continue;
     const int ng = (maxr + nb - 1) / nb;
     for (int rg : {1, 2, 4, 0})
-      if (rg < ng) cand.push_back({nb, rg});
+      if (rg < ng) cand.push_back(Shape{nb, rg, 0});
   }
   if (f32) {
     for (int g : {1, 2, 3, 4, 6, 0})
-      if (g < maxr) cand.push_back({0, g});
+      if (g < maxr)
+        for (int o : {0, 1, 2})
+          if (o < 2 || (g != 0 && g < maxr)) cand.push_back(Shape{0, g, o});
   }
   if (cand.size() == 1) return cand[0];
   int big = 0;
@@ -215,7 +232,8 @@ std::pair<int, int> choose_shape_half(dbq_ctx* c, bool f32, const DsBatch& b) {
     if ((long long)b.lat[i].g.V * b.lat[i].nrhs > (long long)b.lat[big].g.V * b.lat[big].nrhs) big = i;
   const auto key = std::make_tuple(f32 ? 3 : 2, b.lat[big].g.V, b.lat[big].nrhs);
   auto it = c->ds_tune.find(key);
-  if (it != c->ds_tune.end()) return it->second;
+  if (it != c->ds_tune.end())
+    return Shape{std::get<0>(it->second), std::get<1>(it->second), std::get<2>(it->second)};
   WsScope ws(c);
   DsBatch t;
   std::memset(&t, 0, sizeof(t));
@@ -234,14 +252,15 @@ std::pair<int, int> choose_shape_half(dbq_ctx* c, bool f32, const DsBatch& b) {
   hipEvent_t e0, e1;
   DBQ_HIP(hipEventCreate(&e0));
   DBQ_HIP(hipEventCreate(&e1));
-  std::pair<int, int> best = cand[0];
+  Shape best = cand[0];
   float best_ms = 1e30f;
   for (const auto& sh : cand) {
+    t.torder = sh.order;
     for (int rep = 0; rep < 2; ++rep) {  // warm-up, then timed
       DBQ_HIP(hipEventRecord(e0, c->stream));
       for (int k = 0; k < 3; ++k) {
-        if (f32) launch_dslash_half_f32(c->stream, t, 1, 0, EPI_NONE, nullptr, nullptr, sh.first, sh.second, 0);
-        else launch_dslash_half_f64(c->stream, t, 1, 0, EPI_NONE, nullptr, nullptr, sh.first, sh.second, 0);
+        if (f32) launch_dslash_half_f32(c->stream, t, 1, 0, EPI_NONE, nullptr, nullptr, sh.nb, sh.rg, 0);
+        else launch_dslash_half_f64(c->stream, t, 1, 0, EPI_NONE, nullptr, nullptr, sh.nb, sh.rg, 0);
       }
       DBQ_HIP(hipEventRecord(e1, c->stream));
     }
@@ -249,8 +268,9 @@ std::pair<int, int> choose_shape_half(dbq_ctx* c, bool f32, const DsBatch& b) {
     float ms = 0;
     DBQ_HIP(hipEventElapsedTime(&ms, e0, e1));
     if (std::getenv("DBQ_DEBUG"))
-      std::fprintf(stderr, "[dbq] tune half %s V=%d nrhs=%d nb=%d rg=%d: %.1f us\n",
-                   f32 ? "fp32" : "fp64", t.lat[0].g.V, maxr, sh.first, sh.second, ms * 1e3f / 3);
+      std::fprintf(stderr, "[dbq] tune half %s V=%d nrhs=%d nb=%d rg=%d order=%d: %.1f us\n",
+                   f32 ? "fp32" : "fp64", t.lat[0].g.V, maxr, sh.nb, sh.rg, sh.order,
+                   ms * 1e3f / 3);
     if (ms < best_ms) {
       best_ms = ms;
       best = sh;
@@ -258,7 +278,7 @@ std::pair<int, int> choose_shape_half(dbq_ctx* c, bool f32, const DsBatch& b) {
   }
   DBQ_HIP(hipEventDestroy(e0));
   DBQ_HIP(hipEventDestroy(e1));
-  c->ds_tune[key] = best;
+  c->ds_tune[key] = std::make_tuple(best.nb, best.rg, best.order);
   return best;
 }
 
@@ -271,14 +291,22 @@ void run_schur(dbq_ctx* c, bool f32, const DsBatch& b0, int dagger, int epi, Rhs
   const int gate = sc ? (epi == EPI_RESID ? 2 : 1) : 0;
   DsBatch b1 = b0;
   b1.acct = DsAcct{};
+  size_t need = 0;
+  for (int i = 0; i < b1.nlat; ++i)
+    need += size_t(b1.lat[i].nrhs) * (b1.lat[i].g.V / 2) *
+            (f32 ? 6 * sizeof(float4) : 12 * sizeof(double2));
+  char* tmp = (c->schur_tmp && c->schur_tmp_bytes >= need) ? (char*)c->schur_tmp
+                                                            : (char*)ws.take(need);
   for (int i = 0; i < b1.nlat; ++i) {
     DsLat& L = b1.lat[i];
-    L.out = ws.take(size_t(L.nrhs) * (L.g.V / 2) * (f32 ? 6 * sizeof(float4) : 12 * sizeof(double2)));
+    L.out = tmp;
+    tmp += size_t(L.nrhs) * (L.g.V / 2) * (f32 ? 6 * sizeof(float4) : 12 * sizeof(double2));
     L.cen = nullptr;
     L.aux = nullptr;
     L.kappa = 1.0;
   }
-  const auto shape = choose_shape_half(c, f32, b1);
+  const Shape shape = choose_shape_half(c, f32, b1);
+  b1.torder = shape.order;
   DsBatch b2 = b0;
   b2.acct = DsAcct{};
   for (int i = 0; i < b2.nlat; ++i) {
@@ -287,12 +315,13 @@ void run_schur(dbq_ctx* c, bool f32, const DsBatch& b0, int dagger, int epi, Rhs
     L.cen = b0.lat[i].in;
     L.kappa = b0.lat[i].kappa * b0.lat[i].kappa;
   }
+  b2.torder = shape.order;
   if (f32) {
-    launch_dslash_half_f32(c->stream, b1, 1, dagger, EPI_NONE, sc, partials, shape.first, shape.second, gate);
-    launch_dslash_half_f32(c->stream, b2, 2, dagger, epi, sc, partials, shape.first, shape.second, gate);
+    launch_dslash_half_f32(c->stream, b1, 1, dagger, EPI_NONE, sc, partials, shape.nb, shape.rg, gate);
+    launch_dslash_half_f32(c->stream, b2, 2, dagger, epi, sc, partials, shape.nb, shape.rg, gate);
   } else {
-    launch_dslash_half_f64(c->stream, b1, 1, dagger, EPI_NONE, sc, partials, shape.first, shape.second, gate);
-    launch_dslash_half_f64(c->stream, b2, 2, dagger, epi, sc, partials, shape.first, shape.second, gate);
+    launch_dslash_half_f64(c->stream, b1, 1, dagger, EPI_NONE, sc, partials, shape.nb, shape.rg, gate);
+    launch_dslash_half_f64(c->stream, b2, 2, dagger, epi, sc, partials, shape.nb, shape.rg, gate);
   }
   launch_ds_finalize(c->stream, b2, epi, sc, partials);
 }
@@ -303,10 +332,11 @@ void run_dslash(dbq_ctx* c, bool f32, const DsBatch& b0, int dagger, int epi, Rh
     run_schur(c, f32, b0, dagger, epi, sc, partials);
     return;
   }
-  const auto shape = choose_shape(c, f32, b0);
+  const Shape shape = choose_shape(c, f32, b0);
   const int kind = f32 ? 1 : 0;
   DsBatch b = b0;
   b.acct = DsAcct{};
+  b.torder = shape.order;
   hipEvent_t e0;
   timer_begin(c, kind, &e0);  // null unless this launch is a timed sample
   // a gated launch (scalars given) skips inactive rhs: the bytes of a timed one are counted on
@@ -315,17 +345,16 @@ void run_dslash(dbq_ctx* c, bool f32, const DsBatch& b0, int dagger, int epi, Rh
   if (dev_acct) {
     b.acct.bytes = c->acct + kind;
     b.acct.tags = c->acct + 8 + 8 * kind;
-    b.acct.id = ++c->acct_seq;
     b.acct.spinor_passes = ds_spinor_passes(epi);
     b.acct.spinor_bytes = f32 ? 24 * 4 : 12 * 16;
     b.acct.link_bytes = f32 ? 4 * 12 * 4 : 4 * 9 * 16;
   }
   // residual launches select few rhs: with all rhs groups of a site block adjacent, the selected
   // ones still cover every XCD (chunks of rhs groups would put one rhs on one or two XCDs)
-  const int rg = (epi == EPI_RESID && shape.first > 0) ? 0 : shape.second;
+  const int rg = (epi == EPI_RESID && shape.nb > 0) ? 0 : shape.rg;
   const double bytes =
-      f32 ? launch_dslash_f32(c->stream, b, dagger, epi, sc, partials, shape.first, rg)
-          : launch_dslash_f64(c->stream, b, dagger, epi, sc, partials, shape.first, rg);
+      f32 ? launch_dslash_f32(c->stream, b, dagger, epi, sc, partials, shape.nb, rg)
+          : launch_dslash_f64(c->stream, b, dagger, epi, sc, partials, shape.nb, rg);
   timer_end(c, kind, e0, dev_acct ? 0.0 : bytes);
   launch_ds_finalize(c->stream, b, epi, sc, partials);
 }
@@ -500,6 +529,103 @@ void apply_operator(dbq_ctx* c, const dbq_operator* o, const void* in, void* out
 }
 
 // ============================================================================ D-BiCGStab(k)
+namespace {
+
+// HIP graphs of the mixed-precision iteration blocks of one solve, keyed by block length.
+// DBQ_GRAPH=0 runs every block eagerly, and so does a solve with kernel timing on.  A capture that fails (an operation the runtime cannot
+// capture) ends the capture and the solve continues eagerly.
+struct LoopGraphs {
+  struct G {
+    int n = 0;
+    hipGraphExec_t exec = nullptr;
+    std::vector<dbq_ctx::GraphTimer> timers;
+  };
+  dbq_ctx* c;
+  std::vector<std::unique_ptr<G>> gs;
+  bool enabled, warm = false;
+  LoopGraphs(dbq_ctx* ctx, size_t schur_bytes, WsScope& ws) : c(ctx) {
+    const char* e = std::getenv("DBQ_GRAPH");
+    // timed launches run eagerly: an event recorded by a graph node cannot be read back as a
+    // timestamp pair on this runtime
+    enabled = !(e && std::atoi(e) == 0) && !c->timing;
+    if (enabled && schur_bytes) {
+      c->schur_tmp = ws.take(schur_bytes);
+      c->schur_tmp_bytes = schur_bytes;
+    }
+  }
+  LoopGraphs(const LoopGraphs&) = delete;
+  LoopGraphs& operator=(const LoopGraphs&) = delete;
+  ~LoopGraphs() {
+    for (auto& g : gs) {
+      if (g->exec) (void)hipGraphExecDestroy(g->exec);
+      graph_timers_release(c, g->timers);
+    }
+    c->schur_tmp = nullptr;
+    c->schur_tmp_bytes = 0;
+  }
+  // run a block of n iterations; returns the graph replayed, or null when it ran eagerly
+  template <typename F>
+  const G* run(int n, F&& block) {
+    if (!enabled || !warm) {
+      block(n);
+      warm = true;
+      return nullptr;
+    }
+    G* g = nullptr;
+    for (auto& q : gs)
+      if (q->n == n) g = q.get();
+    if (!g) {
+      g = capture(n, block);
+      if (!g) {
+        enabled = false;
+        block(n);
+        return nullptr;
+      }
+    }
+    DBQ_HIP(hipGraphLaunch(g->exec, c->stream));
+    return g;
+  }
+  template <typename F>
+  G* capture(int n, F&& block) {
+    if (!c->cap_stream) DBQ_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    std::unique_ptr<G> g(new G());
+    g->n = n;
+    const hipStream_t orig = c->stream;
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    c->stream = c->cap_stream;
+    c->cap_timers = &g->timers;
+    bool ok = true;
+    try {
+      block(n);
+    } catch (const Error&) {
+      ok = false;
+    }
+    c->stream = orig;
+    c->cap_timers = nullptr;
+    if (hipStreamEndCapture(c->cap_stream, &graph) != hipSuccess || !ok || !graph) {
+      (void)hipGetLastError();
+      if (graph) (void)hipGraphDestroy(graph);
+      graph_timers_release(c, g->timers);
+      return nullptr;
+    }
+    const hipError_t e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      graph_timers_release(c, g->timers);
+      return nullptr;
+    }
+    gs.push_back(std::move(g));
+    return gs.back().get();
+  }
+};
+
+}  // namespace
+
 int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* Vin,
               const int32_t* kk, const void* const* B, void* const* X, const int32_t* nrhs,
               double tol, int64_t max_mv, int prec, int dagger, dbq_stats* st) {
@@ -516,7 +642,8 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
     DBQ_CHECK(kk[i] == 0 || (Vin && Vin[i]), "null deflation vectors");
     DBQ_CHECK(B[i] && X[i], "null right-hand side or solution");
   }
-  hipStream_t s = c->stream;
+  // s follows c->stream, which a graph capture points at the capture stream for its duration
+  hipStream_t& s = c->stream;
   const bool mixed = prec == DBQ_MIXED;
   WsScope ws(c);
   std::vector<Op> op(nops);
@@ -782,9 +909,13 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
                      j, hs[j].iters, hs[j].flags, hs[j].active, hs[j].sel, hs[j].rr, hs[j].bb,
                      hs[j].rr_max, hs[j].nrel);
   };
-  // breakdowns: restart with rhat <- r (the selection is pushed with the host scalars)
+  // breakdowns: restart with rhat <- r (the selection is pushed with the host scalars).  Polls
+  // of the mixed loop follow a reliable-update block, after which no rhs waits with sel set;
+  // a selection that is still pending is kept (the restart then restarts that rhs as well and
+  // it carries on iterating) rather than cleared, which would leave it neither live nor done.
   auto restart = [&](const std::vector<int>& Bk) {
-    for (int j = 0; j < NR; ++j) hs[j].sel = 0;
+    if (!mixed)
+      for (int j = 0; j < NR; ++j) hs[j].sel = 0;
     bool any = false;
     for (int j : Bk) {
       if (done[j]) continue;
@@ -824,10 +955,24 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
       run_dslash(c, false, bres_dec, dagger, EPI_RESID, sc, partials);
       bicg_aux_f32(s, AX_REPLACE, vs32, vs64, r64, r32, rhat32, p32, v32, x32, sc, partials);
     };
+    auto block = [&](int n) {
+      for (int it = 1; it <= n; ++it) {
+        iterate();
+        if (it % every == 0) relup_dev();
+      }
+    };
+    // Blocks of iterations between two polls run as HIP graphs: the launches of a block (7 per
+    // iteration, 5 for the reliable-update step) are captured once per solve and block length
+    // and replayed, so the host issues one launch per block.  The first block runs eagerly
+    // (it tunes the launch shapes and settles the workspace the graphs capture).
+    LoopGraphs graphs(c, op[0].schur ? tot64 * sizeof(double2) : 0, ws);
+    const LoopGraphs::G* replayed = nullptr;
     relup_dev();  // rhs whose starting residual already meets the tolerance
     int nchk = every;
     while (true) {
       pull();
+      if (replayed && c->timing) graph_timers_add(c, replayed->timers);
+      replayed = nullptr;
       trace();
       std::vector<int> Bk, Cc;
       bool live = false;
@@ -877,11 +1022,15 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
       }
       if (!live) break;
       nchk = (Bk.empty() && Cc.empty()) ? std::min(nchk * 2, std::max(32, every)) : every;
-      for (int it = 1; it <= nchk; ++it) {
-        iterate();
-        if (it % every == 0) relup_dev();
-      }
+      // every poll comes right after a reliable-update block
+      nchk = ((nchk + every - 1) / every) * every;
+      replayed = graphs.run(nchk, block);
     }
+    for (int j = 0; j < NR; ++j)
+      if (!done[j])
+        throw Error(DBQ_EHIP, "internal error: right-hand side " + std::to_string(j) +
+                                  " left the mixed-precision loop undecided (flags " +
+                                  std::to_string(hs[j].flags) + ")");
   } else {
     int nchk = 1;
     bool first = true;

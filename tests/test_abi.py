@@ -74,3 +74,46 @@ def test_python_binding_rejects_bad_lattices_before_any_call():
         dbq.geometry_host((4, 4, 4, 5))
     with pytest.raises(ValueError):
         dbq.geometry_host((4, 4, 4))
+
+
+@pytest.mark.parametrize("L", [(24, 24, 24, 48), (16, 16, 16, 16), (20, 20, 20, 32), (8, 8, 8, 8),
+                               (4, 4, 4, 4), (6, 4, 2, 10), (12, 12, 12, 12)])
+@pytest.mark.parametrize("nch", [1, 3])
+def test_tile_schedule_is_a_permutation_with_regions(L, nch):
+    """Every LDS-tile launch order visits each (tile, rhs chunk) pair exactly once; order 0 is
+    tile-major; orders 1 and 2 keep each of the eight x/y/z half-regions of the tile grid in one
+    contiguous run of blocks (one run per XCD when the tile counts are even), and order 2 runs
+    the chunks of a region one after the other."""
+    import paper_0710_1988_amd as dbq
+    T = dbq.site_tile(L)
+    NT = [L[i] // T[i] for i in range(4)]
+    nt = int(np.prod(NT))
+    for order in (0, 1, 2):
+        tile, chunk = dbq.tile_schedule_host(L, nch, order)
+        pairs = tile.astype(np.int64) * nch + chunk
+        assert np.array_equal(np.sort(pairs), np.arange(nt * nch)), order
+        if order == 0:
+            b = np.arange(nt * nch)
+            assert np.array_equal(tile, b // nch) and np.array_equal(chunk, b % nch)
+            continue
+        tc = [tile % NT[0], (tile // NT[0]) % NT[1], (tile // (NT[0] * NT[1])) % NT[2]]
+        half = [(NT[d] + 1) // 2 for d in range(3)]
+        region = sum(((tc[d] >= half[d]).astype(int) << d) for d in range(3))
+        # regions appear in increasing order, each as one contiguous run
+        assert np.all(np.diff(region) >= 0), order
+        if all(n % 2 == 0 for n in NT[:3]):
+            runs = np.split(region, 8)
+            assert all(np.all(r == i) for i, r in enumerate(runs))
+        if order == 2:
+            for rho in range(8):
+                c = chunk[region == rho]
+                assert np.all(np.diff(c) >= 0)
+
+
+def test_tile_schedule_rejects_bad_arguments():
+    from paper_0710_1988_amd import _abi
+    lib = _abi.load()
+    L = (ctypes.c_int32 * 4)(4, 4, 4, 4)
+    buf = (ctypes.c_int32 * 16)()
+    assert lib.dbq_tile_schedule_host(L, 1, 3, buf, buf) == _abi.DBQ_EINVAL
+    assert lib.dbq_tile_schedule_host(L, 0, 1, buf, buf) == _abi.DBQ_EINVAL

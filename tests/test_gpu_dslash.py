@@ -51,14 +51,20 @@ def test_apply_fp32_matches_oracle(gpu_lib, L, dagger):
     assert relerr(out, ref) <= 2e-6
 
 
-@pytest.mark.parametrize("L", LATS + [(8, 8, 4, 12)])
+@pytest.mark.parametrize("L", LATS + [(8, 8, 4, 12), (16, 8, 12, 8)])
 @pytest.mark.parametrize("shape", [("0", "1"), ("0", "2"), ("0", "0"), ("1", "1"), ("1", "0"),
-                                   ("2", "1"), ("4", "0")])
+                                   ("2", "1"), ("4", "0"), ("0", "1", "1"), ("0", "0", "1"),
+                                   ("0", "2", "2"), ("0", "1", "2"), ("0", "1", "0", "1")])
 def test_every_fp32_launch_shape_matches_oracle(gpu_lib, monkeypatch, L, shape):
     """Each FP32 launch shape: rhs per thread 1/2/4 with rhs grouping, and the LDS-staged tile
-    kernel (nb 0) with 1, 2 or all rhs per block; 5 rhs leave a ragged last chunk."""
+    kernel (nb 0) with 1, 2 or all rhs per block in each tile order (lexicographic; eight x/y/z
+    regions; regions with rhs chunks outermost); 5 rhs leave a ragged last chunk, and the tile
+    grids include odd and unit tile counts, whose regions are uneven or empty, and tiles smaller
+    than 4^4."""
     monkeypatch.setenv("DBQ_DS_NB", shape[0])
     monkeypatch.setenv("DBQ_DS_RG", shape[1])
+    if len(shape) > 2:
+        monkeypatch.setenv("DBQ_TILE_ORDER", shape[2])
     lat = W.Lattice(L)
     U = synth.gauge_field(L, 0.6, 208)
     psi = synth.gaussian_sources(L, 5, 209)
@@ -128,6 +134,38 @@ def test_full_size_16x16x16x16_batch_of_12_sampled_sites(gpu_lib, dagger):
     for j in range(12):
         ref = W.apply_A_sites(U, psi[j], lat, 0.2074870, sites, 0.0, dagger)
         assert relerr(out[j][sites], ref) <= 2e-6
+
+
+_BIG = {}
+
+
+def _big_batch():
+    """24^3 x 48 field and 12 Z2 sources (host and device), built once for the module."""
+    if not _BIG:
+        L = (24, 24, 24, 48)
+        U = synth.gauge_field(L, 0.6, 105)
+        psi = synth.z2_sources(L, 12, 1105)
+        _BIG.update(L=L, lat=W.Lattice(L), U=U, psi=psi, Ud=dev(U), psid=dev(psi))
+    return _BIG
+
+
+@pytest.mark.parametrize("order", [None, "0", "1", "2"])
+def test_full_size_24x48_batch_of_12_sampled_sites(gpu_lib, monkeypatch, order):
+    """The HBM-sized operator launch: 24^3 x 48 with 12 Z2 sources in one FP32 call, in the tuned
+    launch shape (None) and as the LDS tile kernel with 4 rhs per block in each tile order; 128
+    sampled sites of every source recomputed by the oracle one by one."""
+    if order is not None:
+        monkeypatch.setenv("DBQ_DS_NB", "0")
+        monkeypatch.setenv("DBQ_DS_RG", "4")
+        monkeypatch.setenv("DBQ_TILE_ORDER", order)
+    d = _big_batch()
+    out = gpu_lib.wilson_apply(d["L"], d["Ud"], d["psid"], 0.13, 0.005, False, "mixed")
+    sites = np.random.default_rng(11).choice(d["lat"].V, 128, replace=False)
+    got = host(out[:, sites])
+    del out
+    for j in range(12):
+        ref = W.apply_A_sites(d["U"], d["psi"][j], d["lat"], 0.13, sites, 0.005)
+        assert relerr(got[j], ref) <= 2e-6, j
 
 
 def test_rejects_bad_shapes_before_launch(gpu_lib):

@@ -158,6 +158,61 @@ def test_dbicgstab_mixed_reaches_fp64_residual(gpu_lib):
         assert err <= 1e-6
 
 
+def test_dbicgstab_mixed_past_kappa_c_at_c1(gpu_lib, c1_vectors, capsys):
+    """C1 as configured: kappa = 0.15 lies past kappa_c (about 0.140 for this field), so A has
+    eigenvalues with negative real part.  Mixed-precision D-BiCGStab(6) with the oracle's
+    GMRES-DR(20,6) vectors on the three Z2 sources: every solution meets 1e-8 on the oracle's
+    FP64 residual, and the library's reported residual agrees with it.  Which sources the FP32
+    recursion finished and which the FP64 continuation finished is printed."""
+    L, lat, U = _c1()
+    B = synth.z2_sources(L, 3, 1101)
+    Vt = dev(c1_vectors.T.reshape(-1, lat.V, 4, 3))
+    X, st, status = gpu_lib.dbicgstab_solve(
+        [dict(L=L, links=dev(U), kappa=0.15, B=dev(B), V=Vt)], tol=1e-8, prec="mixed")
+    assert status == 0, st
+    Xg = host(X[0])
+    for j in range(3):
+        rel = _true_rel(U, lat, 0.15, 0.0, Xg[j].reshape(-1), B[j].reshape(-1))
+        with capsys.disabled():
+            print(f"\n  [C1 kappa 0.15 mixed rhs {j}: {st[j]['matvecs']} MVPs, "
+                  f"{st[j]['reliable_updates']} reliable updates, fp64_continued "
+                  f"{st[j]['fp64_continued']}, oracle residual {rel:.2e}]", flush=True)
+        assert st[j]["status"] == 0 and rel <= 1.0001e-8
+        assert abs(st[j]["rel_true_resid"] - rel) <= 1e-3 * rel
+
+
+@pytest.mark.parametrize("schur", [False, True])
+def test_gmresdr_from_nonzero_x0_with_twisted_mass_matches_oracle(gpu_lib, schur):
+    """gmresdr_first_rhs from a nonzero initial guess with mu != 0 (the call the Sec. 4 shift
+    experiment makes after each projection), on the full operator and on the even-odd reduced
+    system: matvecs = 1 + m + (m-k)(cycles-1), the oracle's GMRES-DR from the same x0 takes the
+    same number of cycles (within one), and the full solution meets the tolerance."""
+    from oracle import evenodd as EO
+    L, lat, U = _c1()
+    kappa, mu, m, k = 0.139, 0.02, 20, 6
+    b = synth.z2_sources(L, 1, 1101)
+    # x0: the solution at a heavier twisted mass, slightly perturbed
+    Ah = W.operator(U, lat, kappa, 0.04)
+    xh, _ = S.bicgstab(Ah, b.reshape(-1), tol=1e-10)
+    x0 = (xh + 0.01 * synth.gaussian_sources(L, 1, 1102).reshape(-1)).reshape(1, lat.V, 4, 3)
+    x, V, th, st = gpu_lib.gmresdr_first_rhs(L, dev(U), dev(b), kappa, m, k, mu=mu, tol=1e-10,
+                                             x0=dev(x0), schur=schur)
+    assert st["status"] == 0
+    assert st["matvecs"] == 1 + m + (m - k) * (st["iterations"] - 1)
+    assert _true_rel(U, lat, kappa, mu, host(x).reshape(-1), b.reshape(-1)) <= 1.0001e-10
+    nb = np.linalg.norm(b)
+    if schur:
+        A = EO.schur_operator(U, lat, kappa, mu)
+        bh = EO.schur_source(U, lat, kappa, b[0], mu)
+        x0o = EO.restrict(lat, x0[0], 0)
+        _, _, _, io = S.gmresdr(A, bh, m, k, tol=1e-10 * nb / np.linalg.norm(bh), x0=x0o)
+    else:
+        A = W.operator(U, lat, kappa, mu)
+        _, _, _, io = S.gmresdr(A, b.reshape(-1), m, k, tol=1e-10, x0=x0.reshape(-1))
+    assert io["status"] == S.OK and io["matvecs"] == 1 + m + (m - k) * (io["cycles"] - 1)
+    assert abs(st["iterations"] - io["cycles"]) <= 1
+
+
 @pytest.mark.parametrize("shape", [None, ("0", "1"), ("0", "0"), ("0", "3"), ("1", "0")])
 def test_batched_equals_separate_and_uneven_batch(gpu_lib, monkeypatch, shape):
     """Three lattices of different size in one call give the same solutions (to the solve
@@ -207,6 +262,25 @@ def test_point_source_breakdown_restarts(gpu_lib):
                                             tol=1e-8, prec="fp64")
     assert status == 0 and st[0]["restarts"] >= 1
     assert _true_rel(U, lat, 0.15, 0.0, host(X[0]).reshape(-1), b.reshape(-1)) <= 1.0001e-8
+
+
+@pytest.mark.parametrize("every", ["5", "24"])
+def test_mixed_breakdown_restart_with_uneven_reliable_update_interval(gpu_lib, monkeypatch,
+                                                                      every):
+    """Mixed precision with the point source among the right-hand sides (rho vanishes exactly
+    after one iteration, so the host restarts it) and reliable-update blocks every 5 or 24
+    iterations (not dividing the 32-iteration poll interval): every rhs, the restarted one and
+    the others whose updates were pending, converges to 1e-8 on the oracle's residual."""
+    monkeypatch.setenv("DBQ_RELUP_EVERY", every)
+    L, lat, U = _c1()
+    B = np.concatenate([synth.point_source(L), synth.z2_sources(L, 2, 1101)])
+    X, st, status = gpu_lib.dbicgstab_solve([dict(L=L, links=dev(U), kappa=0.13, B=dev(B))],
+                                            tol=1e-8, prec="mixed")
+    assert status == 0, st
+    assert st[0]["restarts"] >= 1
+    Xh = host(X[0])
+    for j in range(3):
+        assert _true_rel(U, lat, 0.13, 0.0, Xh[j].reshape(-1), B[j].reshape(-1)) <= 1.0001e-8
 
 
 def test_max_mv_reports_not_converged(gpu_lib):
@@ -440,3 +514,56 @@ def test_mixed_solve_reaches_a_tolerance_below_fp32_precision(gpu_lib):
     for j in range(4):
         rel = _true_rel(U, lat, kap, 0.0, Xh[j].reshape(-1), B[j].reshape(-1))
         assert rel <= 1.0001e-10, (j, rel)
+
+
+# ----------------------------------------------------------------------------- projection products
+@pytest.mark.parametrize("L,k,nrhs,schur,dagger", [
+    ((4, 4, 4, 4), 6, 3, False, False),
+    ((8, 8, 8, 8), 20, 12, False, False),
+    ((8, 8, 8, 8), 40, 12, False, True),
+    ((8, 8, 4, 8), 33, 17, False, False),
+    ((8, 8, 8, 8), 20, 12, True, False),
+    ((6, 4, 4, 8), 48, 5, False, False),
+    ((6, 4, 4, 8), 50, 2, False, False)])
+def test_deflation_projection_products_match_oracle(gpu_lib, L, k, nrhs, schur, dagger):
+    """The Sec. 2 projection alone: with max_mv = 1 a D-BiCGStab call stops right after
+    x0 = V (U^H A V)^{-1} U^H b (U = gamma5 V; for the adjoint system right vectors gamma5 V and
+    left vectors V), so its output is the projected start.  The oracle forms U^H A V, U^H b and
+    the solve with dense products.  Random orthonormal V of k = 6 .. 50 columns and 2 .. 17 rhs
+    cover every tile shape of the Gram products (up to 48 columns on matrix cores, the FMA path
+    beyond), the full and the reduced system and the adjoint roles."""
+    from oracle import evenodd as EO
+    lat = W.Lattice(L)
+    U = synth.gauge_field(L, 0.5, 811)
+    kappa, mu = 0.12, 0.01
+    B = synth.z2_sources(L, nrhs, 812)
+    rng = np.random.default_rng(813)
+    even = lat.parity == 0
+    nsite = lat.V // 2 if schur else lat.V
+    G = rng.standard_normal((nsite * 12, k)) + 1j * rng.standard_normal((nsite * 12, k))
+    Vh, _ = np.linalg.qr(G)
+    if schur:
+        A = EO.schur_operator(U, lat, kappa, mu, dagger)
+        g5 = EO.gamma5_half
+        Vfull = np.zeros((k, lat.V, 4, 3), complex)
+        Vfull[:, even] = Vh.T.reshape(k, -1, 4, 3)
+        rhs = [EO.schur_source(U, lat, kappa, B[j], mu, dagger) for j in range(nrhs)]
+    else:
+        A = W.operator(U, lat, kappa, mu, dagger)
+        g5 = lambda v: W.gamma5_flat(v, lat.V)
+        Vfull = Vh.T.reshape(k, lat.V, 4, 3)
+        rhs = [B[j].reshape(-1) for j in range(nrhs)]
+    G5V = np.stack([g5(Vh[:, i]) for i in range(k)], axis=1)
+    right, left = (G5V, Vh) if dagger else (Vh, G5V)
+    AV = np.stack([A(right[:, i]) for i in range(k)], axis=1)
+    M = left.conj().T @ AV
+    cond = np.linalg.cond(M)
+    X, st, status = gpu_lib.dbicgstab_solve(
+        [dict(L=L, links=dev(U), kappa=kappa, mu=mu, B=dev(B), V=dev(Vfull), schur=schur)],
+        tol=1e-14, max_mv=1, prec="fp64", dagger=dagger)
+    Xh = host(X[0])
+    for j in range(nrhs):
+        y = np.linalg.solve(M, left.conj().T @ rhs[j])
+        want = right @ y
+        got = Xh[j][even].reshape(-1) if schur else Xh[j].reshape(-1)
+        assert np.linalg.norm(got - want) <= 1e-13 * cond * np.linalg.norm(want), (j, cond)
