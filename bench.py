@@ -170,8 +170,7 @@ def leg_c2eo(dbq, torch, synth):
     """The benchmark's 16^4 problem (links exp(0.6 iQ) seed 102, kappa = 0.995 kappa_c, 12 Z2
     sources seed 1102, tol 1e-8) on the even-odd reduced system, as a leg of its own."""
     L = (16, 16, 16, 16)
-    U = torch.from_numpy(synth.gauge_field(L, 0.6, 102)).cuda()
-    kc, _, _, _ = dbq.kappa_critical(L, U, m=96, k=32, tol=1e-8)
+    U, kc = _c2_field(dbq, torch, synth)
     B = torch.from_numpy(synth.z2_sources(L, 12, 1102)).cuda()
     return {"16x16x16x16_nrhs12_even_odd": even_odd(dbq, torch, L, U, 0.995 * kc, B, 60, 20, 1e-8,
                                                       2)}
@@ -195,7 +194,8 @@ def leg_c3(dbq, torch, synth):
                                                                    prec="mixed"))
     info.update(nrhs=24, ms_per_source=round(t * 1e3 / 24, 3), all_converged=status == 0,
                 worst_rel_true_resid=max(x["rel_true_resid"] for x in st),
-                mvps_per_source=float(np.mean([x["matvecs"] for x in st])))
+                mvps_per_source=float(np.mean([x["matvecs"] for x in st])),
+                fp64_continued=int(sum(x["fp64_continued"] for x in st)))
     out["20x20x20x32_nrhs24"] = info
     del X, B, V, U, prob
     probs, infos = [], []
@@ -210,6 +210,7 @@ def leg_c3(dbq, torch, synth):
     out["uneven_8^4_12^4_16^4_nrhs8x3"] = dict(
         lattices=infos, ms_per_source=round(t * 1e3 / 24, 3), all_converged=status == 0,
         worst_rel_true_resid=max(x["rel_true_resid"] for x in st),
+        fp64_continued=int(sum(x["fp64_continued"] for x in st)),
         mvps_per_source=[float(np.mean([x["matvecs"] for x in st[i * 8:(i + 1) * 8]]))
                          for i in range(3)])
     return out
@@ -239,6 +240,20 @@ def leg_c4(dbq, torch, synth):
     return {"16x16x16x16_gradient_nrhs8": info}
 
 
+_C2 = {}
+
+
+def _c2_field(dbq, torch, synth):
+    """The benchmark's 16^4 field (links exp(0.6 iQ), seed 102) on the device and its kappa_c,
+    computed once and shared by the legs."""
+    if not _C2:
+        L = (16, 16, 16, 16)
+        U = torch.from_numpy(synth.gauge_field(L, 0.6, 102)).cuda()
+        kc, _, _, _ = dbq.kappa_critical(L, U, m=96, k=32, tol=1e-8)
+        _C2.update(U=U, kc=kc)
+    return _C2["U"], _C2["kc"]
+
+
 def leg_f2(dbq, torch, synth):
     """The trends of Tables 1-2 on the 16^4 field of the benchmark (kappa = 0.995 kappa_c), on the
     even-odd reduced system the paper solves: GMRES-DR(k+20, k) on the point source to the
@@ -246,8 +261,7 @@ def leg_f2(dbq, torch, synth):
     on one Z2 source to 1e-8; BiCGStab without deflation for reference.  MVPs = products of the
     reduced operator."""
     L = (16, 16, 16, 16)
-    U = torch.from_numpy(synth.gauge_field(L, 0.6, 102)).cuda()
-    kc, _, _, _ = dbq.kappa_critical(L, U, m=96, k=32, tol=1e-8)
+    U, kc = _c2_field(dbq, torch, synth)
     kap = 0.995 * kc
     b0 = torch.from_numpy(synth.point_source(L)).cuda()
     b = torch.from_numpy(synth.z2_sources(L, 1, 1102)).cuda()
@@ -276,8 +290,7 @@ def leg_f3(dbq, torch, synth):
     eigenvectors of the point source (first-rhs tolerance 1e-10): BiCGStab, GMRES(20)-Proj(20),
     D-BiCGStab(20), and the mixed-precision D-BiCGStab(20) of this library."""
     L = (16, 16, 16, 16)
-    U = torch.from_numpy(synth.gauge_field(L, 0.6, 102)).cuda()
-    kc, _, _, _ = dbq.kappa_critical(L, U, m=96, k=32, tol=1e-8)
+    U, kc = _c2_field(dbq, torch, synth)
     kap = 0.995 * kc
     b0 = torch.from_numpy(synth.point_source(L)).cuda()
     b = torch.from_numpy(synth.z2_sources(L, 1, 1102)).cuda()
@@ -309,8 +322,7 @@ def leg_f4(dbq, torch, synth):
     the previous shifts' solutions (all of them, or only the last one), heaviest first and lightest
     first; total products of the reduced operator per order."""
     L = (16, 16, 16, 16)
-    U = torch.from_numpy(synth.gauge_field(L, 0.6, 102)).cuda()
-    kc, _, _, _ = dbq.kappa_critical(L, U, m=96, k=32, tol=1e-8)
+    U, kc = _c2_field(dbq, torch, synth)
     b = torch.from_numpy(synth.z2_sources(L, 1, 1102)).cuda()
     heavy_first = [0.001 * 20 ** (j / 7) for j in range(8)][::-1]
     out = dict(kappa=kc, runs=[])
@@ -381,6 +393,39 @@ def leg_c5eo(dbq, torch, synth):
     return leg_c5(dbq, torch, synth, schur=True)
 
 
+def summarize(extra):
+    """Compact summaries of the workload and experiment legs for the one-line record."""
+    out = {}
+    c3 = extra.get("20x20x20x32_nrhs24")
+    if c3:
+        un = extra.get("uneven_8^4_12^4_16^4_nrhs8x3", {})
+        out["c3_summary"] = {
+            "20x20x20x32_nrhs24": {k: c3[k] for k in ("ms_per_source", "mvps_per_source",
+                                                     "all_converged", "worst_rel_true_resid",
+                                                     "fp64_continued", "kappa_c_s", "gmresdr_s",
+                                                     "gmresdr_mvps")},
+            "uneven_8^4_12^4_16^4_nrhs8x3": {k: un.get(k) for k in (
+                "ms_per_source", "mvps_per_source", "all_converged", "fp64_continued")}}
+    f2 = extra.get("16x16x16x16_eigvec_accuracy_and_k")
+    if f2:
+        rows = f2["rows"]
+        d = {"bicgstab_mvps": rows[0]["bicgstab_mvps"],
+             "columns": "first-rhs tol 1e-8 / 1e-10 / 1e-14 (L1 / L2 / L3)"}
+        for k in (10, 20, 30):
+            rk = [r for r in rows if r["k"] == k]
+            d[f"k{k}_dbicgstab_mvps"] = [r["bicgstab_mvps"] for r in rk]
+            d[f"k{k}_gmresdr_mvps"] = [r["gmresdr_mvps"] for r in rk]
+        out["f2_summary"] = d
+    f3 = extra.get("16x16x16x16_method_comparison")
+    if f3:
+        out["f3_summary"] = {k: [v["mvps"], v["ms"]] for k, v in f3["runs"].items()}
+        out["f3_summary"]["columns"] = "MVPs, ms (one Z2 source, reduced system, tol 1e-8)"
+    f4 = extra.get("16x16x16x16_shift_order")
+    if f4:
+        out["f4_summary"] = {r["order"]: r["total_mvps"] for r in f4["runs"]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -390,6 +435,9 @@ def main():
     ap.add_argument("--quick", action="store_true", help="skip the FP64 comparisons and sweep")
     ap.add_argument("--dslash-only", action="store_true",
                     help="only the 24^3 x 48 Dslash bandwidth sweep (one JSON line)")
+    ap.add_argument("--summary-legs", default="c3,f2,f3,f4",
+                    help="legs run after the timed steps and reported as compact summaries "
+                         "(empty: none)")
     ap.add_argument("--extra", default="",
                     help="comma-separated extra workload legs, outside the timed steps: c2eo "
                          "(the benchmark problem on the even-odd reduced system), c3 "
@@ -571,12 +619,20 @@ def main():
         log(f"dslash sweep: {out['dslash_24x24x24x48']}")
     legs = {"c2eo": leg_c2eo, "c3": leg_c3, "c4": leg_c4, "c5": leg_c5, "c5eo": leg_c5eo,
             "f2": leg_f2, "f3": leg_f3, "f4": leg_f4}
-    for name in [x for x in a.extra.split(",") if x]:
+    _C2.update(U=U, kc=kc)
+    summary_legs = [] if a.quick else [x for x in a.summary_legs.split(",") if x]
+    extra_legs = [x for x in a.extra.split(",") if x]
+    for name in summary_legs + [x for x in extra_legs if x not in summary_legs]:
         if name not in legs:
             raise SystemExit(f"unknown leg {name}")
         log(f"leg {name} ...")
-        out.setdefault("extra", {}).update(legs[name](dbq, torch, synth))
-        log(f"leg {name}: {out['extra']}")
+        t_leg = time.perf_counter()
+        res = legs[name](dbq, torch, synth)
+        log(f"leg {name} ({time.perf_counter() - t_leg:.1f} s): {res}")
+        if name in summary_legs:
+            out.update(summarize(res))
+        if name in extra_legs:
+            out.setdefault("extra", {}).update(res)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Uh, L, kappa, Bh[0], mv64 or mv_mixed)
         log(f"cpu baseline: {out['cpu_baseline']}")
