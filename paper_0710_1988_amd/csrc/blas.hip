@@ -144,7 +144,7 @@ void gram_impl(hipStream_t s, const double2* A, long long lda, int na, const dou
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int GM_BS = 256;           // 4 waves
 constexpr int GM_CHUNK = 16;         // doubles per column per wave step
-constexpr int GM_MAX_BLOCKS = 512;
+constexpr int GM_MAX_BLOCKS = 1024;
 
 template <int TA, int TB>
 __global__ __launch_bounds__(GM_BS) void k_gram_mfma(const double* __restrict__ A, long long lda,
@@ -172,9 +172,10 @@ __global__ __launch_bounds__(GM_BS) void k_gram_mfma(const double* __restrict__ 
   for (int b = 0; b < TB; ++b) bp[b] = B + (long long)min(16 * b + r, nb - 1) * ldb;
   const long long nchunks = (n2 + GM_CHUNK - 1) / GM_CHUNK;
   const long long stride = (long long)gridDim.x * (GM_BS / 64);
-  for (long long ch = (long long)blockIdx.x * (GM_BS / 64) + wv; ch < nchunks; ch += stride) {
+  // this lane's four doubles of chunk ch of every column (zero past the end; negated on the
+  // gamma5 = -1 half for the left vectors)
+  auto load = [&](long long ch, double (&av)[TA][4], double (&bv)[TB][4]) {
     const long long k0 = ch * GM_CHUNK + 4 * q;
-    double av[TA][4], bv[TB][4];
     if (k0 + 4 <= n2) {
 #pragma unroll
       for (int a = 0; a < TA; ++a) {
@@ -204,6 +205,8 @@ __global__ __launch_bounds__(GM_BS) void k_gram_mfma(const double* __restrict__ 
 #pragma unroll
         for (int t = 0; t < 4; ++t) av[a][t] = -av[a][t];
     }
+  };
+  auto mfma = [&](const double (&av)[TA][4], const double (&bv)[TB][4]) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
 #pragma unroll
@@ -217,6 +220,20 @@ __global__ __launch_bounds__(GM_BS) void k_gram_mfma(const double* __restrict__ 
         }
       }
     }
+  };
+  // two chunks per step: the second chunk's loads are in flight while the first is multiplied
+  long long ch = (long long)blockIdx.x * (GM_BS / 64) + wv;
+  for (; ch + stride < nchunks; ch += 2 * stride) {
+    double av0[TA][4], bv0[TB][4], av1[TA][4], bv1[TB][4];
+    load(ch, av0, bv0);
+    load(ch + stride, av1, bv1);
+    mfma(av0, bv0);
+    mfma(av1, bv1);
+  }
+  if (ch < nchunks) {
+    double av0[TA][4], bv0[TB][4];
+    load(ch, av0, bv0);
+    mfma(av0, bv0);
   }
   // the four waves' products summed in LDS in wave order, then stored as this block's partial
   // [a][b][re, im][16 rows][16 columns]
@@ -246,23 +263,26 @@ __global__ __launch_bounds__(GM_BS) void k_gram_mfma(const double* __restrict__ 
   for (int v = threadIdx.x; v < NV; v += GM_BS) out[v] = sh[v];
 }
 
-// C[i + j na] = sum over the blocks' partials, in block order: one thread per output value
+// C[i + j na] = sum over the blocks' partials: one wavefront per output value, lane l adding the
+// blocks l, l + 64, ... in order, then a fixed butterfly over the lanes (deterministic)
 template <int TA, int TB>
 __global__ __launch_bounds__(256) void k_gram_mfma_final(const double* __restrict__ work,
                                                          int nblocks, int na, int nb,
                                                          double2* __restrict__ C) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (t >= na * nb) return;
   const int i = t % na, j = t / na;
   const int a = i >> 4, b = j >> 4;
   const int o = (a * TB + b) * 512 + (i & 15) * 16 + (j & 15);
   constexpr int NV = TA * TB * 2 * 256;
   double re = 0.0, im = 0.0;
-  for (int k = 0; k < nblocks; ++k) {
+  for (int k = lane; k < nblocks; k += 64) {
     re += work[(long long)k * NV + o];
     im += work[(long long)k * NV + o + 256];
   }
-  C[i + (long long)j * na] = make_double2(re, im);
+  re = wave_sum(re);
+  im = wave_sum(im);
+  if (lane == 0) C[i + (long long)j * na] = make_double2(re, im);
 }
 
 template <int TA, int TB>
@@ -278,7 +298,7 @@ void gram_mfma_impl(hipStream_t s, const double2* A, long long lda, int na, cons
   hipLaunchKernelGGL((k_gram_mfma<TA, TB>), dim3(nblocks), dim3(GM_BS), 0, s, (const double*)A,
                      2 * lda, na, (const double*)B, 2 * ldb, nb, n2, 12 * V, g5, work);
   DBQ_HIP(hipGetLastError());
-  hipLaunchKernelGGL((k_gram_mfma_final<TA, TB>), dim3((na * nb + 255) / 256), dim3(256), 0, s,
+  hipLaunchKernelGGL((k_gram_mfma_final<TA, TB>), dim3((na * nb + 3) / 4), dim3(256), 0, s,
                      work, nblocks, na, nb, C);
   DBQ_HIP(hipGetLastError());
 }
@@ -443,7 +463,8 @@ size_t gram_work_elems(long long n, int na, int nb) {
   // the largest of the tilings
   const long long t1 = nchunks * ((na + 7) / 8) * ((nb + 3) / 4) * 8 * 4 * 2;
   const long long t2 = nchunks * ((na + 15) / 16) * 16 * 2;
-  const long long t3 = (long long)GM_MAX_BLOCKS * 3 * 3 * 2 * 256;
+  const long long ta = (na + 15) / 16, tb = (nb + 15) / 16;
+  const long long t3 = (ta <= 3 && tb <= 3) ? (long long)GM_MAX_BLOCKS * ta * tb * 2 * 256 : 0;
   return size_t(std::max(t1, std::max(t2, t3)));
 }
 
