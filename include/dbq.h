@@ -143,6 +143,21 @@ int dbq_stream_probe(dbq_ctx* ctx, const void* src, void* dst, int64_t bytes, in
 int wilson_apply(dbq_ctx* ctx, const dbq_operator* op, const void* in, void* out,
                  int32_t nrhs, int32_t dagger, int32_t prec);
 
+/* wilson_apply for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same operator, but the packed
+ * links and vectors live in one static device array of 64 MiB per GPU (each GPU that the library
+ * runs on holds it until the process ends; its device address is looked up in dbq_create), and
+ * the call allocates nothing.  Full operator only (op->schur = 0); a fixed launch shape (FP64:
+ * one thread per site; DBQ_MIXED: the LDS tile kernel with every rhs per block), so no tuning.
+ * in, out: DEVICE complex128 [nrhs][V][12] as for wilson_apply (the caller owns them).  The
+ * scratch must hold the packed links and both packed vectors: V * (576 + 384 nrhs) bytes in FP64,
+ * V * (192 + 192 nrhs) in DBQ_MIXED (each part rounded up to 256 bytes); larger inputs return
+ * DBQ_EINVAL before any launch.  Every call on a GPU uses that GPU's one array: calls that overlap
+ * on one GPU (several streams or threads) race; calls ordered on one stream do not.  Not
+ * synchronising. */
+int wilson_apply_noalloc(dbq_ctx* ctx, const dbq_operator* op, const void* in, void* out,
+                         int32_t nrhs, int32_t dagger, int32_t prec);
+
 /* First right-hand side by GMRES-DR(m,k) (Sec. 1 and Sec. 3): restarted GMRES whose restart
  * keeps the k harmonic Ritz vectors of smallest |theta|; convergence is tested once per cycle,
  * so matvecs = m + (m-k)(cycles-1) when x0 = 0.

@@ -21,7 +21,8 @@ EXPORTED = ["dbq_create", "dbq_destroy", "dbq_last_error", "dbq_set_stream", "db
             "dbq_geometry_host", "dbq_site_tile", "wilson_apply", "gmresdr_first_rhs", "dbicgstab_solve",
             "project_shifts", "gmres_proj_solve", "link_force", "kappa_critical", "dbq_set_timing",
             "dbq_kernel_time",
-            "dbq_reset_timing", "dbq_version", "dbq_tile_schedule_host", "dbq_stream_probe"]
+            "dbq_reset_timing", "dbq_version", "dbq_tile_schedule_host", "dbq_stream_probe",
+            "wilson_apply_noalloc"]
 
 
 class Operator(ctypes.Structure):
@@ -67,6 +68,7 @@ def load():
         "dbq_geometry_host": ([PI32, PI32, PI32], ctypes.c_int),
         "dbq_site_tile": ([PI32, PI32], ctypes.c_int),
         "wilson_apply": ([P, POP, P, P, I32, I32, I32], ctypes.c_int),
+        "wilson_apply_noalloc": ([P, POP, P, P, I32, I32, I32], ctypes.c_int),
         "gmresdr_first_rhs": ([P, POP, P, P, I32, I32, D, I64, P, PD, PI32, PST], ctypes.c_int),
         "dbicgstab_solve": ([P, POP, I32, ctypes.POINTER(P), PI32, ctypes.POINTER(P),
                              ctypes.POINTER(P), PI32, D, I64, I32, I32, PST], ctypes.c_int),

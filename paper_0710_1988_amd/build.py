@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "libdbq.so")
 ARCH = os.environ.get("DBQ_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["pack.hip", "dslash.hip", "bicg.hip", "blas.hip", "dense.hip", "force.hip",
-           "solvers.hip", "probe.hip", "ctx.cpp", "capi.cpp"]
+           "solvers.hip", "probe.hip", "noalloc.hip", "ctx.cpp", "capi.cpp"]
 
 
 def hipcc():

@@ -46,6 +46,14 @@ int dbq_create(dbq_ctx** out, void* stream) {
     delete c;
     return DBQ_EHIP;
   }
+  // set-up of the allocation-free apply: this device's address of its static scratch array
+  // (a failure here leaves it null; that entry point then retries and reports the error)
+  try {
+    c->scratch = dbq::noalloc_scratch(c->device);
+  } catch (const Error&) {
+    (void)hipGetLastError();
+    c->scratch = nullptr;
+  }
   *out = c;
   return DBQ_OK;
 }
@@ -144,6 +152,14 @@ int wilson_apply(dbq_ctx* c, const dbq_operator* op, const void* in, void* out, 
                  int32_t dagger, int32_t prec) {
   return guarded(c, [&]() {
     dbq::apply_operator(c, op, in, out, nrhs, dagger ? 1 : 0, prec);
+    return DBQ_OK;
+  });
+}
+
+int wilson_apply_noalloc(dbq_ctx* c, const dbq_operator* op, const void* in, void* out,
+                         int32_t nrhs, int32_t dagger, int32_t prec) {
+  return guarded(c, [&]() {
+    dbq::apply_operator_noalloc(c, op, in, out, nrhs, dagger ? 1 : 0, prec);
     return DBQ_OK;
   });
 }

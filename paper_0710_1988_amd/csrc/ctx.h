@@ -21,6 +21,10 @@ struct dbq_ctx {
   };
   std::vector<Buf> pool;
 
+  // ---- this device's copy of the allocation-free apply's static scratch array (its device
+  //      address, looked up at dbq_create; null until then)
+  void* scratch = nullptr;
+
   // ---- pinned host staging for scalar readbacks
   void* pinned = nullptr;
   size_t pinned_bytes = 0;

@@ -22,5 +22,11 @@ void force(dbq_ctx* c, const dbq_operator* o, const void* lambda, const void* x,
            int kind, void* F);
 // average milliseconds of one streaming probe launch (probe.hip)
 double stream_probe(dbq_ctx* c, const void* src, void* dst, long long bytes, int kind, int reps);
+// the operator apply on the static scratch array of noalloc.hip (no device allocation)
+void apply_operator_noalloc(dbq_ctx* c, const dbq_operator* o, const void* in, void* out,
+                            int nrhs, int dagger, int prec);
+// device address of the current device's scratch array (looked up once per device)
+void* noalloc_scratch(int device);
+size_t noalloc_scratch_bytes();
 
 }  // namespace dbq
