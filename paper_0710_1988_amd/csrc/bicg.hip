@@ -355,6 +355,13 @@ __global__ __launch_bounds__(BL_BS) void k_xacc(VecSet vs, VecSet vs64, double2*
   }
 }
 
+__global__ void k_mask_unselected(double2* __restrict__ Y, int k, int nrhs,
+                                  const RhsScal* __restrict__ sc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k * nrhs) return;
+  if (!sc[i / k].sel) Y[i] = make_double2(0.0, 0.0);
+}
+
 template <typename E>
 void step(hipStream_t s, int op, const VecSet& vs, E* x, E* r, const E* rhat, E* p, const E* v,
           const E* t, RhsScal* sc, double* partials, unsigned long long* acct) {
@@ -421,6 +428,12 @@ void bicg_aux_f32(hipStream_t s, int op, const VecSet& vs32, const VecSet& vs64,
   if (op == AX_INIT) launch_fin_aux<AX_INIT>(s, vs32, sc, partials);
   else if (op == AX_RESTART) launch_fin_aux<AX_RESTART>(s, vs32, sc, partials);
   else launch_fin_aux<AX_REPLACE>(s, vs32, sc, partials);
+}
+
+void mask_unselected_f64(hipStream_t s, double2* Y, int k, int nrhs, const RhsScal* sc) {
+  hipLaunchKernelGGL(k_mask_unselected, dim3((k * nrhs + 255) / 256), dim3(256), 0, s, Y, k, nrhs,
+                     sc);
+  DBQ_HIP(hipGetLastError());
 }
 
 void bicg_xacc(hipStream_t s, const VecSet& vs32, const VecSet& vs64, double2* x64, float4* x32,

@@ -3,6 +3,7 @@
 // Gram-Schmidt steps of GMRES-DR's Arnoldi process.  All of them stream long vectors once and
 // are bound by HBM bandwidth; the gamma5 of the left vectors is a sign folded into the loads.
 #include <algorithm>
+#include <cfloat>
 
 #include "kernels.h"
 
@@ -345,6 +346,136 @@ __global__ __launch_bounds__(256) void k_combine(const double2* __restrict__ A, 
   }
 }
 
+// ---- Arnoldi step with delayed reorthogonalisation (classical Gram-Schmidt twice, the second
+// pass of each new vector done one step late so that both passes share the sweeps over the basis:
+// two sweeps per step instead of four).
+// On entry to step j, column j of the basis holds z_j, the once-orthogonalised, not yet
+// normalised new vector, and column j+1 holds w = A z_j.  One Gram sweep gives
+// G = [q_0 .. q_{j-1}, z_j]^H [z_j, w].  With nu = |z_j|, u = z_j / nu and Q = [q_0 .. q_{j-1}]:
+//   s = Q^H u (second-pass coefficients of u), rho = sqrt(1 - |s|^2), q_j = (u - Q s) / rho;
+//   previous column: A q_{j-1} = Q (h_{j-1} + nu s) + nu rho q_j;
+//   t = Q^H w / nu, beta = u^H w / nu and, since A q_j = (w / nu - A Q s) / rho with
+//   A Q = [Q, q_j] Hbar (Hbar: the corrected (j+1) x j Hessenberg block), the new column
+//   h_j = ([t; (beta - s^H t) / rho] - Hbar s) / rho and the next vector
+//   z_{j+1} = A q_j - [Q, q_j] h_j = (w / nu - Q (t - gamma s) - gamma u) / rho,
+//   gamma = (beta - s^H t) / rho^2.
+// The second sweep (k_arn_combine) writes q_j and z_{j+1} in place from
+//   m0 = [-s / rho; 1 / (nu rho)],  m1 = [(t - gamma s) / rho; gamma / (nu rho)],
+//   c1 = 1 / (nu rho):  col j = [Q, z_j] m0,  col j+1 = c1 w - [Q, z_j] m1.
+// A vector that starts a cycle (v_1, or the last vector of a restart basis) is already
+// orthonormal and consistent with Hbar: there s = 0 and nu = rho = 1, and no column is
+// corrected.  With last = 1 column j (= m) is only reorthogonalised (G has one column) and the
+// last Hessenberg column corrected.
+constexpr int AC_BS = 256;
+constexpr int AC_MAXJ = 128;
+
+__global__ __launch_bounds__(AC_BS) void k_arn_coef(const double2* __restrict__ G, int j,
+                                                    int start, int last, double2* __restrict__ H,
+                                                    int ldh, double2* __restrict__ m0,
+                                                    double2* __restrict__ m1,
+                                                    double* __restrict__ c1) {
+  __shared__ zd s_s[AC_MAXJ];
+  __shared__ double red[3 * (AC_BS / 64)];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int na = j + 1;
+  const double nu = start ? 1.0 : sqrt(G[j].x);
+  const double inu = 1.0 / nu;
+  double p[3] = {0.0, 0.0, 0.0};  // |s|^2, s^H t
+  for (int i = t; i < j; i += AC_BS) {
+    const zd si = start ? zd{0.0, 0.0} : zd{G[i].x * inu, G[i].y * inu};
+    s_s[i] = si;
+    p[0] += norm2(si);
+    if (!last) {
+      const zd st = cmulc(si, zd{G[na + i].x * inu, G[na + i].y * inu});
+      p[1] += st.re;
+      p[2] += st.im;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    p[q] = wave_sum(p[q]);
+    if (lane == 0) red[q * (AC_BS / 64) + wv] = p[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    double v = 0.0;
+    for (int w = 0; w < AC_BS / 64; ++w) v += red[q * (AC_BS / 64) + w];
+    p[q] = v;
+  }
+  // a vector that lies (to rounding) in the span of Q leaves nothing to normalise: keep rho
+  // away from zero so that the step stays finite (the Hessenberg entry nu rho is then ~0)
+  const double rho = start ? 1.0 : sqrt(fmax(1.0 - p[0], DBL_EPSILON));
+  const double irho = 1.0 / rho, c = inu * irho;
+  if (!start && j >= 1) {
+    for (int i = t; i < j; i += AC_BS) {
+      const double2 h = H[i + (long long)(j - 1) * ldh];
+      H[i + (long long)(j - 1) * ldh] = make_double2(h.x + nu * s_s[i].re, h.y + nu * s_s[i].im);
+    }
+    if (t == 0) H[j + (long long)(j - 1) * ldh] = make_double2(nu * rho, 0.0);
+  }
+  __syncthreads();
+  if (last) {
+    for (int i = t; i <= j; i += AC_BS)
+      m0[i] = i < j ? make_double2(-s_s[i].re * irho, -s_s[i].im * irho) : make_double2(c, 0.0);
+    if (t == 0) *c1 = c;
+    return;
+  }
+  const zd beta{G[na + j].x * inu * inu, G[na + j].y * inu * inu};
+  const zd bq{(beta.re - p[1]) * irho, (beta.im - p[2]) * irho};  // q_j^H w / nu
+  const zd gam{bq.re * irho, bq.im * irho};
+  for (int i = t; i <= j; i += AC_BS) {
+    zd hs{0.0, 0.0};
+    if (!start)
+      for (int cc = 0; cc < j; ++cc) {
+        const double2 h = H[i + (long long)cc * ldh];
+        hs = hs + zd{h.x, h.y} * s_s[cc];
+      }
+    const zd ti = i < j ? zd{G[na + i].x * inu, G[na + i].y * inu} : bq;
+    H[i + (long long)j * ldh] = make_double2((ti.re - hs.re) * irho, (ti.im - hs.im) * irho);
+    if (i < j) {
+      const zd si = s_s[i];
+      m0[i] = make_double2(-si.re * irho, -si.im * irho);
+      const zd g = gam * si;
+      m1[i] = make_double2((ti.re - g.re) * irho, (ti.im - g.im) * irho);
+    } else {
+      m0[i] = make_double2(c, 0.0);
+      m1[i] = make_double2(gam.re * c, gam.im * c);
+    }
+  }
+  if (t == 0) *c1 = c;
+}
+
+// col j = sum_{i<=j} Q_i m0[i]; with TWO also col j+1 = c1 col(j+1) - sum_{i<=j} Q_i m1[i]
+// (each thread reads its row of every column before it writes, so in place is safe)
+template <bool TWO>
+__global__ __launch_bounds__(256) void k_arn_combine(double2* Q, long long ld, int j, long long n,
+                                                     const double2* __restrict__ m0,
+                                                     const double2* __restrict__ m1,
+                                                     const double* __restrict__ c1) {
+  const long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  double a0r = 0, a0i = 0, a1r = 0, a1i = 0;
+#pragma unroll 4
+  for (int i = 0; i <= j; ++i) {
+    const double2 q = Q[(long long)i * ld + row];
+    const double2 x = m0[i];
+    a0r += q.x * x.x - q.y * x.y;
+    a0i += q.x * x.y + q.y * x.x;
+    if (TWO) {
+      const double2 y = m1[i];
+      a1r += q.x * y.x - q.y * y.y;
+      a1i += q.x * y.y + q.y * y.x;
+    }
+  }
+  if (TWO) {
+    const double f = *c1;
+    const double2 w = Q[(long long)(j + 1) * ld + row];
+    Q[(long long)(j + 1) * ld + row] = make_double2(f * w.x - a1r, f * w.y - a1i);
+  }
+  Q[(long long)j * ld + row] = make_double2(a0r, a0i);
+}
+
 __global__ void k_scale(const double2* __restrict__ x, double2* __restrict__ y, long long n,
                         const double* __restrict__ nrm2) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -498,6 +629,29 @@ void gram_f64(hipStream_t s, const double2* A, long long lda, int na, const doub
     }
   }
   gram_impl<8, 4>(s, A, lda, na, B, ldb, nb, n, V, g5, C, work, work_elems);
+}
+
+void gram2_f64(hipStream_t s, const double2* A, long long lda, int na, const double2* B,
+               long long ldb, long long n, double2* C, double* work, size_t work_elems) {
+  gram_impl<16, 2>(s, A, lda, na, B, ldb, 2, n, 1, 0, C, work, work_elems);
+}
+
+void arn_coef_f64(hipStream_t s, const double2* G, int j, int start, int last, double2* H, int ldh,
+                  double2* m0, double2* m1, double* c1) {
+  DBQ_CHECK(j >= 0 && j <= AC_MAXJ, "arn_coef: column index out of range");
+  hipLaunchKernelGGL(k_arn_coef, dim3(1), dim3(AC_BS), 0, s, G, j, start, last, H, ldh, m0, m1, c1);
+  DBQ_HIP(hipGetLastError());
+}
+
+void arn_combine_f64(hipStream_t s, double2* Q, long long ld, int j, long long n, const double2* m0,
+                     const double2* m1, const double* c1) {
+  if (m1)
+    hipLaunchKernelGGL((k_arn_combine<true>), dim3(nb256(n)), dim3(256), 0, s, Q, ld, j, n, m0,
+                       m1, c1);
+  else
+    hipLaunchKernelGGL((k_arn_combine<false>), dim3(nb256(n)), dim3(256), 0, s, Q, ld, j, n, m0,
+                       m1, c1);
+  DBQ_HIP(hipGetLastError());
 }
 
 void combine_f64(hipStream_t s, const double2* A, long long lda, int na, const double2* M, int ldm,

@@ -1,9 +1,16 @@
 // Small dense FP64 complex linear algebra on one workgroup (one wavefront): the k x k solve of
 // the deflation step (Sec. 2), and the end of a GMRES-DR / Arnoldi cycle -- least squares on the
 // (m+1) x m Hessenberg-like matrix, the harmonic Ritz (or Ritz) eigenproblem, selection of k
-// vectors, and the restart basis.  These matrices have at most 129 x 128 entries; the kernels
-// keep them in global memory (resident in L2) and run every rotation and reflection with the 64
-// lanes of one wavefront working on a row or column at a time.
+// vectors, and the restart basis.  The matrices have at most 129 x 128 entries.
+//
+// Every phase works on a copy in LDS where it fits: one shared area of 97 x 96 complex entries
+// (145.5 KiB), reused phase by phase, holds the (m+1) x m least-squares matrix (m <= 96), then the
+// m x m matrix of the eigenproblem (m <= 96) together with its Schur vectors (m <= 68), then the
+// restart basis and Hbar times it.  Larger problems use the same code on the global scratch area
+// (resident in L2).  The 64 lanes share every step: vectors that one lane would otherwise walk
+// serially (pivot search, triangular solves, eigenvectors of the triangular factor) are held one
+// entry per lane in registers and move by shuffles, and a Givens rotation of the QR iteration
+// updates its two rows, its two columns and the Schur vectors in one phase (one barrier).
 #include <cfloat>
 
 #include "kernels.h"
@@ -12,7 +19,8 @@ namespace dbq {
 
 namespace {
 
-constexpr int NT = 64;  // one wavefront
+constexpr int NT = 64;         // one wavefront
+constexpr int LDS_CAP = 9312;  // double2 entries of the shared area (97 x 96)
 
 __device__ __forceinline__ double cabs_(zd a) { return hypot(a.re, a.im); }
 __device__ __forceinline__ zd ld2(const double2* p, long long i) {
@@ -20,36 +28,122 @@ __device__ __forceinline__ zd ld2(const double2* p, long long i) {
   return zd{v.x, v.y};
 }
 __device__ __forceinline__ void st2(double2* p, long long i, zd a) { p[i] = make_double2(a.re, a.im); }
-
-// sum of v over the workgroup (single wavefront), result in every lane
 __device__ __forceinline__ double wsum(double v) { return wave_sum(v); }
+__device__ __forceinline__ double nrm1(zd a) { return fabs(a.re) + fabs(a.im); }
 
-// ----------------------------------------------------------------------------- LU (column-major)
-// In-place LU with partial pivoting of an n x n matrix; piv[j] = row swapped with j.
-// Returns false (in every lane) if a pivot is exactly zero.
-__device__ bool lu_factor(double2* A, int n, int ld, int* piv) {
-  __shared__ int s_p;
-  __shared__ int s_ok;
+// A vector of up to 128 entries held across the wavefront: entry i in lane i % 64, in member a
+// for i < 64 and b above.  Index arguments are uniform over the wave.
+struct WVec {
+  zd a, b;
+};
+__device__ __forceinline__ zd wv_get(const WVec& x, int i) {
+  const zd v = i < 64 ? x.a : x.b;
+  return zd{__shfl(v.re, i & 63, 64), __shfl(v.im, i & 63, 64)};
+}
+__device__ __forceinline__ void wv_set(WVec& x, int i, zd v) {
+  if (int(threadIdx.x) == (i & 63)) {
+    if (i < 64) x.a = v;
+    else x.b = v;
+  }
+}
+__device__ __forceinline__ WVec wv_load(const double2* p, int n) {
   const int t = threadIdx.x;
-  if (t == 0) s_ok = 1;
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    if (t == 0) {
-      int p = j;
-      double best = -1.0;
-      for (int i = j; i < n; ++i) {
-        const double a = cabs_(ld2(A, i + (long long)j * ld));
-        if (a > best) {
-          best = a;
-          p = i;
-        }
-      }
-      s_p = p;
-      piv[j] = p;
-      if (best == 0.0) s_ok = 0;
+  WVec x;
+  x.a = t < n ? ld2(p, t) : zd{0.0, 0.0};
+  x.b = t + 64 < n ? ld2(p, t + 64) : zd{0.0, 0.0};
+  return x;
+}
+
+// ----------------------------------------------------------------------------- reflections
+// Householder reflector H = I - f w w^H with H x = alpha e_1, alpha = -phase(x_0) |x|: from x_0
+// and |x|^2, w equals x except w_0 = x_0 - alpha.
+__device__ __forceinline__ void reflector(zd x0, double nx2, zd& w0, double& f) {
+  const double ax0 = cabs_(x0), nx = sqrt(nx2);
+  const zd ph = ax0 > 0 ? zd{x0.re / ax0, x0.im / ax0} : zd{1.0, 0.0};
+  const zd alpha{-ph.re * nx, -ph.im * nx};
+  w0 = x0 - alpha;
+  f = 2.0 / (nx2 - ax0 * ax0 + norm2(w0));
+}
+
+// col[0..len) <- H col with w = (w0, v[1], ..., v[len-1])
+__device__ __forceinline__ void reflect_col(double2* col, const double2* v, zd w0, int len,
+                                            double f) {
+  zd s = cmulc(w0, ld2(col, 0));
+#pragma unroll 4
+  for (int i = 1; i < len; ++i) s = s + cmulc(ld2(v, i), ld2(col, i));
+  s = f * s;
+  st2(col, 0, ld2(col, 0) - w0 * s);
+#pragma unroll 4
+  for (int i = 1; i < len; ++i) st2(col, i, ld2(col, i) - ld2(v, i) * s);
+}
+
+// ----------------------------------------------------------------------------- least squares
+// Householder QR of QR ((m+1) x m, ld m+1) with g (m+1 entries) transformed alongside: on exit the
+// upper triangle of QR is R and g = Q^H g.  v: scratch of m+1 entries.
+__device__ __forceinline__ void ls_qr(double2* QR, double2* g, int m, double2* v) {
+  const int t = threadIdx.x, m1 = m + 1;
+  for (int j = 0; j < m; ++j) {
+    const int len = m1 - j;
+    double p = 0;
+    for (int i = t; i < len; i += NT) {
+      const double2 x = QR[(j + i) + (long long)j * m1];
+      p += x.x * x.x + x.y * x.y;
+      v[i] = x;
     }
+    const double nx2 = wsum(p);
     __syncthreads();
-    const int p = s_p;
+    if (nx2 == 0.0) continue;
+    zd w0;
+    double f;
+    reflector(ld2(v, 0), nx2, w0, f);
+    for (int c = j + t; c <= m; c += NT)
+      reflect_col(c < m ? QR + (long long)c * m1 + j : g + j, v, w0, len, f);
+    __syncthreads();
+  }
+}
+
+// R d = g for upper-triangular R (m x m, ld ldr); d across the wave (0 where R_ii = 0)
+__device__ __forceinline__ WVec back_subst(const double2* R, int ldr, const double2* g, int m) {
+  const int t = threadIdx.x;
+  WVec b = wv_load(g, m);
+  for (int j = m - 1; j >= 0; --j) {
+    const zd rjj = ld2(R, j + (long long)j * ldr);
+    const zd dj = (rjj.re != 0.0 || rjj.im != 0.0) ? cdiv(wv_get(b, j), rjj) : zd{0.0, 0.0};
+    wv_set(b, j, dj);
+    if (t < j) b.a = b.a - ld2(R, t + (long long)j * ldr) * dj;
+    if (t + 64 < j) b.b = b.b - ld2(R, t + 64 + (long long)j * ldr) * dj;
+  }
+  return b;
+}
+
+// ----------------------------------------------------------------------------- LU
+// In-place LU with partial pivoting of A (n x n, ld ld); piv[j] = row swapped with j (LDS).
+// Returns false if a pivot column is exactly zero (that step is skipped).
+__device__ __forceinline__ bool lu_wave(double2* A, int n, int ld, int* piv) {
+  const int t = threadIdx.x;
+  bool ok = true;
+  for (int j = 0; j < n; ++j) {
+    double best = -1.0;
+    int bi = n;
+    for (int i = j + t; i < n; i += NT) {
+      const double a = cabs_(ld2(A, i + (long long)j * ld));
+      if (a > best) {
+        best = a;
+        bi = i;
+      }
+    }
+    // the largest modulus, the first row among equal ones
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    const int p = bi;
+    if (t == 0) piv[j] = p;
+    if (best == 0.0) ok = false;
     if (p != j)
       for (int c = t; c < n; c += NT) {
         const zd a = ld2(A, j + (long long)c * ld), b = ld2(A, p + (long long)c * ld);
@@ -59,192 +153,198 @@ __device__ bool lu_factor(double2* A, int n, int ld, int* piv) {
     __syncthreads();
     const zd d = ld2(A, j + (long long)j * ld);
     if (d.re != 0.0 || d.im != 0.0) {
-      for (int i = j + 1 + t; i < n; i += NT) st2(A, i + (long long)j * ld, cdiv(ld2(A, i + (long long)j * ld), d));
+      for (int i = j + 1 + t; i < n; i += NT)
+        st2(A, i + (long long)j * ld, cdiv(ld2(A, i + (long long)j * ld), d));
       __syncthreads();
-      for (int idx = t; idx < (n - j - 1) * (n - j - 1); idx += NT) {
-        const int i = j + 1 + idx % (n - j - 1), c = j + 1 + idx / (n - j - 1);
-        st2(A, i + (long long)c * ld, ld2(A, i + (long long)c * ld) - ld2(A, i + (long long)j * ld) * ld2(A, j + (long long)c * ld));
+      const int r = n - j - 1;
+      for (int idx = t; idx < r * r; idx += NT) {
+        const int i = j + 1 + idx % r, c = j + 1 + idx / r;
+        st2(A, i + (long long)c * ld,
+            ld2(A, i + (long long)c * ld) - ld2(A, i + (long long)j * ld) * ld2(A, j + (long long)c * ld));
       }
     }
     __syncthreads();
   }
-  return s_ok != 0;
+  return ok;
 }
 
-// Solve (LU) x = b for one right-hand side in a single lane (b overwritten).
-__device__ void lu_solve_lane(const double2* A, int n, int ld, const int* piv, double2* b, long long ldb_stride) {
+// (LU) x = b with the factors of lu_wave; b and x across the wave
+__device__ __forceinline__ void lu_solve_wave(const double2* A, int n, int ld, const int* piv,
+                                              WVec& b) {
+  const int t = threadIdx.x;
   for (int j = 0; j < n; ++j) {
     const int p = piv[j];
     if (p != j) {
-      const zd a = ld2(b, j * ldb_stride), c = ld2(b, p * ldb_stride);
-      st2(b, j * ldb_stride, c);
-      st2(b, p * ldb_stride, a);
+      const zd bj = wv_get(b, j), bp = wv_get(b, p);
+      wv_set(b, j, bp);
+      wv_set(b, p, bj);
     }
   }
-  for (int i = 0; i < n; ++i) {  // L y = b (unit diagonal)
-    zd s = ld2(b, i * ldb_stride);
-    for (int j = 0; j < i; ++j) s = s - ld2(A, i + (long long)j * ld) * ld2(b, j * ldb_stride);
-    st2(b, i * ldb_stride, s);
+  for (int j = 0; j < n; ++j) {  // L y = b (unit diagonal)
+    const zd bj = wv_get(b, j);
+    if (t > j && t < n) b.a = b.a - ld2(A, t + (long long)j * ld) * bj;
+    if (t + 64 > j && t + 64 < n) b.b = b.b - ld2(A, t + 64 + (long long)j * ld) * bj;
   }
-  for (int i = n - 1; i >= 0; --i) {  // U x = y
-    zd s = ld2(b, i * ldb_stride);
-    for (int j = i + 1; j < n; ++j) s = s - ld2(A, i + (long long)j * ld) * ld2(b, j * ldb_stride);
-    st2(b, i * ldb_stride, cdiv(s, ld2(A, i + (long long)i * ld)));
+  for (int j = n - 1; j >= 0; --j) {  // U x = y
+    const zd xj = cdiv(wv_get(b, j), ld2(A, j + (long long)j * ld));
+    wv_set(b, j, xj);
+    if (t < j) b.a = b.a - ld2(A, t + (long long)j * ld) * xj;
+    if (t + 64 < j) b.b = b.b - ld2(A, t + 64 + (long long)j * ld) * xj;
   }
 }
 
 // ----------------------------------------------------------------------------- k x k solve
-__global__ __launch_bounds__(NT) void k_lu_solve(const double2* __restrict__ M, int k,
-                                                 double2* __restrict__ C, int nrhs,
-                                                 double2* __restrict__ work, double* cond) {
+__device__ __forceinline__ void lu_solve_body(const double2* __restrict__ M, int k,
+                                              double2* __restrict__ C, int nrhs, double2* LU,
+                                              double* cond, int* piv) {
   const int t = threadIdx.x;
-  double2* LU = work;
-  double2* inv = work + k * k;
-  int* piv = (int*)(work + 2 * k * k);
-  __shared__ double s_n1;
   for (int i = t; i < k * k; i += NT) LU[i] = M[i];
-  __syncthreads();
-  // 1-norm of M
-  if (t == 0) {
-    double best = 0;
-    for (int j = 0; j < k; ++j) {
-      double s = 0;
-      for (int i = 0; i < k; ++i) s += cabs_(ld2(M, i + (long long)j * k));
-      best = fmax(best, s);
-    }
-    s_n1 = best;
+  // 1-norm of M: largest column sum
+  double n1 = 0;
+  for (int j = t; j < k; j += NT) {
+    double s = 0;
+    for (int i = 0; i < k; ++i) s += cabs_(ld2(M, i + (long long)j * k));
+    n1 = fmax(n1, s);
   }
-  const bool ok = lu_factor(LU, k, k, piv);
-  if (!ok) {
+  for (int o = 32; o > 0; o >>= 1) n1 = fmax(n1, __shfl_xor(n1, o, 64));
+  __syncthreads();
+  if (!lu_wave(LU, k, k, piv)) {
     if (t == 0) *cond = INFINITY;
     return;
   }
-  // inverse, one column per lane
-  for (int j = t; j < k; j += NT) {
-    for (int i = 0; i < k; ++i) inv[i + (long long)j * k] = make_double2(i == j ? 1.0 : 0.0, 0.0);
-    lu_solve_lane(LU, k, k, piv, inv + (long long)j * k, 1);
+  // 1-norm of M^{-1}, one column at a time
+  double ninv = 0;
+  for (int j = 0; j < k; ++j) {
+    WVec e{zd{t == j ? 1.0 : 0.0, 0.0}, zd{t + 64 == j ? 1.0 : 0.0, 0.0}};
+    lu_solve_wave(LU, k, k, piv, e);
+    const double s = wsum((t < k ? cabs_(e.a) : 0.0) + (t + 64 < k ? cabs_(e.b) : 0.0));
+    ninv = fmax(ninv, s);
   }
-  __syncthreads();
   if (t == 0) {
-    double best = 0;
-    for (int j = 0; j < k; ++j) {
-      double s = 0;
-      for (int i = 0; i < k; ++i) s += cabs_(ld2(inv, i + (long long)j * k));
-      best = fmax(best, s);
-    }
-    const double c = s_n1 * best;
+    const double c = n1 * ninv;
     *cond = isfinite(c) ? c : INFINITY;
   }
-  // Y = M^{-1} C, one column of C per lane (solve with the factors for accuracy)
-  for (int j = t; j < nrhs; j += NT) lu_solve_lane(LU, k, k, piv, C + (long long)j * k, 1);
+  // Y = M^{-1} C (solved with the factors for accuracy)
+  for (int j = 0; j < nrhs; ++j) {
+    double2* cj = C + (long long)j * k;
+    WVec b = wv_load(cj, k);
+    lu_solve_wave(LU, k, k, piv, b);
+    if (t < k) st2(cj, t, b.a);
+    if (t + 64 < k) st2(cj, t + 64, b.b);
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_lu_solve(const double2* __restrict__ M, int k,
+                                                 double2* __restrict__ C, int nrhs,
+                                                 double2* __restrict__ work, double* cond) {
+  __shared__ double2 sh[LDS_CAP];
+  __shared__ int piv[128];
+  if (k * k <= LDS_CAP) lu_solve_body(M, k, C, nrhs, sh, cond, piv);
+  else lu_solve_body(M, k, C, nrhs, work, cond, piv);
 }
 
 // ----------------------------------------------------------------------------- eigenproblem
-// Householder reduction of G (n x n, ld n) to upper Hessenberg form; Q (n x n) accumulates the
-// reflections so that G_in = Q G_out Q^H.
-__device__ void hessenberg(double2* G, double2* Q, int n) {
-  __shared__ double2 v[128];
-  __shared__ double s_vn2;
+// Householder reduction of G (n x n, ld n) to upper Hessenberg form.  Reflector j (acting on rows
+// and columns j+1..n-1) is kept below the subdiagonal of column j, its first entry in w0s[j] and
+// its factor in fs[j] (0: identity), for form_q; the caller zeroes that part afterwards.
+__device__ __forceinline__ void hessenberg(double2* G, int n, double2* v, double2* w0s, double* fs) {
   const int t = threadIdx.x;
-  for (int i = t; i < n * n; i += NT) Q[i] = make_double2((i % n) == (i / n) ? 1.0 : 0.0, 0.0);
-  __syncthreads();
   for (int j = 0; j + 2 < n; ++j) {
     const int len = n - j - 1;
     double p = 0;
     for (int i = t; i < len; i += NT) {
-      const zd x = ld2(G, (j + 1 + i) + (long long)j * n);
-      p += norm2(x);
-      v[i] = make_double2(x.re, x.im);
+      const double2 x = G[(j + 1 + i) + (long long)j * n];
+      p += x.x * x.x + x.y * x.y;
+      v[i] = x;
     }
     const double nx2 = wsum(p);
     __syncthreads();
-    if (nx2 == 0.0) continue;
+    zd w0{0.0, 0.0};
+    double f = 0.0;
+    if (nx2 != 0.0) reflector(ld2(v, 0), nx2, w0, f);
     if (t == 0) {
-      const zd x0{v[0].x, v[0].y};
-      const double ax0 = cabs_(x0), nx = sqrt(nx2);
-      const zd ph = ax0 > 0 ? zd{x0.re / ax0, x0.im / ax0} : zd{1.0, 0.0};
-      const zd alpha{-ph.re * nx, -ph.im * nx};
-      const zd v0 = x0 - alpha;
-      v[0] = make_double2(v0.re, v0.im);
-      s_vn2 = nx2 - ax0 * ax0 + norm2(v0);
+      w0s[j] = make_double2(w0.re, w0.im);
+      fs[j] = f;
     }
-    __syncthreads();
-    const double f = 2.0 / s_vn2;
+    if (nx2 == 0.0) continue;
     // left: rows j+1.., columns j..n-1
-    for (int c = j + t; c < n; c += NT) {
-      zd s{0, 0};
-      for (int i = 0; i < len; ++i) s = s + cmulc(zd{v[i].x, v[i].y}, ld2(G, (j + 1 + i) + (long long)c * n));
-      for (int i = 0; i < len; ++i) {
-        const zd vi{v[i].x, v[i].y};
-        st2(G, (j + 1 + i) + (long long)c * n, ld2(G, (j + 1 + i) + (long long)c * n) - f * (vi * s));
-      }
-    }
+    for (int c = j + t; c < n; c += NT) reflect_col(G + (long long)c * n + j + 1, v, w0, len, f);
     __syncthreads();
-    // right: all rows, columns j+1..
+    // right: all rows, columns j+1..n-1
     for (int r = t; r < n; r += NT) {
-      zd s{0, 0};
-      for (int i = 0; i < len; ++i) s = s + ld2(G, r + (long long)(j + 1 + i) * n) * zd{v[i].x, v[i].y};
-      for (int i = 0; i < len; ++i) {
-        const zd vc = conj(zd{v[i].x, v[i].y});
-        st2(G, r + (long long)(j + 1 + i) * n, ld2(G, r + (long long)(j + 1 + i) * n) - f * (s * vc));
-      }
-      zd q{0, 0};
-      for (int i = 0; i < len; ++i) q = q + ld2(Q, r + (long long)(j + 1 + i) * n) * zd{v[i].x, v[i].y};
-      for (int i = 0; i < len; ++i) {
-        const zd vc = conj(zd{v[i].x, v[i].y});
-        st2(Q, r + (long long)(j + 1 + i) * n, ld2(Q, r + (long long)(j + 1 + i) * n) - f * (q * vc));
-      }
+      double2* row = G + r + (long long)(j + 1) * n;
+      zd s = ld2(row, 0) * w0;
+#pragma unroll 4
+      for (int i = 1; i < len; ++i) s = s + ld2(row, (long long)i * n) * ld2(v, i);
+      s = f * s;
+      st2(row, 0, ld2(row, 0) - s * conj(w0));
+#pragma unroll 4
+      for (int i = 1; i < len; ++i)
+        st2(row, (long long)i * n, ld2(row, (long long)i * n) - s * conj(ld2(v, i)));
     }
     __syncthreads();
-    for (int i = j + 2 + t; i < n; i += NT) G[i + (long long)j * n] = make_double2(0.0, 0.0);
+    for (int i = 1 + t; i < len; i += NT) G[(j + 1 + i) + (long long)j * n] = v[i];
     __syncthreads();
   }
 }
 
-__device__ __forceinline__ double nrm1(zd a) { return fabs(a.re) + fabs(a.im); }
+// Q = H_0 H_1 ... H_{n-3} (so that G_in = Q G_out Q^H), accumulated backwards (Q <- H_j Q), one
+// column per lane: no lane reads another lane's column, so no barriers.
+__device__ __forceinline__ void form_q(const double2* G, int n, const double2* w0s,
+                                       const double* fs, double2* Q) {
+  const int t = threadIdx.x;
+  for (int c = t; c < n; c += NT) {
+    double2* qc = Q + (long long)c * n;
+    for (int r = 0; r < n; ++r) qc[r] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+    for (int j = min(n - 3, c - 1); j >= 0; --j) {
+      const double f = fs[j];
+      if (f == 0.0) continue;
+      const int len = n - j - 1;
+      const zd w0 = ld2(w0s, j);
+      const double2* w = G + (long long)j * n + j + 1;  // w[i], i >= 1
+      double2* col = qc + j + 1;
+      zd s = cmulc(w0, ld2(col, 0));
+#pragma unroll 4
+      for (int i = 1; i < len; ++i) s = s + cmulc(ld2(w, i), ld2(col, i));
+      s = f * s;
+      st2(col, 0, ld2(col, 0) - w0 * s);
+#pragma unroll 4
+      for (int i = 1; i < len; ++i) st2(col, i, ld2(col, i) - ld2(w, i) * s);
+    }
+  }
+}
 
-// Shifted QR iteration (single Wilkinson shift, Givens bulge chase) on an upper Hessenberg G,
-// reducing it to upper triangular Schur form T with G_in = Z T Z^H; Z must hold the
-// Hessenberg reduction's Q on entry.  Returns false if it did not converge.
-__device__ bool schur(double2* G, double2* Z, int n) {
-  __shared__ int s_l, s_hi;
-  __shared__ double s_c;
-  __shared__ double2 s_s;
-  __shared__ int s_done;
+// Shifted QR iteration (single Wilkinson shift, Givens bulge chase) on the upper Hessenberg G,
+// reducing it to upper triangular Schur form T with G_in = Z T Z^H; Z holds the Hessenberg
+// reduction's Q on entry.  With zlds the Schur vectors are rotated in the same phase as G (Z in
+// LDS); otherwise each sweep's rotations are recorded (rc, rs) and applied to the rows of Z after
+// the sweep.  Returns false if it did not converge.
+__device__ __forceinline__ bool schur(double2* G, double2* Z, int n, bool zlds, double* rc,
+                                      double2* rs) {
   const int t = threadIdx.x;
   const double eps = DBL_EPSILON;
-  int iter = 0, total = 0;
-  if (t == 0) {
-    s_hi = n - 1;
-    s_done = 0;
-  }
-  __syncthreads();
-  while (true) {
-    if (t == 0) {
-      int hi = s_hi;
-      int l = hi;
-      while (l > 0) {
-        const double s = nrm1(ld2(G, (l - 1) + (long long)(l - 1) * n)) + nrm1(ld2(G, l + (long long)l * n));
-        const double sub = nrm1(ld2(G, l + (long long)(l - 1) * n));
-        if (sub <= eps * (s > 0 ? s : 1e-300)) {
-          G[l + (long long)(l - 1) * n] = make_double2(0.0, 0.0);
-          break;
-        }
-        --l;
+  int hi = n - 1, iter = 0, total = 0;
+  while (hi > 0) {
+    // the largest l in 1..hi with a negligible subdiagonal entry G[l][l-1] (0 if none)
+    int l = 0;
+    for (int qb = 0; qb <= hi; qb += NT) {
+      const int q = qb + t;
+      bool neg = false;
+      if (q >= 1 && q <= hi) {
+        const double s = nrm1(ld2(G, (q - 1) + (long long)(q - 1) * n)) + nrm1(ld2(G, q + (long long)q * n));
+        neg = nrm1(ld2(G, q + (long long)(q - 1) * n)) <= eps * (s > 0 ? s : 1e-300);
       }
-      s_l = l;
+      const unsigned long long mask = __ballot(neg);
+      if (mask) l = qb + 63 - __clzll(mask);
     }
-    __syncthreads();
-    const int hi = s_hi, l = s_l;
-    if (hi <= 0) break;
+    if (l > 0 && t == 0) G[l + (long long)(l - 1) * n] = make_double2(0.0, 0.0);
     if (l == hi) {
-      if (t == 0) s_hi = hi - 1;
+      --hi;
       iter = 0;
-      __syncthreads();
       continue;
     }
     if (total > 60 * n) return false;
-    // shift
+    // shift (every lane computes it)
     zd mu;
     {
       const zd a = ld2(G, (hi - 1) + (long long)(hi - 1) * n), b = ld2(G, (hi - 1) + (long long)hi * n);
@@ -254,7 +354,6 @@ __device__ bool schur(double2* G, double2* Z, int n) {
       } else {
         const zd half{0.5 * (a.re - d.re), 0.5 * (a.im - d.im)};
         const zd disc2 = half * half + b * c;
-        // principal square root
         const double r = cabs_(disc2);
         double sr = sqrt(0.5 * (r + disc2.re)), si = sqrt(fmax(0.0, 0.5 * (r - disc2.re)));
         if (disc2.im < 0) si = -si;
@@ -265,103 +364,149 @@ __device__ bool schur(double2* G, double2* Z, int n) {
       }
     }
     for (int kk = l; kk < hi; ++kk) {
+      zd x, y;
+      if (kk == l) {
+        x = ld2(G, l + (long long)l * n) - mu;
+        y = ld2(G, (l + 1) + (long long)l * n);
+      } else {
+        x = ld2(G, kk + (long long)(kk - 1) * n);
+        y = ld2(G, (kk + 1) + (long long)(kk - 1) * n);
+      }
+      // c = |x| / rho, s = (x / |x|) conj(y) / rho, rho = sqrt(|x|^2 + |y|^2) (entries far from
+      // the range limits: no hypot-style scaling)
+      const double nx = x.re * x.re + x.im * x.im, ny = y.re * y.re + y.im * y.im;
+      double c;
+      zd s;
+      if (nx + ny == 0.0) {
+        c = 1.0;
+        s = zd{0.0, 0.0};
+      } else if (nx == 0.0) {
+        c = 0.0;
+        s = zd{1.0, 0.0};
+      } else {
+        const double ax = sqrt(nx);
+        const double irho = 1.0 / sqrt(nx + ny);
+        const double iax = 1.0 / ax;
+        c = ax * irho;
+        const zd ph{x.re * iax, x.im * iax};
+        s = ph * conj(y);
+        s = zd{s.re * irho, s.im * irho};
+      }
+      // one phase: rows kk, kk+1 (columns outside {kk, kk+1} from kk-1, or kk at the start of
+      // the sweep, where column l-1 holds zeros), columns kk, kk+1 (rows up to min(kk+2, hi)
+      // outside {kk, kk+1}), the 2 x 2 block where both act (row rotation first), the Schur
+      // vectors; the bulge below the subdiagonal in column kk-1 becomes exactly zero
+      const int j0 = kk == l ? kk : kk - 1;
+      const int rmax = kk + 2 < hi ? kk + 2 : hi;
+      for (int q = t; q < n; q += NT) {
+        if (q >= j0 && q != kk && q != kk + 1) {
+          const zd a = ld2(G, kk + (long long)q * n), b = ld2(G, (kk + 1) + (long long)q * n);
+          st2(G, kk + (long long)q * n, c * a + s * b);
+          st2(G, (kk + 1) + (long long)q * n, q == kk - 1 ? zd{0.0, 0.0} : c * b - conj(s) * a);
+        }
+        if (q <= rmax && q != kk && q != kk + 1) {
+          const zd a = ld2(G, q + (long long)kk * n), b = ld2(G, q + (long long)(kk + 1) * n);
+          st2(G, q + (long long)kk * n, c * a + conj(s) * b);
+          st2(G, q + (long long)(kk + 1) * n, c * b - s * a);
+        }
+        if (zlds) {
+          const zd a = ld2(Z, q + (long long)kk * n), b = ld2(Z, q + (long long)(kk + 1) * n);
+          st2(Z, q + (long long)kk * n, c * a + conj(s) * b);
+          st2(Z, q + (long long)(kk + 1) * n, c * b - s * a);
+        }
+      }
       if (t == 0) {
-        zd x, y;
-        if (kk == l) {
-          x = ld2(G, l + (long long)l * n) - mu;
-          y = ld2(G, (l + 1) + (long long)l * n);
-        } else {
-          x = ld2(G, kk + (long long)(kk - 1) * n);
-          y = ld2(G, (kk + 1) + (long long)(kk - 1) * n);
+        const zd a11 = ld2(G, kk + (long long)kk * n), a12 = ld2(G, kk + (long long)(kk + 1) * n);
+        const zd a21 = ld2(G, (kk + 1) + (long long)kk * n), a22 = ld2(G, (kk + 1) + (long long)(kk + 1) * n);
+        const zd b11 = c * a11 + s * a21, b12 = c * a12 + s * a22;
+        const zd b21 = c * a21 - conj(s) * a11, b22 = c * a22 - conj(s) * a12;
+        st2(G, kk + (long long)kk * n, c * b11 + conj(s) * b12);
+        st2(G, kk + (long long)(kk + 1) * n, c * b12 - s * b11);
+        st2(G, (kk + 1) + (long long)kk * n, c * b21 + conj(s) * b22);
+        st2(G, (kk + 1) + (long long)(kk + 1) * n, c * b22 - s * b21);
+        if (!zlds) {
+          rc[kk] = c;
+          rs[kk] = make_double2(s.re, s.im);
         }
-        // c = |x| / rho, s = (x / |x|) conj(y) / rho, rho = sqrt(|x|^2 + |y|^2): two square roots
-        // and two reciprocals that do not depend on each other (the entries are far from the
-        // range limits, so no hypot-style scaling is needed; this chain is the critical path of
-        // every rotation)
-        const double nx = x.re * x.re + x.im * x.im, ny = y.re * y.re + y.im * y.im;
-        double c;
-        zd s;
-        if (nx + ny == 0.0) {
-          c = 1.0;
-          s = zd{0.0, 0.0};
-        } else if (nx == 0.0) {
-          c = 0.0;
-          s = zd{1.0, 0.0};
-        } else {
-          const double ax = sqrt(nx);
-          const double irho = 1.0 / sqrt(nx + ny);
-          const double iax = 1.0 / ax;
-          c = ax * irho;
-          const zd ph{x.re * iax, x.im * iax};
-          s = ph * conj(y);
-          s = zd{s.re * irho, s.im * irho};
-        }
-        s_c = c;
-        s_s = make_double2(s.re, s.im);
       }
       __syncthreads();
-      const double c = s_c;
-      const zd s{s_s.x, s_s.y};
-      // rows kk, kk+1 over columns max(kk-1, 0).. n-1
-      for (int j = (kk > 0 ? kk - 1 : 0) + t; j < n; j += NT) {
-        const zd a = ld2(G, kk + (long long)j * n), b = ld2(G, (kk + 1) + (long long)j * n);
-        st2(G, kk + (long long)j * n, c * a + s * b);
-        st2(G, (kk + 1) + (long long)j * n, c * b - conj(s) * a);
-      }
-      __syncthreads();
-      // columns kk, kk+1 over rows 0 .. min(kk+2, hi); Z over all rows
-      const int rmax = (kk + 2 < hi ? kk + 2 : hi);
-      for (int i = t; i < n; i += NT) {
-        if (i <= rmax) {
-          const zd a = ld2(G, i + (long long)kk * n), b = ld2(G, i + (long long)(kk + 1) * n);
-          st2(G, i + (long long)kk * n, c * a + conj(s) * b);
-          st2(G, i + (long long)(kk + 1) * n, c * b - s * a);
+    }
+    if (!zlds) {
+      // the sweep's rotations on the rows of Z: column kk is final after rotation kk, column
+      // kk+1 carried to the next one; the untouched columns are loaded ahead in groups of 16
+      for (int r = t; r < n; r += NT) {
+        zd za = ld2(Z, r + (long long)l * n);
+        for (int kb = l; kb < hi; kb += 16) {
+          const int cnt = hi - kb < 16 ? hi - kb : 16;
+          zd zb[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u)
+            if (u < cnt) zb[u] = ld2(Z, r + (long long)(kb + 1 + u) * n);
+#pragma unroll
+          for (int u = 0; u < 16; ++u)
+            if (u < cnt) {
+              const double cc = rc[kb + u];
+              const zd ss = ld2(rs, kb + u);
+              st2(Z, r + (long long)(kb + u) * n, cc * za + conj(ss) * zb[u]);
+              za = cc * zb[u] - ss * za;
+            }
         }
-        const zd a = ld2(Z, i + (long long)kk * n), b = ld2(Z, i + (long long)(kk + 1) * n);
-        st2(Z, i + (long long)kk * n, c * a + conj(s) * b);
-        st2(Z, i + (long long)(kk + 1) * n, c * b - s * a);
+        st2(Z, r + (long long)hi * n, za);
       }
-      __syncthreads();
-      if (kk > l && t == 0) G[(kk + 1) + (long long)(kk - 1) * n] = make_double2(0.0, 0.0);
-      __syncthreads();
     }
     ++iter;
     ++total;
   }
+  __syncthreads();
   return true;
 }
 
-// Eigenvector of upper-triangular T for diagonal position q, in Schur coordinates (y, length n,
-// y_j = 0 for j > q), then g = Z y.  Runs in one lane.
-__device__ void tri_eigvec(const double2* T, const double2* Z, int n, int q, double tnorm,
-                           double2* y, double2* g) {
+// Eigenvector of the upper-triangular T (n x n) for diagonal position q, y with y_q = 1 and
+// y_j = 0 above q, solved backwards column by column across the wave; returns g = Z y normalised
+// in out[0..n) (column of ld-strided storage) and writes out[n] = 0 when pad.
+__device__ __forceinline__ void tri_eigvec(const double2* T, const double2* Z, int n, int q,
+                                           double tnorm, double2* out, bool pad) {
+  const int t = threadIdx.x;
   const zd th = ld2(T, q + (long long)q * n);
   const double small = fmax(DBL_EPSILON * tnorm, 1e-300);
-  for (int j = 0; j < n; ++j) y[j] = make_double2(j == q ? 1.0 : 0.0, 0.0);
-  for (int i = q - 1; i >= 0; --i) {
-    zd s{0, 0};
-    for (int j = i + 1; j <= q; ++j) s = s + ld2(T, i + (long long)j * n) * ld2(y, j);
-    zd d = ld2(T, i + (long long)i * n) - th;
+  WVec acc{zd{0.0, 0.0}, zd{0.0, 0.0}};
+  WVec y{zd{0.0, 0.0}, zd{0.0, 0.0}};
+  wv_set(y, q, zd{1.0, 0.0});
+  zd yj{1.0, 0.0};
+  for (int j = q; j >= 1; --j) {
+    if (t < j) acc.a = acc.a + ld2(T, t + (long long)j * n) * yj;
+    if (t + 64 < j) acc.b = acc.b + ld2(T, t + 64 + (long long)j * n) * yj;
+    zd d = ld2(T, (j - 1) + (long long)(j - 1) * n) - th;
     if (cabs_(d) < small) d = zd{small, 0.0};
-    st2(y, i, -cdiv(s, d));
+    yj = -cdiv(wv_get(acc, j - 1), d);
+    wv_set(y, j - 1, yj);
   }
+  zd g[2];
   double nn = 0;
-  for (int r = 0; r < n; ++r) {
-    zd s{0, 0};
-    for (int j = 0; j <= q; ++j) s = s + ld2(Z, r + (long long)j * n) * ld2(y, j);
-    st2(g, r, s);
-    nn += norm2(s);
+#pragma unroll
+  for (int slot = 0; slot < 2; ++slot) {
+    const int r = slot * 64 + t;
+    zd s{0.0, 0.0};
+    if (slot * 64 < n)
+      for (int j = 0; j <= q; ++j) {
+        const zd yv = wv_get(y, j);
+        if (r < n) s = s + ld2(Z, r + (long long)j * n) * yv;
+      }
+    g[slot] = s;
+    if (r < n) nn += norm2(s);
   }
-  nn = 1.0 / sqrt(nn);
-  for (int r = 0; r < n; ++r) {
-    const zd s = ld2(g, r);
-    st2(g, r, zd{s.re * nn, s.im * nn});
+  nn = 1.0 / sqrt(wsum(nn));
+#pragma unroll
+  for (int slot = 0; slot < 2; ++slot) {
+    const int r = slot * 64 + t;
+    if (r < n) st2(out, r, zd{g[slot].re * nn, g[slot].im * nn});
   }
+  if (pad && t == 0) out[n] = make_double2(0.0, 0.0);
 }
 
-// orthonormalise column q of P (length len, ld ldp) against columns 0..q-1 (Gram-Schmidt twice);
-// returns the norm before normalisation (all lanes)
-__device__ double orth_column(double2* P, int ldp, int len, int q, double2* h) {
+// orthonormalise column q of P (len rows, ld ldp) against columns 0..q-1 (Gram-Schmidt twice);
+// h: scratch of q entries
+__device__ __forceinline__ void orth_column(double2* P, int ldp, int len, int q, double2* h) {
   const int t = threadIdx.x;
   for (int pass = 0; pass < 2; ++pass) {
     for (int i = t; i < q; i += NT) {
@@ -386,146 +531,86 @@ __device__ double orth_column(double2* P, int ldp, int len, int q, double2* h) {
     st2(P, r + (long long)q * ldp, zd{w.re * f, w.im * f});
   }
   __syncthreads();
-  return nn;
 }
 
-__global__ __launch_bounds__(NT) void k_cycle(CycleArgs a) {
-  const int t = threadIdx.x;
-  const int m = a.m, m1 = m + 1, k = a.k;
-  double2* w = a.work;
-  double2* QR = w;                 // (m+1) x m
-  double2* gv = QR + m1 * m;       // m+1
-  double2* rho = gv + m1;          // m+1
-  double2* G = rho + m1;           // m x m
-  double2* Z = G + m * m;          // m x m
-  double2* Bm = Z + m * m;         // m x m
-  double2* f = Bm + m * m;         // m
-  double2* Y = f + m;              // m x m eigenvector scratch
-  double2* Gv = Y + m * m;         // m x m selected eigenvectors
-  double2* T1 = Gv + m * m;        // (m+1) x m
-  double2* hh = T1 + m1 * m;       // m+1
-  int* piv = (int*)(hh + m1);      // m ints
-  __shared__ int order[128];
-  __shared__ int s_kout;
-  __shared__ int s_conv;
+// ----------------------------------------------------------------------------- cycle phases
+// least squares min || c - Hbar d || (QR: m1 x m area, g: m1 entries); rho = c - Hbar d into rho
+// (LDS), and cnew in mode 3; returns ||rho|| in every lane
+__device__ __forceinline__ double phase_ls(const CycleArgs& a, double2* QR, double2* g,
+                                           double2* v, double2* rho) {
+  const int t = threadIdx.x, m = a.m, m1 = m + 1;
   const double2* H = a.Hbar;
-
-  if (a.mode == 0 || a.mode == 1 || a.mode == 3) {
-    // ---- least squares min || c - Hbar d || by Householder QR
-    for (int i = t; i < m1 * m; i += NT) QR[i] = H[i];
-    for (int i = t; i < m1; i += NT) gv[i] = a.c[i];
-    __syncthreads();
-    __shared__ double2 v[129];
-    __shared__ double s_vn2;
+  for (int i = t; i < m1 * m; i += NT) QR[i] = H[i];
+  for (int i = t; i < m1; i += NT) g[i] = a.c[i];
+  __syncthreads();
+  ls_qr(QR, g, m, v);
+  const WVec d = back_subst(QR, m1, g, m);
+  if (t < m) st2(a.d, t, d.a);
+  if (t + 64 < m) st2(a.d, t + 64, d.b);
+  double p = 0;
+  for (int rb = 0; rb < m1; rb += NT) {
+    const int r = rb + t;
+    zd s = r < m1 ? ld2(a.c, r) : zd{0.0, 0.0};
     for (int j = 0; j < m; ++j) {
-      const int len = m1 - j;
-      double p = 0;
-      for (int i = t; i < len; i += NT) {
-        const zd x = ld2(QR, (j + i) + (long long)j * m1);
-        p += norm2(x);
-        v[i] = make_double2(x.re, x.im);
-      }
-      const double nx2 = wsum(p);
-      __syncthreads();
-      if (nx2 == 0.0) continue;
-      if (t == 0) {
-        const zd x0{v[0].x, v[0].y};
-        const double ax0 = cabs_(x0), nx = sqrt(nx2);
-        const zd ph = ax0 > 0 ? zd{x0.re / ax0, x0.im / ax0} : zd{1.0, 0.0};
-        const zd alpha{-ph.re * nx, -ph.im * nx};
-        const zd v0 = x0 - alpha;
-        v[0] = make_double2(v0.re, v0.im);
-        s_vn2 = nx2 - ax0 * ax0 + norm2(v0);
-      }
-      __syncthreads();
-      const double fct = 2.0 / s_vn2;
-      for (int c = j + t; c <= m; c += NT) {  // columns j..m-1 of QR, plus gv as column m
-        double2* col = (c < m) ? QR + (long long)c * m1 : gv;
-        zd s{0, 0};
-        for (int i = 0; i < len; ++i) s = s + cmulc(zd{v[i].x, v[i].y}, ld2(col, j + i));
-        for (int i = 0; i < len; ++i) st2(col, j + i, ld2(col, j + i) - fct * (zd{v[i].x, v[i].y} * s));
-      }
-      __syncthreads();
+      const zd dj = wv_get(d, j);
+      if (r < m1) s = s - ld2(H, r + (long long)j * m1) * dj;
     }
-    // back substitution R d = gv[0..m-1]
-    if (t == 0) {
-      for (int i = m - 1; i >= 0; --i) {
-        zd s = ld2(gv, i);
-        for (int j = i + 1; j < m; ++j) s = s - ld2(QR, i + (long long)j * m1) * ld2(a.d, j);
-        const zd rii = ld2(QR, i + (long long)i * m1);
-        st2(a.d, i, (rii.re != 0.0 || rii.im != 0.0) ? cdiv(s, rii) : zd{0.0, 0.0});
-      }
-    }
-    __syncthreads();
-    // rho = c - Hbar d with the original Hbar
-    double p = 0;
-    for (int r = t; r < m1; r += NT) {
-      zd s = ld2(a.c, r);
-      for (int j = 0; j < m; ++j) s = s - ld2(H, r + (long long)j * m1) * ld2(a.d, j);
+    if (r < m1) {
       st2(rho, r, s);
       if (a.mode == 3) st2(a.cnew, r, s);
       p += norm2(s);
     }
-    const double rn = sqrt(wsum(p));
-    if (t == 0) {
-      a.info[0] = rn;
-      a.info[2] = (rn <= a.tol_abs) ? 1.0 : 0.0;
-      s_conv = (rn <= a.tol_abs) ? 1 : 0;
+  }
+  __syncthreads();
+  return sqrt(wsum(p));
+}
+
+// harmonic Ritz matrix G = H_m + |h_{m+1,m}|^2 f e_m^T with H_m^H f = e_m (Bm: m x m area that
+// G then overwrites), or the Ritz matrix G = H_m (mode 2)
+__device__ __forceinline__ void phase_g(const CycleArgs& a, double2* G, int* piv) {
+  const int t = threadIdx.x, m = a.m, m1 = m + 1;
+  const double2* H = a.Hbar;
+  WVec f{zd{0.0, 0.0}, zd{0.0, 0.0}};
+  if (a.mode != 2) {
+    for (int i = t; i < m * m; i += NT) {
+      const int r = i % m, c = i / m;
+      st2(G, i, conj(ld2(H, c + (long long)r * m1)));
     }
     __syncthreads();
-    if ((a.mode == 0 && s_conv) || a.mode == 3) return;
+    lu_wave(G, m, m, piv);
+    wv_set(f, m - 1, zd{1.0, 0.0});
+    lu_solve_wave(G, m, m, piv, f);
+    __syncthreads();
   }
-
-  // ---- eigenproblem matrix G (m x m)
   for (int i = t; i < m * m; i += NT) {
     const int r = i % m, c = i / m;
     G[i] = H[r + (long long)c * m1];
   }
   __syncthreads();
   if (a.mode != 2) {
-    // harmonic Ritz: G = H_m + |h_{m+1,m}|^2 f e_m^T with H_m^H f = e_m
-    for (int i = t; i < m * m; i += NT) {
-      const int r = i % m, c = i / m;
-      const zd hv = ld2(H, c + (long long)r * m1);
-      st2(Bm, i, conj(hv));
-    }
-    __syncthreads();
-    lu_factor(Bm, m, m, piv);
-    __syncthreads();
-    if (t == 0) {
-      for (int i = 0; i < m; ++i) f[i] = make_double2(i == m - 1 ? 1.0 : 0.0, 0.0);
-      lu_solve_lane(Bm, m, m, piv, f, 1);
-    }
-    __syncthreads();
     const double h2 = norm2(ld2(H, m + (long long)(m - 1) * m1));
-    for (int r = t; r < m; r += NT) st2(G, r + (long long)(m - 1) * m, ld2(G, r + (long long)(m - 1) * m) + h2 * ld2(f, r));
+    if (t < m) st2(G, t + (long long)(m - 1) * m, ld2(G, t + (long long)(m - 1) * m) + h2 * f.a);
+    if (t + 64 < m)
+      st2(G, t + 64 + (long long)(m - 1) * m, ld2(G, t + 64 + (long long)(m - 1) * m) + h2 * f.b);
     __syncthreads();
   }
-  // The Hessenberg reduction and the QR iteration touch the whole matrix after every Givens
-  // rotation: for m <= 64 they run on a copy in LDS (two 64 x 64 complex matrices, 128 KiB)
-  // instead of through the caches.
-  constexpr int LDS_M = 64;
-  __shared__ double2 sGZ[2 * LDS_M * LDS_M];
-  const bool in_lds = m <= LDS_M;
-  double2* Gw = in_lds ? sGZ : G;
-  double2* Zw = in_lds ? sGZ + m * m : Z;
-  if (in_lds) {
-    for (int i = t; i < m * m; i += NT) Gw[i] = G[i];
-    __syncthreads();
-  }
-  hessenberg(Gw, Zw, m);
+}
+
+// Schur form of G (m x m) with Schur vectors Z; sorted eigenvalues into a.theta and order[];
+// returns the number of vectors to keep (in every lane) and the largest |entry| of T in tn
+__device__ __forceinline__ int phase_eig(const CycleArgs& a, double2* G, double2* Z, bool zlds,
+                                         double2* v, double2* w0s, double* fs, int* order,
+                                         int* s_kout, double& tn) {
+  const int t = threadIdx.x, m = a.m, k = a.k;
+  hessenberg(G, m, v, w0s, fs);
+  form_q(G, m, w0s, fs, Z);
   __syncthreads();
-  const bool ok = schur(Gw, Zw, m);
+  for (int c = t; c < m; c += NT)
+    for (int r = c + 2; r < m; ++r) G[r + (long long)c * m] = make_double2(0.0, 0.0);
   __syncthreads();
-  if (in_lds) {
-    for (int i = t; i < m * m; i += NT) {
-      G[i] = Gw[i];
-      Z[i] = Zw[i];
-    }
-    __syncthreads();
-  }
+  const bool ok = schur(G, Z, m, zlds, fs, w0s);
   if (t == 0) a.info[4] = ok ? 0.0 : 1.0;
-  // ---- sort eigenvalues: |theta| ascending (harmonic) or Re descending (Ritz)
+  // sort: |theta| ascending (harmonic) or Re descending (Ritz), ties by (Re, Im, index)
   for (int i = t; i < m; i += NT) {
     const zd ti = ld2(G, i + (long long)i * m);
     int rank = 0;
@@ -552,59 +637,122 @@ __global__ __launch_bounds__(NT) void k_cycle(CycleArgs a) {
       const double sc = cabs_(x);
       if (fabs(x.im) > 1e-3 * sc && cabs_(x - conj(y)) <= 1e-3 * sc) kout = k - 1;
     }
-    s_kout = kout;
+    *s_kout = kout;
     a.info[1] = kout;
   }
+  double mx = 0;
+  for (int i = t; i < m * m; i += NT) mx = fmax(mx, cabs_(ld2(G, i)));
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  tn = mx;
   __syncthreads();
-  const int ks = s_kout;
-  // ---- eigenvectors of the selected values
-  double tn = 0;
-  for (int i = t; i < m * m; i += NT) tn = fmax(tn, cabs_(ld2(G, i)));
-  for (int o = 32; o > 0; o >>= 1) tn = fmax(tn, __shfl_xor(tn, o, 64));
-  for (int q = t; q < ks; q += NT) tri_eigvec(G, Z, m, order[q], tn, Y + (long long)q * m, Gv + (long long)q * m);
-  __syncthreads();
-  // ---- P: orthonormal basis of the selected vectors padded with a zero row, then the extra column
-  for (int i = t; i < m1 * (k + 1); i += NT) a.P[i] = make_double2(0.0, 0.0);
-  __syncthreads();
-  for (int i = t; i < m * ks; i += NT) {
-    const int r = i % m, c = i / m;
-    a.P[r + (long long)c * m1] = Gv[r + (long long)c * m];
-  }
-  __syncthreads();
-  for (int q = 0; q < ks; ++q) orth_column(a.P, m1, m1, q, hh);
+  return *s_kout;
+}
+
+// P: orthonormal basis of the ks selected eigenvectors (already in P's columns) padded with a zero
+// row, then the extra column (rho in mode 0, e_{m+1} in mode 2); then Hnew = P^H Hbar P_k and
+// cnew = P^H rho (mode 0).  P: (m+1) x (k+1) area, T1: (m+1) x k area.
+__device__ __forceinline__ void phase_restart(const CycleArgs& a, double2* P, double2* T1, int ks,
+                                              const double2* rho, double2* h) {
+  const int t = threadIdx.x, m = a.m, m1 = m + 1, k = a.k;
+  const double2* H = a.Hbar;
+  for (int q = 0; q < ks; ++q) orth_column(P, m1, m1, q, h);
   if (a.mode == 2) {
-    // Ritz residual of the first (rightmost) pair: |h_{m+1,m}| |e_m^T g|
     if (t == 0) {
       const double hm = cabs_(ld2(H, m + (long long)(m - 1) * m1));
-      a.info[3] = hm * cabs_(ld2(a.P, (m - 1)));
-      a.P[m + (long long)k * m1] = make_double2(1.0, 0.0);
+      a.info[3] = hm * cabs_(ld2(P, m - 1));
+      P[m + (long long)k * m1] = make_double2(1.0, 0.0);
     }
     __syncthreads();
   } else if (a.mode == 0) {
-    for (int r = t; r < m1; r += NT) a.P[r + (long long)k * m1] = rho[r];
+    for (int r = t; r < m1; r += NT) P[r + (long long)k * m1] = rho[r];
     __syncthreads();
-    orth_column(a.P, m1, m1, k, hh);
+    orth_column(P, m1, m1, k, h);
   }
   if (a.mode == 1) return;
-  // ---- Hnew = P^H Hbar P_k  ((k+1) x k), cnew = P^H rho
   for (int i = t; i < m1 * k; i += NT) {
     const int r = i % m1, c = i / m1;
     zd s{0, 0};
-    for (int j = 0; j < m; ++j) s = s + ld2(H, r + (long long)j * m1) * ld2(a.P, j + (long long)c * m1);
+    for (int j = 0; j < m; ++j) s = s + ld2(H, r + (long long)j * m1) * ld2(P, j + (long long)c * m1);
     st2(T1, r + (long long)c * m1, s);
   }
   __syncthreads();
   for (int i = t; i < (k + 1) * k; i += NT) {
     const int r = i % (k + 1), c = i / (k + 1);
     zd s{0, 0};
-    for (int j = 0; j < m1; ++j) s = s + cmulc(ld2(a.P, j + (long long)r * m1), ld2(T1, j + (long long)c * m1));
+    for (int j = 0; j < m1; ++j) s = s + cmulc(ld2(P, j + (long long)r * m1), ld2(T1, j + (long long)c * m1));
     st2(a.Hnew, r + (long long)c * m1, s);
   }
   for (int r = t; r < m1; r += NT) {
     zd s{0, 0};
     if (r <= k && a.mode == 0)
-      for (int j = 0; j < m1; ++j) s = s + cmulc(ld2(a.P, j + (long long)r * m1), ld2(rho, j));
+      for (int j = 0; j < m1; ++j) s = s + cmulc(ld2(P, j + (long long)r * m1), ld2(rho, j));
     st2(a.cnew, r, s);
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_cycle(CycleArgs a) {
+  const int t = threadIdx.x;
+  const int m = a.m, m1 = m + 1, k = a.k;
+  // global scratch for what does not fit in LDS
+  double2* w = a.work;
+  double2* wA = w;                 // (m+1) x m
+  double2* wG = wA + m1 * m;       // m x m
+  double2* wZ = wG + m * m;        // m x m
+  double2* wT1 = wZ + m * m;       // (m+1) x m
+  __shared__ double2 sh[LDS_CAP];
+  __shared__ double2 v[129];
+  __shared__ double2 gr[129];      // c transformed by the least squares, then rho
+  __shared__ double2 w0s[128];     // Hessenberg reflectors, then the sweep's rotations
+  __shared__ double fs[128];
+  __shared__ int piv[128];
+  __shared__ int order[128];
+  __shared__ int s_kout;
+
+  if (a.mode == 0 || a.mode == 1 || a.mode == 3) {
+    const double rn = m1 * m <= LDS_CAP ? phase_ls(a, sh, gr, v, gr) : phase_ls(a, wA, gr, v, gr);
+    const bool conv = rn <= a.tol_abs;
+    if (t == 0) {
+      a.info[0] = rn;
+      a.info[2] = conv ? 1.0 : 0.0;
+    }
+    if ((a.mode == 0 && conv) || a.mode == 3) return;
+  }
+
+  // ---- eigenproblem: G (and Z) in LDS where they fit
+  int ks;
+  double tn;
+  const bool g_lds = m * m <= LDS_CAP, z_lds = 2 * m * m <= LDS_CAP;
+  if (z_lds) {
+    phase_g(a, sh, piv);
+    ks = phase_eig(a, sh, sh + m * m, true, v, w0s, fs, order, &s_kout, tn);
+  } else if (g_lds) {
+    phase_g(a, sh, piv);
+    ks = phase_eig(a, sh, wZ, false, v, w0s, fs, order, &s_kout, tn);
+  } else {
+    phase_g(a, wG, piv);
+    ks = phase_eig(a, wG, wZ, false, v, w0s, fs, order, &s_kout, tn);
+  }
+  // ---- eigenvectors of the selected values into the columns of P (padded with a zero row)
+  for (int i = t; i < m1 * (k + 1); i += NT) a.P[i] = make_double2(0.0, 0.0);
+  __syncthreads();
+  for (int q = 0; q < ks; ++q) {
+    const int col = order[q];
+    if (z_lds) tri_eigvec(sh, sh + m * m, m, col, tn, a.P + (long long)q * m1, true);
+    else if (g_lds) tri_eigvec(sh, wZ, m, col, tn, a.P + (long long)q * m1, true);
+    else tri_eigvec(wG, wZ, m, col, tn, a.P + (long long)q * m1, true);
+  }
+  __syncthreads();
+  // ---- restart basis and Hnew, in LDS where P and Hbar P fit
+  if (m1 * (2 * k + 1) <= LDS_CAP) {
+    double2* P = sh;
+    double2* T1 = sh + m1 * (k + 1);
+    for (int i = t; i < m1 * (k + 1); i += NT) P[i] = a.P[i];
+    __syncthreads();
+    phase_restart(a, P, T1, ks, gr, v);
+    __syncthreads();
+    for (int i = t; i < m1 * (k + 1); i += NT) a.P[i] = P[i];
+  } else {
+    phase_restart(a, a.P, wT1, ks, gr, v);
   }
 }
 
@@ -625,11 +773,12 @@ __global__ void k_trsolve(const double2* __restrict__ R, int ldr, int n, double2
 
 size_t dense_cycle_work(int m) {
   const size_t m1 = m + 1;
-  return m1 * m * 2 + 3 * m1 + 6 * size_t(m) * m + m + m1 + (size_t(m) + 3) / 4 + 8;
+  return 2 * m1 * m + 2 * size_t(m) * m + 8;
 }
 
 void dense_lu_solve(hipStream_t s, const double2* M, int k, double2* C, int nrhs, double2* work,
                     double* cond) {
+  DBQ_CHECK(k >= 1 && k <= 128, "dense_lu_solve: k must be in 1..128");
   hipLaunchKernelGGL(k_lu_solve, dim3(1), dim3(NT), 0, s, M, k, C, nrhs, work, cond);
   DBQ_HIP(hipGetLastError());
 }

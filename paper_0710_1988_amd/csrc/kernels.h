@@ -189,6 +189,8 @@ void bicg_aux_f32(hipStream_t s, int op, const VecSet& vs32, const VecSet& vs64,
                   const double2* r64, float4* r, float4* rhat, float4* p, float4* v, float4* x32,
                   RhsScal* sc, double* partials);
 // x64 += widen(x32), x32 = 0 for rhs with sel != 0
+// Y[:, j] = 0 (k entries) for every rhs j < nrhs whose sel is clear (sc points at the first)
+void mask_unselected_f64(hipStream_t s, double2* Y, int k, int nrhs, const RhsScal* sc);
 void bicg_xacc(hipStream_t s, const VecSet& vs32, const VecSet& vs64, double2* x64, float4* x32,
                const RhsScal* sc);
 
@@ -205,6 +207,18 @@ size_t gram_work_elems(long long n, int na, int nb);
 // -1 subtracts (Y_j -= sum ...).  Y_j at Y + j*ldy.
 void combine_f64(hipStream_t s, const double2* A, long long lda, int na, const double2* M, int ldm,
                  double2* Y, long long ldy, int nb, long long n, long long V, int g5, int beta);
+// C = A^H [B_0, B_1] (na x 2) for the Arnoldi step (no gamma5)
+void gram2_f64(hipStream_t s, const double2* A, long long lda, int na, const double2* B,
+               long long ldb, long long n, double2* C, double* work, size_t work_elems);
+// Arnoldi step with delayed reorthogonalisation: from G = [Q, z_j]^H [z_j, w] ((j+1) x 2, or
+// (j+1) x 1 with last) correct Hessenberg column j-1, write column j (rows 0..j) and the
+// coefficients m0, m1 (j+1 each) and c1 of the second sweep; start = 1 for a vector that is
+// already orthonormal.  j <= 128.
+void arn_coef_f64(hipStream_t s, const double2* G, int j, int start, int last, double2* H, int ldh,
+                  double2* m0, double2* m1, double* c1);
+// In place: col j = sum_{i<=j} Q_i m0[i]; if m1, col j+1 = c1 col(j+1) - sum_{i<=j} Q_i m1[i]
+void arn_combine_f64(hipStream_t s, double2* Q, long long ld, int j, long long n, const double2* m0,
+                     const double2* m1, const double* c1);
 // y = alpha * x (complex scalar from device memory, optional reciprocal of a real norm)
 void scale_f64(hipStream_t s, const double2* x, double2* y, long long n, const double* inv_norm_of);
 // ||x||^2 per vector (count vectors of n elements, stride ld) into out[count] (device)

@@ -781,6 +781,18 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
   // ---- deflation: (U^H A V) y = U^H r0, x0 += V y with U = gamma5 V (roles swapped for A^H)
   bool any_defl = false;
   double* dcond = ws.get<double>(MAXLAT);
+  // DBQ_REPROJECT=1 (mixed precision only): the same projection is applied again to the FP64
+  // residual at every reliable update, with (U^H A V)^{-1} and W = A V kept from the start
+  struct Reproj {
+    const double2 *left = nullptr, *right = nullptr, *W = nullptr;
+    double2 *Minv = nullptr, *C = nullptr, *Y = nullptr;
+    double* gwork = nullptr;
+    size_t gw = 0;
+  };
+  std::vector<Reproj> rp(nops);
+  bool reproject = false;
+  if (mixed)
+    if (const char* e = std::getenv("DBQ_REPROJECT")) reproject = std::atoi(e) != 0;
   for (int i = 0; i < nops; ++i) {
     const int k = kk[i];
     if (k == 0) continue;
@@ -806,6 +818,23 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
     gram_f64(s, Vp, n, k, W, n, k, n, V, dagger ? 0 : 1, M, gwork, gw);
     gram_f64(s, Vp, n, k, r64 + o, n, nrhs[i], n, V, dagger ? 0 : 1, Cm, gwork, gw);
     double2* lw = ws.get<double2>(2 * k * k + k);
+    if (reproject) {
+      Reproj& R = rp[i];
+      R.left = Vp;
+      R.right = Vp;
+      R.W = W;
+      R.Minv = ws.get<double2>(size_t(k) * k);
+      R.C = ws.get<double2>(size_t(k) * nrhs[i]);
+      R.Y = ws.get<double2>(size_t(k) * nrhs[i]);
+      R.gwork = gwork;
+      R.gw = gw;
+      std::vector<double2> id(size_t(k) * k, make_double2(0.0, 0.0));
+      for (int q = 0; q < k; ++q) id[q + size_t(q) * k] = make_double2(1.0, 0.0);
+      DBQ_HIP(hipMemcpyAsync(R.Minv, id.data(), sizeof(double2) * id.size(),
+                             hipMemcpyHostToDevice, s));
+      DBQ_HIP(hipStreamSynchronize(s));
+      dense_lu_solve(s, M, k, R.Minv, k, lw, dcond + i);
+    }
     dense_lu_solve(s, M, k, Cm, nrhs[i], lw, dcond + i);
     combine_f64(s, Vp, n, k, Cm, k, x64 + o, n, nrhs[i], n, V, dagger ? 1 : 0, 1);
     DBQ_HIP(hipMemcpyAsync(hcond + i, dcond + i, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -953,6 +982,20 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
     auto relup_dev = [&]() {
       bicg_xacc(s, vs32, vs64, x64, x32, sc);
       run_dslash(c, false, bres_dec, dagger, EPI_RESID, sc, partials);
+      if (reproject)
+        for (int i = 0; i < nops; ++i) {
+          const Reproj& R = rp[i];
+          if (!R.W) continue;
+          const int k = kk[i];
+          const long long n = op[i].n(), V = op[i].sites(), o = off64[base[i]];
+          // y = (U^H A V)^{-1} U^H r for the rhs that continue (sel), x += V y, r -= W y
+          gram_f64(s, R.left, n, k, r64 + o, n, nrhs[i], n, V, dagger ? 0 : 1, R.C, R.gwork,
+                   R.gw);
+          combine_f64(s, R.Minv, k, k, R.C, k, R.Y, k, nrhs[i], k, 1, 0, 0);
+          mask_unselected_f64(s, R.Y, k, nrhs[i], sc + base[i]);
+          combine_f64(s, R.right, n, k, R.Y, k, x64 + o, n, nrhs[i], n, V, dagger ? 1 : 0, 1);
+          combine_f64(s, R.W, n, k, R.Y, k, r64 + o, n, nrhs[i], n, V, 0, -1);
+        }
       bicg_aux_f32(s, AX_REPLACE, vs32, vs64, r64, r32, rhat32, p32, v32, x32, sc, partials);
     };
     auto block = [&](int n) {
@@ -1270,10 +1313,13 @@ struct Arnoldi {
   double2 *Vb, *Vb2;  // (m+1) x n bases
   double2 *Hbar, *Hnew, *cv, *cnew;
   double2 *d, *P, *theta, *h1, *h2, *dwork;
-  double *info, *nrm, *gwork, *nwork;
+  double2 *G2, *cf0, *cf1;  // Gram of the step, coefficients of its combination sweep
+  double *info, *nrm, *gwork, *nwork, *c1;
   size_t gw, nw;
   int dagger = 0;
   int64_t mv = 0;
+  // DBQ_ARNOLDI_CGS2=1: classical Gram-Schmidt twice in four sweeps per step (for comparison)
+  bool cgs2 = false;
 
   Arnoldi(dbq_ctx* ctx, WsScope& ws, const Op* o, int mm, int k) : c(ctx), op(o), m(mm) {
     n = o->n();
@@ -1293,7 +1339,13 @@ struct Arnoldi {
     dwork = ws.get<double2>(dense_cycle_work(m));
     info = ws.get<double>(8);
     nrm = ws.get<double>(4);
-    gw = gram_work_elems(n, m1, 1);
+    G2 = ws.get<double2>(2 * size_t(m1));
+    cf0 = ws.get<double2>(m1);
+    cf1 = ws.get<double2>(m1);
+    c1 = ws.get<double>(1);
+    const char* e = std::getenv("DBQ_ARNOLDI_CGS2");
+    cgs2 = e && std::atoi(e) != 0;
+    gw = gram_work_elems(n, m1, 2);
     gwork = ws.get<double>(gw);
     nw = norm_work(n, 1);
     nwork = ws.get<double>(nw);
@@ -1302,8 +1354,30 @@ struct Arnoldi {
 
   double2* col(int j) { return Vb + size_t(j) * n; }
 
-  // extend the Arnoldi relation from column j0 to m with CGS2
+  // extend the Arnoldi relation from column j0 to m; columns 0..j0 are orthonormal on entry and
+  // 0..m on exit
   void extend(int j0) {
+    if (cgs2) {
+      extend_cgs2(j0);
+      return;
+    }
+    hipStream_t s = c->stream;
+    for (int j = j0; j < m; ++j) {
+      // w = A z_j, then one Gram sweep and one combination sweep over columns 0..j
+      const DsBatch b = make_batch({DsSpec{op, false, col(j), col(j + 1), nullptr, 1, 0}});
+      run_dslash(c, false, b, dagger, EPI_NONE, nullptr, nullptr);
+      ++mv;
+      gram2_f64(s, Vb, n, j + 1, col(j), n, n, G2, gwork, gw);
+      arn_coef_f64(s, G2, j, j == j0 ? 1 : 0, 0, Hbar, m + 1, cf0, cf1, c1);
+      arn_combine_f64(s, Vb, n, j, n, cf0, cf1, c1);
+    }
+    // the second pass of the last vector
+    gram_f64(s, Vb, n, m + 1, col(m), n, 1, n, V, 0, G2, gwork, gw);
+    arn_coef_f64(s, G2, m, 0, 1, Hbar, m + 1, cf0, nullptr, c1);
+    arn_combine_f64(s, Vb, n, m, n, cf0, nullptr, c1);
+  }
+
+  void extend_cgs2(int j0) {
     hipStream_t s = c->stream;
     for (int j = j0; j < m; ++j) {
       const DsBatch b = make_batch({DsSpec{op, false, col(j), col(j + 1), nullptr, 1, 0}});
