@@ -19,6 +19,34 @@ __device__ __forceinline__ double g5sign(long long e, long long V, int g5) {
   return (g5 && ((e / (6 * V)) & 1)) ? -1.0 : 1.0;
 }
 
+// Sums of NV (32 or 64) values over the 64 lanes of a wave, scattered: on return lane l holds the
+// wave's sum of value l % NV.  Each step sends half of the remaining values to the lane whose
+// index differs in one bit and keeps the half that bit selects (63 shuffles, against 6 NV for NV
+// separate butterfly sums); the order of the additions is fixed.
+template <int HALF, int NV>
+__device__ __forceinline__ void step(double (&v)[NV], int lane) {
+  const bool up = (lane & HALF) != 0;
+#pragma unroll
+  for (int i = 0; i < HALF; ++i) {
+    const double lo = v[i], hi = v[i + HALF];
+    const double send = up ? lo : hi;
+    v[i] = (up ? hi : lo) + __shfl_xor(send, HALF, 64);
+  }
+  if constexpr (HALF > 1) step<HALF / 2>(v, lane);
+}
+
+template <int NV>
+__device__ __forceinline__ double wave_sum_scatter(double (&v)[NV]) {
+  static_assert(NV == 32 || NV == 64, "32 or 64 values");
+  const int lane = threadIdx.x & 63;
+  if (NV == 32) {
+#pragma unroll
+    for (int i = 0; i < 32; ++i) v[i] += __shfl_xor(v[i], 32, 64);
+  }
+  step<NV / 2>(v, lane);
+  return v[0];
+}
+
 // Each block: one chunk of G_CHUNK rows x one (TA x TB) tile of (i, j) pairs.  Tile index is
 // the fastest-varying logical block index so that all tiles of a chunk run on one XCD and
 // re-read the chunk from its L2.
@@ -62,15 +90,15 @@ __global__ __launch_bounds__(G_BS) void k_gram(const double2* __restrict__ A, lo
   constexpr int NV = TA * TB * 2, NW = G_BS / 64;
   __shared__ double sh[NV * NW];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double flat[NV];
 #pragma unroll
   for (int a = 0; a < TA; ++a)
 #pragma unroll
     for (int b = 0; b < TB; ++b)
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const double v = wave_sum(acc[a][b][q]);
-        if (lane == 0) sh[((a * TB + b) * 2 + q) * NW + w] = v;
-      }
+      for (int q = 0; q < 2; ++q) flat[(a * TB + b) * 2 + q] = acc[a][b][q];
+  const double mine = wave_sum_scatter<NV>(flat);
+  if (lane < NV) sh[lane * NW + w] = mine;
   __syncthreads();
   double* out = work + ((long long)chunk * ntiles + tile) * NV;
   for (int v = threadIdx.x; v < NV; v += G_BS) {
@@ -99,17 +127,20 @@ __global__ __launch_bounds__(G_BS) void k_gram_final(const double* __restrict__ 
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] += p[v];
   }
-  __shared__ double sh[NV * (G_BS / 64)];
-  block_sum<NV, G_BS>(acc, sh);
-  if (threadIdx.x == 0) {
+  constexpr int NW = G_BS / 64;
+  __shared__ double sh[NV * NW];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const double mine = wave_sum_scatter<NV>(acc);
+  if (lane < NV) sh[lane * NW + w] = mine;
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    const int v = threadIdx.x;
+    double s = 0;
 #pragma unroll
-    for (int a = 0; a < TA; ++a)
-#pragma unroll
-      for (int b = 0; b < TB; ++b) {
-        const int i = ta * TA + a, j = tb * TB + b;
-        if (i < na && j < nb)
-          C[i + (long long)j * na] = make_double2(acc[(a * TB + b) * 2], acc[(a * TB + b) * 2 + 1]);
-      }
+    for (int k = 0; k < NW; ++k) s += sh[v * NW + k];
+    const int q = v & 1, a = (v >> 1) / TB, b = (v >> 1) % TB;
+    const int i = ta * TA + a, j = tb * TB + b;
+    if (i < na && j < nb) ((double*)C)[2 * (i + (long long)j * na) + q] = s;
   }
 }
 

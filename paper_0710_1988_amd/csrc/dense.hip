@@ -20,16 +20,25 @@ namespace dbq {
 namespace {
 
 constexpr int NT = 64;         // one wavefront
+constexpr int CY_BS = 256;     // the cycle kernel: four wavefronts (all in the QR iteration)
 constexpr int LDS_CAP = 9312;  // double2 entries of the shared area (97 x 96)
 
 __device__ __forceinline__ double cabs_(zd a) { return hypot(a.re, a.im); }
-__device__ __forceinline__ zd ld2(const double2* p, long long i) {
+__device__ __forceinline__ zd ld2(const double2* p, int i) {
   const double2 v = p[i];
   return zd{v.x, v.y};
 }
-__device__ __forceinline__ void st2(double2* p, long long i, zd a) { p[i] = make_double2(a.re, a.im); }
+__device__ __forceinline__ void st2(double2* p, int i, zd a) { p[i] = make_double2(a.re, a.im); }
 __device__ __forceinline__ double wsum(double v) { return wave_sum(v); }
 __device__ __forceinline__ double nrm1(zd a) { return fabs(a.re) + fabs(a.im); }
+
+// Orders the LDS (and global) accesses of the lanes of one wavefront: the phases that run on one
+// wave while the others wait use it instead of a workgroup barrier.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // A vector of up to 128 entries held across the wavefront: entry i in lane i % 64, in member a
 // for i < 64 and b above.  Index arguments are uniform over the wave.
@@ -86,19 +95,19 @@ __device__ __forceinline__ void ls_qr(double2* QR, double2* g, int m, double2* v
     const int len = m1 - j;
     double p = 0;
     for (int i = t; i < len; i += NT) {
-      const double2 x = QR[(j + i) + (long long)j * m1];
+      const double2 x = QR[(j + i) + j * m1];
       p += x.x * x.x + x.y * x.y;
       v[i] = x;
     }
     const double nx2 = wsum(p);
-    __syncthreads();
+    wave_sync();
     if (nx2 == 0.0) continue;
     zd w0;
     double f;
     reflector(ld2(v, 0), nx2, w0, f);
     for (int c = j + t; c <= m; c += NT)
-      reflect_col(c < m ? QR + (long long)c * m1 + j : g + j, v, w0, len, f);
-    __syncthreads();
+      reflect_col(c < m ? QR + c * m1 + j : g + j, v, w0, len, f);
+    wave_sync();
   }
 }
 
@@ -107,11 +116,11 @@ __device__ __forceinline__ WVec back_subst(const double2* R, int ldr, const doub
   const int t = threadIdx.x;
   WVec b = wv_load(g, m);
   for (int j = m - 1; j >= 0; --j) {
-    const zd rjj = ld2(R, j + (long long)j * ldr);
+    const zd rjj = ld2(R, j + j * ldr);
     const zd dj = (rjj.re != 0.0 || rjj.im != 0.0) ? cdiv(wv_get(b, j), rjj) : zd{0.0, 0.0};
     wv_set(b, j, dj);
-    if (t < j) b.a = b.a - ld2(R, t + (long long)j * ldr) * dj;
-    if (t + 64 < j) b.b = b.b - ld2(R, t + 64 + (long long)j * ldr) * dj;
+    if (t < j) b.a = b.a - ld2(R, t + j * ldr) * dj;
+    if (t + 64 < j) b.b = b.b - ld2(R, t + 64 + j * ldr) * dj;
   }
   return b;
 }
@@ -126,7 +135,7 @@ __device__ __forceinline__ bool lu_wave(double2* A, int n, int ld, int* piv) {
     double best = -1.0;
     int bi = n;
     for (int i = j + t; i < n; i += NT) {
-      const double a = cabs_(ld2(A, i + (long long)j * ld));
+      const double a = cabs_(ld2(A, i + j * ld));
       if (a > best) {
         best = a;
         bi = i;
@@ -146,24 +155,24 @@ __device__ __forceinline__ bool lu_wave(double2* A, int n, int ld, int* piv) {
     if (best == 0.0) ok = false;
     if (p != j)
       for (int c = t; c < n; c += NT) {
-        const zd a = ld2(A, j + (long long)c * ld), b = ld2(A, p + (long long)c * ld);
-        st2(A, j + (long long)c * ld, b);
-        st2(A, p + (long long)c * ld, a);
+        const zd a = ld2(A, j + c * ld), b = ld2(A, p + c * ld);
+        st2(A, j + c * ld, b);
+        st2(A, p + c * ld, a);
       }
-    __syncthreads();
-    const zd d = ld2(A, j + (long long)j * ld);
+    wave_sync();
+    const zd d = ld2(A, j + j * ld);
     if (d.re != 0.0 || d.im != 0.0) {
       for (int i = j + 1 + t; i < n; i += NT)
-        st2(A, i + (long long)j * ld, cdiv(ld2(A, i + (long long)j * ld), d));
-      __syncthreads();
+        st2(A, i + j * ld, cdiv(ld2(A, i + j * ld), d));
+      wave_sync();
       const int r = n - j - 1;
       for (int idx = t; idx < r * r; idx += NT) {
         const int i = j + 1 + idx % r, c = j + 1 + idx / r;
-        st2(A, i + (long long)c * ld,
-            ld2(A, i + (long long)c * ld) - ld2(A, i + (long long)j * ld) * ld2(A, j + (long long)c * ld));
+        st2(A, i + c * ld,
+            ld2(A, i + c * ld) - ld2(A, i + j * ld) * ld2(A, j + c * ld));
       }
     }
-    __syncthreads();
+    wave_sync();
   }
   return ok;
 }
@@ -182,14 +191,14 @@ __device__ __forceinline__ void lu_solve_wave(const double2* A, int n, int ld, c
   }
   for (int j = 0; j < n; ++j) {  // L y = b (unit diagonal)
     const zd bj = wv_get(b, j);
-    if (t > j && t < n) b.a = b.a - ld2(A, t + (long long)j * ld) * bj;
-    if (t + 64 > j && t + 64 < n) b.b = b.b - ld2(A, t + 64 + (long long)j * ld) * bj;
+    if (t > j && t < n) b.a = b.a - ld2(A, t + j * ld) * bj;
+    if (t + 64 > j && t + 64 < n) b.b = b.b - ld2(A, t + 64 + j * ld) * bj;
   }
   for (int j = n - 1; j >= 0; --j) {  // U x = y
-    const zd xj = cdiv(wv_get(b, j), ld2(A, j + (long long)j * ld));
+    const zd xj = cdiv(wv_get(b, j), ld2(A, j + j * ld));
     wv_set(b, j, xj);
-    if (t < j) b.a = b.a - ld2(A, t + (long long)j * ld) * xj;
-    if (t + 64 < j) b.b = b.b - ld2(A, t + 64 + (long long)j * ld) * xj;
+    if (t < j) b.a = b.a - ld2(A, t + j * ld) * xj;
+    if (t + 64 < j) b.b = b.b - ld2(A, t + 64 + j * ld) * xj;
   }
 }
 
@@ -203,11 +212,11 @@ __device__ __forceinline__ void lu_solve_body(const double2* __restrict__ M, int
   double n1 = 0;
   for (int j = t; j < k; j += NT) {
     double s = 0;
-    for (int i = 0; i < k; ++i) s += cabs_(ld2(M, i + (long long)j * k));
+    for (int i = 0; i < k; ++i) s += cabs_(ld2(M, i + j * k));
     n1 = fmax(n1, s);
   }
   for (int o = 32; o > 0; o >>= 1) n1 = fmax(n1, __shfl_xor(n1, o, 64));
-  __syncthreads();
+  wave_sync();
   if (!lu_wave(LU, k, k, piv)) {
     if (t == 0) *cond = INFINITY;
     return;
@@ -226,7 +235,7 @@ __device__ __forceinline__ void lu_solve_body(const double2* __restrict__ M, int
   }
   // Y = M^{-1} C (solved with the factors for accuracy)
   for (int j = 0; j < nrhs; ++j) {
-    double2* cj = C + (long long)j * k;
+    double2* cj = C + j * k;
     WVec b = wv_load(cj, k);
     lu_solve_wave(LU, k, k, piv, b);
     if (t < k) st2(cj, t, b.a);
@@ -253,12 +262,12 @@ __device__ __forceinline__ void hessenberg(double2* G, int n, double2* v, double
     const int len = n - j - 1;
     double p = 0;
     for (int i = t; i < len; i += NT) {
-      const double2 x = G[(j + 1 + i) + (long long)j * n];
+      const double2 x = G[(j + 1 + i) + j * n];
       p += x.x * x.x + x.y * x.y;
       v[i] = x;
     }
     const double nx2 = wsum(p);
-    __syncthreads();
+    wave_sync();
     zd w0{0.0, 0.0};
     double f = 0.0;
     if (nx2 != 0.0) reflector(ld2(v, 0), nx2, w0, f);
@@ -268,23 +277,23 @@ __device__ __forceinline__ void hessenberg(double2* G, int n, double2* v, double
     }
     if (nx2 == 0.0) continue;
     // left: rows j+1.., columns j..n-1
-    for (int c = j + t; c < n; c += NT) reflect_col(G + (long long)c * n + j + 1, v, w0, len, f);
-    __syncthreads();
+    for (int c = j + t; c < n; c += NT) reflect_col(G + c * n + j + 1, v, w0, len, f);
+    wave_sync();
     // right: all rows, columns j+1..n-1
     for (int r = t; r < n; r += NT) {
-      double2* row = G + r + (long long)(j + 1) * n;
+      double2* row = G + r + (j + 1) * n;
       zd s = ld2(row, 0) * w0;
 #pragma unroll 4
-      for (int i = 1; i < len; ++i) s = s + ld2(row, (long long)i * n) * ld2(v, i);
+      for (int i = 1; i < len; ++i) s = s + ld2(row, i * n) * ld2(v, i);
       s = f * s;
       st2(row, 0, ld2(row, 0) - s * conj(w0));
 #pragma unroll 4
       for (int i = 1; i < len; ++i)
-        st2(row, (long long)i * n, ld2(row, (long long)i * n) - s * conj(ld2(v, i)));
+        st2(row, i * n, ld2(row, i * n) - s * conj(ld2(v, i)));
     }
-    __syncthreads();
-    for (int i = 1 + t; i < len; i += NT) G[(j + 1 + i) + (long long)j * n] = v[i];
-    __syncthreads();
+    wave_sync();
+    for (int i = 1 + t; i < len; i += NT) G[(j + 1 + i) + j * n] = v[i];
+    wave_sync();
   }
 }
 
@@ -294,14 +303,14 @@ __device__ __forceinline__ void form_q(const double2* G, int n, const double2* w
                                        const double* fs, double2* Q) {
   const int t = threadIdx.x;
   for (int c = t; c < n; c += NT) {
-    double2* qc = Q + (long long)c * n;
+    double2* qc = Q + c * n;
     for (int r = 0; r < n; ++r) qc[r] = make_double2(r == c ? 1.0 : 0.0, 0.0);
     for (int j = min(n - 3, c - 1); j >= 0; --j) {
       const double f = fs[j];
       if (f == 0.0) continue;
       const int len = n - j - 1;
       const zd w0 = ld2(w0s, j);
-      const double2* w = G + (long long)j * n + j + 1;  // w[i], i >= 1
+      const double2* w = G + j * n + j + 1;  // w[i], i >= 1
       double2* col = qc + j + 1;
       zd s = cmulc(w0, ld2(col, 0));
 #pragma unroll 4
@@ -316,39 +325,42 @@ __device__ __forceinline__ void form_q(const double2* G, int n, const double2* w
 
 // Shifted QR iteration (single Wilkinson shift, Givens bulge chase) on the upper Hessenberg G,
 // reducing it to upper triangular Schur form T with G_in = Z T Z^H; Z holds the Hessenberg
-// reduction's Q on entry.  With zlds the Schur vectors are rotated in the same phase as G (Z in
-// LDS); otherwise each sweep's rotations are recorded (rc, rs) and applied to the rows of Z after
-// the sweep.  Returns false if it did not converge.
+// reduction's Q on entry.  All four wavefronts of the block take part: every wave computes each
+// rotation from the two entries it annihilates, then, in one phase closed by one barrier, wave 0
+// rotates the two rows, wave 1 the two columns, wave 3 the 2 x 2 block where both act, and waves
+// 2 and 3 the Schur vectors (zlds, Z in LDS).  Otherwise the sweep's rotations are recorded (rc,
+// rs) and applied to the rows of Z after the sweep.  Returns false if it did not converge.
 __device__ __forceinline__ bool schur(double2* G, double2* Z, int n, bool zlds, double* rc,
                                       double2* rs) {
-  const int t = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const double eps = DBL_EPSILON;
   int hi = n - 1, iter = 0, total = 0;
   while (hi > 0) {
     // the largest l in 1..hi with a negligible subdiagonal entry G[l][l-1] (0 if none)
     int l = 0;
-    for (int qb = 0; qb <= hi; qb += NT) {
-      const int q = qb + t;
+    for (int qb = 0; qb <= hi; qb += 64) {
+      const int q = qb + lane;
       bool neg = false;
       if (q >= 1 && q <= hi) {
-        const double s = nrm1(ld2(G, (q - 1) + (long long)(q - 1) * n)) + nrm1(ld2(G, q + (long long)q * n));
-        neg = nrm1(ld2(G, q + (long long)(q - 1) * n)) <= eps * (s > 0 ? s : 1e-300);
+        const double sd = nrm1(ld2(G, (q - 1) + (q - 1) * n)) + nrm1(ld2(G, q + q * n));
+        neg = nrm1(ld2(G, q + (q - 1) * n)) <= eps * (sd > 0 ? sd : 1e-300);
       }
       const unsigned long long mask = __ballot(neg);
       if (mask) l = qb + 63 - __clzll(mask);
     }
-    if (l > 0 && t == 0) G[l + (long long)(l - 1) * n] = make_double2(0.0, 0.0);
+    __syncthreads();  // every wave has read the entry before it is zeroed
+    if (l > 0 && tid == 0) G[l + (l - 1) * n] = make_double2(0.0, 0.0);
     if (l == hi) {
       --hi;
       iter = 0;
       continue;
     }
     if (total > 60 * n) return false;
-    // shift (every lane computes it)
+    // shift (every thread computes it)
     zd mu;
     {
-      const zd a = ld2(G, (hi - 1) + (long long)(hi - 1) * n), b = ld2(G, (hi - 1) + (long long)hi * n);
-      const zd c = ld2(G, hi + (long long)(hi - 1) * n), d = ld2(G, hi + (long long)hi * n);
+      const zd a = ld2(G, (hi - 1) + (hi - 1) * n), b = ld2(G, (hi - 1) + hi * n);
+      const zd c = ld2(G, hi + (hi - 1) * n), d = ld2(G, hi + hi * n);
       if (iter > 0 && iter % 11 == 0) {
         mu = d + zd{fabs(c.re) + fabs(c.im), 0.0};  // exceptional shift
       } else {
@@ -366,11 +378,11 @@ __device__ __forceinline__ bool schur(double2* G, double2* Z, int n, bool zlds, 
     for (int kk = l; kk < hi; ++kk) {
       zd x, y;
       if (kk == l) {
-        x = ld2(G, l + (long long)l * n) - mu;
-        y = ld2(G, (l + 1) + (long long)l * n);
+        x = ld2(G, l + l * n) - mu;
+        y = ld2(G, (l + 1) + l * n);
       } else {
-        x = ld2(G, kk + (long long)(kk - 1) * n);
-        y = ld2(G, (kk + 1) + (long long)(kk - 1) * n);
+        x = ld2(G, kk + (kk - 1) * n);
+        y = ld2(G, (kk + 1) + (kk - 1) * n);
       }
       // c = |x| / rho, s = (x / |x|) conj(y) / rho, rho = sqrt(|x|^2 + |y|^2) (entries far from
       // the range limits: no hypot-style scaling)
@@ -384,47 +396,51 @@ __device__ __forceinline__ bool schur(double2* G, double2* Z, int n, bool zlds, 
         c = 0.0;
         s = zd{1.0, 0.0};
       } else {
-        const double ax = sqrt(nx);
-        const double irho = 1.0 / sqrt(nx + ny);
-        const double iax = 1.0 / ax;
-        c = ax * irho;
+        const double irho = rsqrt(nx + ny), iax = rsqrt(nx);
+        c = nx * iax * irho;
         const zd ph{x.re * iax, x.im * iax};
         s = ph * conj(y);
         s = zd{s.re * irho, s.im * irho};
       }
-      // one phase: rows kk, kk+1 (columns outside {kk, kk+1} from kk-1, or kk at the start of
-      // the sweep, where column l-1 holds zeros), columns kk, kk+1 (rows up to min(kk+2, hi)
-      // outside {kk, kk+1}), the 2 x 2 block where both act (row rotation first), the Schur
-      // vectors; the bulge below the subdiagonal in column kk-1 becomes exactly zero
+      // rows kk, kk+1 over the columns outside {kk, kk+1} from kk-1 (from kk at the start of the
+      // sweep, where column l-1 holds zeros), the bulge left in column kk-1 set to exactly zero;
+      // columns kk, kk+1 over the rows up to min(kk+2, hi) outside {kk, kk+1}; the 2 x 2 block
+      // (rows first, then columns); the Schur vectors
       const int j0 = kk == l ? kk : kk - 1;
       const int rmax = kk + 2 < hi ? kk + 2 : hi;
-      for (int q = t; q < n; q += NT) {
-        if (q >= j0 && q != kk && q != kk + 1) {
-          const zd a = ld2(G, kk + (long long)q * n), b = ld2(G, (kk + 1) + (long long)q * n);
-          st2(G, kk + (long long)q * n, c * a + s * b);
-          st2(G, (kk + 1) + (long long)q * n, q == kk - 1 ? zd{0.0, 0.0} : c * b - conj(s) * a);
-        }
-        if (q <= rmax && q != kk && q != kk + 1) {
-          const zd a = ld2(G, q + (long long)kk * n), b = ld2(G, q + (long long)(kk + 1) * n);
-          st2(G, q + (long long)kk * n, c * a + conj(s) * b);
-          st2(G, q + (long long)(kk + 1) * n, c * b - s * a);
+      if (wv == 0) {
+        for (int q = lane; q < n; q += 64)
+          if (q >= j0 && q != kk && q != kk + 1) {
+            const zd a = ld2(G, kk + q * n), b = ld2(G, (kk + 1) + q * n);
+            st2(G, kk + q * n, c * a + s * b);
+            st2(G, (kk + 1) + q * n, q == kk - 1 ? zd{0.0, 0.0} : c * b - conj(s) * a);
+          }
+      } else if (wv == 1) {
+        for (int q = lane; q <= rmax; q += 64)
+          if (q != kk && q != kk + 1) {
+            const zd a = ld2(G, q + kk * n), b = ld2(G, q + (kk + 1) * n);
+            st2(G, q + kk * n, c * a + conj(s) * b);
+            st2(G, q + (kk + 1) * n, c * b - s * a);
+          }
+      } else {
+        if (wv == 3 && lane == 0) {
+          const zd a11 = ld2(G, kk + kk * n), a12 = ld2(G, kk + (kk + 1) * n);
+          const zd a21 = ld2(G, (kk + 1) + kk * n), a22 = ld2(G, (kk + 1) + (kk + 1) * n);
+          const zd b11 = c * a11 + s * a21, b12 = c * a12 + s * a22;
+          const zd b21 = c * a21 - conj(s) * a11, b22 = c * a22 - conj(s) * a12;
+          st2(G, kk + kk * n, c * b11 + conj(s) * b12);
+          st2(G, kk + (kk + 1) * n, c * b12 - s * b11);
+          st2(G, (kk + 1) + kk * n, c * b21 + conj(s) * b22);
+          st2(G, (kk + 1) + (kk + 1) * n, c * b22 - s * b21);
         }
         if (zlds) {
-          const zd a = ld2(Z, q + (long long)kk * n), b = ld2(Z, q + (long long)(kk + 1) * n);
-          st2(Z, q + (long long)kk * n, c * a + conj(s) * b);
-          st2(Z, q + (long long)(kk + 1) * n, c * b - s * a);
-        }
-      }
-      if (t == 0) {
-        const zd a11 = ld2(G, kk + (long long)kk * n), a12 = ld2(G, kk + (long long)(kk + 1) * n);
-        const zd a21 = ld2(G, (kk + 1) + (long long)kk * n), a22 = ld2(G, (kk + 1) + (long long)(kk + 1) * n);
-        const zd b11 = c * a11 + s * a21, b12 = c * a12 + s * a22;
-        const zd b21 = c * a21 - conj(s) * a11, b22 = c * a22 - conj(s) * a12;
-        st2(G, kk + (long long)kk * n, c * b11 + conj(s) * b12);
-        st2(G, kk + (long long)(kk + 1) * n, c * b12 - s * b11);
-        st2(G, (kk + 1) + (long long)kk * n, c * b21 + conj(s) * b22);
-        st2(G, (kk + 1) + (long long)(kk + 1) * n, c * b22 - s * b21);
-        if (!zlds) {
+          const int q = (wv - 2) * 64 + lane;
+          if (q < n) {
+            const zd a = ld2(Z, q + kk * n), b = ld2(Z, q + (kk + 1) * n);
+            st2(Z, q + kk * n, c * a + conj(s) * b);
+            st2(Z, q + (kk + 1) * n, c * b - s * a);
+          }
+        } else if (wv == 2 && lane == 0) {
           rc[kk] = c;
           rs[kk] = make_double2(s.re, s.im);
         }
@@ -434,24 +450,24 @@ __device__ __forceinline__ bool schur(double2* G, double2* Z, int n, bool zlds, 
     if (!zlds) {
       // the sweep's rotations on the rows of Z: column kk is final after rotation kk, column
       // kk+1 carried to the next one; the untouched columns are loaded ahead in groups of 16
-      for (int r = t; r < n; r += NT) {
-        zd za = ld2(Z, r + (long long)l * n);
+      for (int r = tid; r < n; r += blockDim.x) {
+        zd za = ld2(Z, r + l * n);
         for (int kb = l; kb < hi; kb += 16) {
           const int cnt = hi - kb < 16 ? hi - kb : 16;
           zd zb[16];
 #pragma unroll
           for (int u = 0; u < 16; ++u)
-            if (u < cnt) zb[u] = ld2(Z, r + (long long)(kb + 1 + u) * n);
+            if (u < cnt) zb[u] = ld2(Z, r + (kb + 1 + u) * n);
 #pragma unroll
           for (int u = 0; u < 16; ++u)
             if (u < cnt) {
               const double cc = rc[kb + u];
               const zd ss = ld2(rs, kb + u);
-              st2(Z, r + (long long)(kb + u) * n, cc * za + conj(ss) * zb[u]);
+              st2(Z, r + (kb + u) * n, cc * za + conj(ss) * zb[u]);
               za = cc * zb[u] - ss * za;
             }
         }
-        st2(Z, r + (long long)hi * n, za);
+        st2(Z, r + hi * n, za);
       }
     }
     ++iter;
@@ -467,16 +483,16 @@ __device__ __forceinline__ bool schur(double2* G, double2* Z, int n, bool zlds, 
 __device__ __forceinline__ void tri_eigvec(const double2* T, const double2* Z, int n, int q,
                                            double tnorm, double2* out, bool pad) {
   const int t = threadIdx.x;
-  const zd th = ld2(T, q + (long long)q * n);
+  const zd th = ld2(T, q + q * n);
   const double small = fmax(DBL_EPSILON * tnorm, 1e-300);
   WVec acc{zd{0.0, 0.0}, zd{0.0, 0.0}};
   WVec y{zd{0.0, 0.0}, zd{0.0, 0.0}};
   wv_set(y, q, zd{1.0, 0.0});
   zd yj{1.0, 0.0};
   for (int j = q; j >= 1; --j) {
-    if (t < j) acc.a = acc.a + ld2(T, t + (long long)j * n) * yj;
-    if (t + 64 < j) acc.b = acc.b + ld2(T, t + 64 + (long long)j * n) * yj;
-    zd d = ld2(T, (j - 1) + (long long)(j - 1) * n) - th;
+    if (t < j) acc.a = acc.a + ld2(T, t + j * n) * yj;
+    if (t + 64 < j) acc.b = acc.b + ld2(T, t + 64 + j * n) * yj;
+    zd d = ld2(T, (j - 1) + (j - 1) * n) - th;
     if (cabs_(d) < small) d = zd{small, 0.0};
     yj = -cdiv(wv_get(acc, j - 1), d);
     wv_set(y, j - 1, yj);
@@ -490,7 +506,7 @@ __device__ __forceinline__ void tri_eigvec(const double2* T, const double2* Z, i
     if (slot * 64 < n)
       for (int j = 0; j <= q; ++j) {
         const zd yv = wv_get(y, j);
-        if (r < n) s = s + ld2(Z, r + (long long)j * n) * yv;
+        if (r < n) s = s + ld2(Z, r + j * n) * yv;
       }
     g[slot] = s;
     if (r < n) nn += norm2(s);
@@ -511,26 +527,26 @@ __device__ __forceinline__ void orth_column(double2* P, int ldp, int len, int q,
   for (int pass = 0; pass < 2; ++pass) {
     for (int i = t; i < q; i += NT) {
       zd s{0, 0};
-      for (int r = 0; r < len; ++r) s = s + cmulc(ld2(P, r + (long long)i * ldp), ld2(P, r + (long long)q * ldp));
+      for (int r = 0; r < len; ++r) s = s + cmulc(ld2(P, r + i * ldp), ld2(P, r + q * ldp));
       st2(h, i, s);
     }
-    __syncthreads();
+    wave_sync();
     for (int r = t; r < len; r += NT) {
-      zd w = ld2(P, r + (long long)q * ldp);
-      for (int i = 0; i < q; ++i) w = w - ld2(P, r + (long long)i * ldp) * ld2(h, i);
-      st2(P, r + (long long)q * ldp, w);
+      zd w = ld2(P, r + q * ldp);
+      for (int i = 0; i < q; ++i) w = w - ld2(P, r + i * ldp) * ld2(h, i);
+      st2(P, r + q * ldp, w);
     }
-    __syncthreads();
+    wave_sync();
   }
   double p = 0;
-  for (int r = t; r < len; r += NT) p += norm2(ld2(P, r + (long long)q * ldp));
+  for (int r = t; r < len; r += NT) p += norm2(ld2(P, r + q * ldp));
   const double nn = sqrt(wsum(p));
   const double f = nn > 0 ? 1.0 / nn : 0.0;
   for (int r = t; r < len; r += NT) {
-    const zd w = ld2(P, r + (long long)q * ldp);
-    st2(P, r + (long long)q * ldp, zd{w.re * f, w.im * f});
+    const zd w = ld2(P, r + q * ldp);
+    st2(P, r + q * ldp, zd{w.re * f, w.im * f});
   }
-  __syncthreads();
+  wave_sync();
 }
 
 // ----------------------------------------------------------------------------- cycle phases
@@ -542,7 +558,7 @@ __device__ __forceinline__ double phase_ls(const CycleArgs& a, double2* QR, doub
   const double2* H = a.Hbar;
   for (int i = t; i < m1 * m; i += NT) QR[i] = H[i];
   for (int i = t; i < m1; i += NT) g[i] = a.c[i];
-  __syncthreads();
+  wave_sync();
   ls_qr(QR, g, m, v);
   const WVec d = back_subst(QR, m1, g, m);
   if (t < m) st2(a.d, t, d.a);
@@ -553,7 +569,7 @@ __device__ __forceinline__ double phase_ls(const CycleArgs& a, double2* QR, doub
     zd s = r < m1 ? ld2(a.c, r) : zd{0.0, 0.0};
     for (int j = 0; j < m; ++j) {
       const zd dj = wv_get(d, j);
-      if (r < m1) s = s - ld2(H, r + (long long)j * m1) * dj;
+      if (r < m1) s = s - ld2(H, r + j * m1) * dj;
     }
     if (r < m1) {
       st2(rho, r, s);
@@ -561,7 +577,7 @@ __device__ __forceinline__ double phase_ls(const CycleArgs& a, double2* QR, doub
       p += norm2(s);
     }
   }
-  __syncthreads();
+  wave_sync();
   return sqrt(wsum(p));
 }
 
@@ -574,48 +590,51 @@ __device__ __forceinline__ void phase_g(const CycleArgs& a, double2* G, int* piv
   if (a.mode != 2) {
     for (int i = t; i < m * m; i += NT) {
       const int r = i % m, c = i / m;
-      st2(G, i, conj(ld2(H, c + (long long)r * m1)));
+      st2(G, i, conj(ld2(H, c + r * m1)));
     }
-    __syncthreads();
+    wave_sync();
     lu_wave(G, m, m, piv);
     wv_set(f, m - 1, zd{1.0, 0.0});
     lu_solve_wave(G, m, m, piv, f);
-    __syncthreads();
+    wave_sync();
   }
   for (int i = t; i < m * m; i += NT) {
     const int r = i % m, c = i / m;
-    G[i] = H[r + (long long)c * m1];
+    G[i] = H[r + c * m1];
   }
-  __syncthreads();
+  wave_sync();
   if (a.mode != 2) {
-    const double h2 = norm2(ld2(H, m + (long long)(m - 1) * m1));
-    if (t < m) st2(G, t + (long long)(m - 1) * m, ld2(G, t + (long long)(m - 1) * m) + h2 * f.a);
+    const double h2 = norm2(ld2(H, m + (m - 1) * m1));
+    if (t < m) st2(G, t + (m - 1) * m, ld2(G, t + (m - 1) * m) + h2 * f.a);
     if (t + 64 < m)
-      st2(G, t + 64 + (long long)(m - 1) * m, ld2(G, t + 64 + (long long)(m - 1) * m) + h2 * f.b);
-    __syncthreads();
+      st2(G, t + 64 + (m - 1) * m, ld2(G, t + 64 + (m - 1) * m) + h2 * f.b);
+    wave_sync();
   }
 }
 
-// Schur form of G (m x m) with Schur vectors Z; sorted eigenvalues into a.theta and order[];
-// returns the number of vectors to keep (in every lane) and the largest |entry| of T in tn
-__device__ __forceinline__ int phase_eig(const CycleArgs& a, double2* G, double2* Z, bool zlds,
-                                         double2* v, double2* w0s, double* fs, int* order,
-                                         int* s_kout, double& tn) {
-  const int t = threadIdx.x, m = a.m, k = a.k;
+// Hessenberg form of G (m x m) and the Q of the reduction in Z (one wave)
+__device__ __forceinline__ void phase_hess(const CycleArgs& a, double2* G, double2* Z, double2* v,
+                                           double2* w0s, double* fs) {
+  const int t = threadIdx.x, m = a.m;
   hessenberg(G, m, v, w0s, fs);
   form_q(G, m, w0s, fs, Z);
-  __syncthreads();
+  wave_sync();
   for (int c = t; c < m; c += NT)
-    for (int r = c + 2; r < m; ++r) G[r + (long long)c * m] = make_double2(0.0, 0.0);
-  __syncthreads();
-  const bool ok = schur(G, Z, m, zlds, fs, w0s);
-  if (t == 0) a.info[4] = ok ? 0.0 : 1.0;
+    for (int r = c + 2; r < m; ++r) G[r + c * m] = make_double2(0.0, 0.0);
+  wave_sync();
+}
+
+// eigenvalues of the Schur form T (in G) sorted into a.theta and order[]; returns the number of
+// vectors to keep (in every lane) and the largest |entry| of T in tn (one wave)
+__device__ __forceinline__ int phase_sort(const CycleArgs& a, const double2* G, int* order,
+                                          int* s_kout, double& tn) {
+  const int t = threadIdx.x, m = a.m, k = a.k;
   // sort: |theta| ascending (harmonic) or Re descending (Ritz), ties by (Re, Im, index)
   for (int i = t; i < m; i += NT) {
-    const zd ti = ld2(G, i + (long long)i * m);
+    const zd ti = ld2(G, i + i * m);
     int rank = 0;
     for (int j = 0; j < m; ++j) {
-      const zd tj = ld2(G, j + (long long)j * m);
+      const zd tj = ld2(G, j + j * m);
       bool less;
       if (a.mode != 2) {
         const double ai = cabs_(ti), aj = cabs_(tj);
@@ -627,13 +646,13 @@ __device__ __forceinline__ int phase_eig(const CycleArgs& a, double2* G, double2
     }
     order[rank] = i;
   }
-  __syncthreads();
-  for (int i = t; i < m; i += NT) a.theta[i] = G[order[i] + (long long)order[i] * m];
+  wave_sync();
+  for (int i = t; i < m; i += NT) a.theta[i] = G[order[i] + order[i] * m];
   if (t == 0) {
     int kout = k;
     if (a.mode == 1 && k < m) {
-      const zd x = ld2(G, order[k - 1] + (long long)order[k - 1] * m);
-      const zd y = ld2(G, order[k] + (long long)order[k] * m);
+      const zd x = ld2(G, order[k - 1] + order[k - 1] * m);
+      const zd y = ld2(G, order[k] + order[k] * m);
       const double sc = cabs_(x);
       if (fabs(x.im) > 1e-3 * sc && cabs_(x - conj(y)) <= 1e-3 * sc) kout = k - 1;
     }
@@ -644,7 +663,7 @@ __device__ __forceinline__ int phase_eig(const CycleArgs& a, double2* G, double2
   for (int i = t; i < m * m; i += NT) mx = fmax(mx, cabs_(ld2(G, i)));
   for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
   tn = mx;
-  __syncthreads();
+  wave_sync();
   return *s_kout;
 }
 
@@ -658,40 +677,40 @@ __device__ __forceinline__ void phase_restart(const CycleArgs& a, double2* P, do
   for (int q = 0; q < ks; ++q) orth_column(P, m1, m1, q, h);
   if (a.mode == 2) {
     if (t == 0) {
-      const double hm = cabs_(ld2(H, m + (long long)(m - 1) * m1));
+      const double hm = cabs_(ld2(H, m + (m - 1) * m1));
       a.info[3] = hm * cabs_(ld2(P, m - 1));
-      P[m + (long long)k * m1] = make_double2(1.0, 0.0);
+      P[m + k * m1] = make_double2(1.0, 0.0);
     }
-    __syncthreads();
+    wave_sync();
   } else if (a.mode == 0) {
-    for (int r = t; r < m1; r += NT) P[r + (long long)k * m1] = rho[r];
-    __syncthreads();
+    for (int r = t; r < m1; r += NT) P[r + k * m1] = rho[r];
+    wave_sync();
     orth_column(P, m1, m1, k, h);
   }
   if (a.mode == 1) return;
   for (int i = t; i < m1 * k; i += NT) {
     const int r = i % m1, c = i / m1;
     zd s{0, 0};
-    for (int j = 0; j < m; ++j) s = s + ld2(H, r + (long long)j * m1) * ld2(P, j + (long long)c * m1);
-    st2(T1, r + (long long)c * m1, s);
+    for (int j = 0; j < m; ++j) s = s + ld2(H, r + j * m1) * ld2(P, j + c * m1);
+    st2(T1, r + c * m1, s);
   }
-  __syncthreads();
+  wave_sync();
   for (int i = t; i < (k + 1) * k; i += NT) {
     const int r = i % (k + 1), c = i / (k + 1);
     zd s{0, 0};
-    for (int j = 0; j < m1; ++j) s = s + cmulc(ld2(P, j + (long long)r * m1), ld2(T1, j + (long long)c * m1));
-    st2(a.Hnew, r + (long long)c * m1, s);
+    for (int j = 0; j < m1; ++j) s = s + cmulc(ld2(P, j + r * m1), ld2(T1, j + c * m1));
+    st2(a.Hnew, r + c * m1, s);
   }
   for (int r = t; r < m1; r += NT) {
     zd s{0, 0};
     if (r <= k && a.mode == 0)
-      for (int j = 0; j < m1; ++j) s = s + cmulc(ld2(P, j + (long long)r * m1), ld2(rho, j));
+      for (int j = 0; j < m1; ++j) s = s + cmulc(ld2(P, j + r * m1), ld2(rho, j));
     st2(a.cnew, r, s);
   }
 }
 
-__global__ __launch_bounds__(NT) void k_cycle(CycleArgs a) {
-  const int t = threadIdx.x;
+__global__ __launch_bounds__(CY_BS) void k_cycle(CycleArgs a) {
+  const int t = threadIdx.x, wv = t >> 6;
   const int m = a.m, m1 = m + 1, k = a.k;
   // global scratch for what does not fit in LDS
   double2* w = a.work;
@@ -706,50 +725,63 @@ __global__ __launch_bounds__(NT) void k_cycle(CycleArgs a) {
   __shared__ double fs[128];
   __shared__ int piv[128];
   __shared__ int order[128];
-  __shared__ int s_kout;
-
-  if (a.mode == 0 || a.mode == 1 || a.mode == 3) {
-    const double rn = m1 * m <= LDS_CAP ? phase_ls(a, sh, gr, v, gr) : phase_ls(a, wA, gr, v, gr);
-    const bool conv = rn <= a.tol_abs;
-    if (t == 0) {
-      a.info[0] = rn;
-      a.info[2] = conv ? 1.0 : 0.0;
-    }
-    if ((a.mode == 0 && conv) || a.mode == 3) return;
-  }
-
-  // ---- eigenproblem: G (and Z) in LDS where they fit
-  int ks;
-  double tn;
+  __shared__ int s_kout, s_exit;
   const bool g_lds = m * m <= LDS_CAP, z_lds = 2 * m * m <= LDS_CAP;
-  if (z_lds) {
-    phase_g(a, sh, piv);
-    ks = phase_eig(a, sh, sh + m * m, true, v, w0s, fs, order, &s_kout, tn);
-  } else if (g_lds) {
-    phase_g(a, sh, piv);
-    ks = phase_eig(a, sh, wZ, false, v, w0s, fs, order, &s_kout, tn);
-  } else {
-    phase_g(a, wG, piv);
-    ks = phase_eig(a, wG, wZ, false, v, w0s, fs, order, &s_kout, tn);
+
+  // ---- wave 0: least squares, the eigenproblem's matrix and its Hessenberg form
+  if (wv == 0) {
+    int ex = 0;
+    if (a.mode == 0 || a.mode == 1 || a.mode == 3) {
+      const double rn = m1 * m <= LDS_CAP ? phase_ls(a, sh, gr, v, gr) : phase_ls(a, wA, gr, v, gr);
+      const bool conv = rn <= a.tol_abs;
+      if (t == 0) {
+        a.info[0] = rn;
+        a.info[2] = conv ? 1.0 : 0.0;
+      }
+      ex = (a.mode == 0 && conv) || a.mode == 3;
+    }
+    if (t == 0) s_exit = ex;
+    if (!ex) {
+      if (z_lds) {
+        phase_g(a, sh, piv);
+        phase_hess(a, sh, sh + m * m, v, w0s, fs);
+      } else if (g_lds) {
+        phase_g(a, sh, piv);
+        phase_hess(a, sh, wZ, v, w0s, fs);
+      } else {
+        phase_g(a, wG, piv);
+        phase_hess(a, wG, wZ, v, w0s, fs);
+      }
+    }
   }
-  // ---- eigenvectors of the selected values into the columns of P (padded with a zero row)
-  for (int i = t; i < m1 * (k + 1); i += NT) a.P[i] = make_double2(0.0, 0.0);
   __syncthreads();
+  if (s_exit) return;
+  // ---- all waves: the QR iteration
+  const bool ok = z_lds ? schur(sh, sh + m * m, m, true, fs, w0s)
+                        : (g_lds ? schur(sh, wZ, m, false, fs, w0s) : schur(wG, wZ, m, false, fs, w0s));
+  if (wv != 0) return;
+  // ---- wave 0: selection, eigenvectors, restart basis
+  if (t == 0) a.info[4] = ok ? 0.0 : 1.0;
+  double tn;
+  const int ks = g_lds ? phase_sort(a, sh, order, &s_kout, tn) : phase_sort(a, wG, order, &s_kout, tn);
+  // eigenvectors of the selected values into the columns of P (padded with a zero row)
+  for (int i = t; i < m1 * (k + 1); i += NT) a.P[i] = make_double2(0.0, 0.0);
+  wave_sync();
   for (int q = 0; q < ks; ++q) {
     const int col = order[q];
-    if (z_lds) tri_eigvec(sh, sh + m * m, m, col, tn, a.P + (long long)q * m1, true);
-    else if (g_lds) tri_eigvec(sh, wZ, m, col, tn, a.P + (long long)q * m1, true);
-    else tri_eigvec(wG, wZ, m, col, tn, a.P + (long long)q * m1, true);
+    if (z_lds) tri_eigvec(sh, sh + m * m, m, col, tn, a.P + q * m1, true);
+    else if (g_lds) tri_eigvec(sh, wZ, m, col, tn, a.P + q * m1, true);
+    else tri_eigvec(wG, wZ, m, col, tn, a.P + q * m1, true);
   }
-  __syncthreads();
-  // ---- restart basis and Hnew, in LDS where P and Hbar P fit
+  wave_sync();
+  // restart basis and Hnew, in LDS where P and Hbar P fit
   if (m1 * (2 * k + 1) <= LDS_CAP) {
     double2* P = sh;
     double2* T1 = sh + m1 * (k + 1);
     for (int i = t; i < m1 * (k + 1); i += NT) P[i] = a.P[i];
-    __syncthreads();
+    wave_sync();
     phase_restart(a, P, T1, ks, gr, v);
-    __syncthreads();
+    wave_sync();
     for (int i = t; i < m1 * (k + 1); i += NT) a.P[i] = P[i];
   } else {
     phase_restart(a, a.P, wT1, ks, gr, v);
@@ -760,11 +792,11 @@ __global__ void k_trsolve(const double2* __restrict__ R, int ldr, int n, double2
                           int nrhs, int ldz) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nrhs) return;
-  double2* b = z + (long long)j * ldz;
+  double2* b = z + j * ldz;
   for (int i = n - 1; i >= 0; --i) {
     zd s = ld2(b, i);
-    for (int c = i + 1; c < n; ++c) s = s - ld2(R, i + (long long)c * ldr) * ld2(b, c);
-    const zd d = ld2(R, i + (long long)i * ldr);
+    for (int c = i + 1; c < n; ++c) s = s - ld2(R, i + c * ldr) * ld2(b, c);
+    const zd d = ld2(R, i + i * ldr);
     st2(b, i, (d.re != 0.0 || d.im != 0.0) ? cdiv(s, d) : zd{0.0, 0.0});
   }
 }
@@ -785,7 +817,7 @@ void dense_lu_solve(hipStream_t s, const double2* M, int k, double2* C, int nrhs
 
 void dense_cycle(hipStream_t s, const CycleArgs& a) {
   DBQ_CHECK(a.m >= 2 && a.m <= 128 && a.k >= 1 && a.k < a.m, "dense_cycle: bad (m, k)");
-  hipLaunchKernelGGL(k_cycle, dim3(1), dim3(NT), 0, s, a);
+  hipLaunchKernelGGL(k_cycle, dim3(1), dim3(CY_BS), 0, s, a);
   DBQ_HIP(hipGetLastError());
 }
 
