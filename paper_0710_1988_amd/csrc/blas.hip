@@ -458,6 +458,7 @@ __global__ __launch_bounds__(AC_BS) void k_arn_coef(const double2* __restrict__ 
   for (int i = t; i <= j; i += AC_BS) {
     zd hs{0.0, 0.0};
     if (!start)
+#pragma unroll 8
       for (int cc = 0; cc < j; ++cc) {
         const double2 h = H[i + (long long)cc * ldh];
         hs = hs + zd{h.x, h.y} * s_s[cc];

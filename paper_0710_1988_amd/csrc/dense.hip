@@ -50,13 +50,13 @@ __device__ __forceinline__ zd wv_get(const WVec& x, int i) {
   return zd{__shfl(v.re, i & 63, 64), __shfl(v.im, i & 63, 64)};
 }
 __device__ __forceinline__ void wv_set(WVec& x, int i, zd v) {
-  if (int(threadIdx.x) == (i & 63)) {
+  if (int(threadIdx.x & 63) == (i & 63)) {
     if (i < 64) x.a = v;
     else x.b = v;
   }
 }
 __device__ __forceinline__ WVec wv_load(const double2* p, int n) {
-  const int t = threadIdx.x;
+  const int t = threadIdx.x & 63;
   WVec x;
   x.a = t < n ? ld2(p, t) : zd{0.0, 0.0};
   x.b = t + 64 < n ? ld2(p, t + 64) : zd{0.0, 0.0};
@@ -482,7 +482,7 @@ __device__ __forceinline__ bool schur(double2* G, double2* Z, int n, bool zlds, 
 // in out[0..n) (column of ld-strided storage) and writes out[n] = 0 when pad.
 __device__ __forceinline__ void tri_eigvec(const double2* T, const double2* Z, int n, int q,
                                            double tnorm, double2* out, bool pad) {
-  const int t = threadIdx.x;
+  const int t = threadIdx.x & 63;
   const zd th = ld2(T, q + q * n);
   const double small = fmax(DBL_EPSILON * tnorm, 1e-300);
   WVec acc{zd{0.0, 0.0}, zd{0.0, 0.0}};
@@ -726,6 +726,7 @@ __global__ __launch_bounds__(CY_BS) void k_cycle(CycleArgs a) {
   __shared__ int piv[128];
   __shared__ int order[128];
   __shared__ int s_kout, s_exit;
+  __shared__ double s_tn;
   const bool g_lds = m * m <= LDS_CAP, z_lds = 2 * m * m <= LDS_CAP;
 
   // ---- wave 0: least squares, the eigenproblem's matrix and its Hessenberg form
@@ -759,21 +760,27 @@ __global__ __launch_bounds__(CY_BS) void k_cycle(CycleArgs a) {
   // ---- all waves: the QR iteration
   const bool ok = z_lds ? schur(sh, sh + m * m, m, true, fs, w0s)
                         : (g_lds ? schur(sh, wZ, m, false, fs, w0s) : schur(wG, wZ, m, false, fs, w0s));
-  if (wv != 0) return;
-  // ---- wave 0: selection, eigenvectors, restart basis
-  if (t == 0) a.info[4] = ok ? 0.0 : 1.0;
-  double tn;
-  const int ks = g_lds ? phase_sort(a, sh, order, &s_kout, tn) : phase_sort(a, wG, order, &s_kout, tn);
-  // eigenvectors of the selected values into the columns of P (padded with a zero row)
-  for (int i = t; i < m1 * (k + 1); i += NT) a.P[i] = make_double2(0.0, 0.0);
-  wave_sync();
-  for (int q = 0; q < ks; ++q) {
+  // ---- wave 0: selection
+  if (wv == 0) {
+    if (t == 0) a.info[4] = ok ? 0.0 : 1.0;
+    double tn;
+    g_lds ? phase_sort(a, sh, order, &s_kout, tn) : phase_sort(a, wG, order, &s_kout, tn);
+    if (t == 0) s_tn = tn;
+    for (int i = t; i < m1 * (k + 1); i += NT) a.P[i] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  // ---- all waves: eigenvectors of the selected values into the columns of P (padded with a
+  // zero row), one vector per wave at a time
+  const int ks = s_kout;
+  const double tn = s_tn;
+  for (int q = wv; q < ks; q += CY_BS / 64) {
     const int col = order[q];
     if (z_lds) tri_eigvec(sh, sh + m * m, m, col, tn, a.P + q * m1, true);
     else if (g_lds) tri_eigvec(sh, wZ, m, col, tn, a.P + q * m1, true);
     else tri_eigvec(wG, wZ, m, col, tn, a.P + q * m1, true);
   }
-  wave_sync();
+  __syncthreads();
+  if (wv != 0) return;
   // restart basis and Hnew, in LDS where P and Hbar P fit
   if (m1 * (2 * k + 1) <= LDS_CAP) {
     double2* P = sh;
