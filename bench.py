@@ -636,6 +636,17 @@ def main():
         out["even_odd_reduced_system"] = eo
         out["dslash_24x24x24x48"] = dslash_sweep(dbq, torch)
         log(f"dslash sweep: {out['dslash_24x24x24x48']}")
+        # the same kernel where its working set does not fit the 256 MB MALL: 24^3 x 48 x 12
+        sw = out["dslash_24x24x24x48"]["mixed_24x24x24x48_nrhs12"]
+        h_traffic, h_src = counter_traffic("DSLASH_F32_HBM_TRAFFIC_BYTES_PER_LAUNCH")
+        out["roofline_hbm"] = {
+            "bound": "hbm", "achieved": sw["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(sw["GBps"] / HBM_PEAK_GBS, 4),
+            "traffic": None if h_traffic is None else round(h_traffic),
+            "traffic_source": h_src,
+            "kernel": "FP32 Dslash k_dslash_tile on 24^3 x 48, 12 rhs per launch (1.66 GB "
+                      "algorithmic, beyond the MALL)",
+            "avg_launch_us": sw["us_per_launch"], "algorithmic_MB_per_launch": sw["MB_per_launch"]}
     legs = {"c2eo": leg_c2eo, "c3": leg_c3, "c4": leg_c4, "c5": leg_c5, "c5eo": leg_c5eo,
             "f2": leg_f2, "f3": leg_f3, "f4": leg_f4}
     _C2.update(U=U, kc=kc)

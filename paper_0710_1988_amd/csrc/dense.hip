@@ -203,9 +203,36 @@ __device__ __forceinline__ void lu_solve_wave(const double2* A, int n, int ld, c
 }
 
 // ----------------------------------------------------------------------------- k x k solve
+// (LU) x = b for lane t's own column, held lane-interleaved (entry i at X[i * 64 + t], so a wave's
+// accesses hit consecutive LDS slots); the factors are read by all lanes at once
+__device__ __forceinline__ void lu_solve_own(const double2* A, int n, const int* piv, double2* X,
+                                             int t) {
+  for (int j = 0; j < n; ++j) {
+    const int p = piv[j];
+    if (p != j) {
+      const zd a = ld2(X, j * 64 + t), b = ld2(X, p * 64 + t);
+      st2(X, j * 64 + t, b);
+      st2(X, p * 64 + t, a);
+    }
+  }
+  for (int i = 0; i < n; ++i) {  // L y = b (unit diagonal)
+    zd s = ld2(X, i * 64 + t);
+    for (int j = 0; j < i; ++j) s = s - ld2(A, i + j * n) * ld2(X, j * 64 + t);
+    st2(X, i * 64 + t, s);
+  }
+  for (int i = n - 1; i >= 0; --i) {  // U x = y
+    zd s = ld2(X, i * 64 + t);
+    for (int j = i + 1; j < n; ++j) s = s - ld2(A, i + j * n) * ld2(X, j * 64 + t);
+    st2(X, i * 64 + t, cdiv(s, ld2(A, i + i * n)));
+  }
+}
+
+// M^{-1} C and the 1-norm condition number of M.  With X (k x 64 LDS slots) every lane solves
+// its own columns (inverse columns, then columns of C); otherwise the wave solves one column at a
+// time with the vector spread over its lanes.
 __device__ __forceinline__ void lu_solve_body(const double2* __restrict__ M, int k,
                                               double2* __restrict__ C, int nrhs, double2* LU,
-                                              double* cond, int* piv) {
+                                              double2* X, double* cond, int* piv) {
   const int t = threadIdx.x;
   for (int i = t; i < k * k; i += NT) LU[i] = M[i];
   // 1-norm of M: largest column sum
@@ -223,23 +250,49 @@ __device__ __forceinline__ void lu_solve_body(const double2* __restrict__ M, int
   }
   // 1-norm of M^{-1}, one column at a time
   double ninv = 0;
-  for (int j = 0; j < k; ++j) {
-    WVec e{zd{t == j ? 1.0 : 0.0, 0.0}, zd{t + 64 == j ? 1.0 : 0.0, 0.0}};
-    lu_solve_wave(LU, k, k, piv, e);
-    const double s = wsum((t < k ? cabs_(e.a) : 0.0) + (t + 64 < k ? cabs_(e.b) : 0.0));
-    ninv = fmax(ninv, s);
+  if (X) {
+    for (int c0 = 0; c0 < k; c0 += 64) {
+      const int j = c0 + t;
+      if (j < k) {
+        for (int i = 0; i < k; ++i) X[i * 64 + t] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+        lu_solve_own(LU, k, piv, X, t);
+        double s = 0;
+        for (int i = 0; i < k; ++i) s += cabs_(ld2(X, i * 64 + t));
+        ninv = fmax(ninv, s);
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) ninv = fmax(ninv, __shfl_xor(ninv, o, 64));
+  } else {
+    for (int j = 0; j < k; ++j) {
+      WVec e{zd{t == j ? 1.0 : 0.0, 0.0}, zd{t + 64 == j ? 1.0 : 0.0, 0.0}};
+      lu_solve_wave(LU, k, k, piv, e);
+      const double s = wsum((t < k ? cabs_(e.a) : 0.0) + (t + 64 < k ? cabs_(e.b) : 0.0));
+      ninv = fmax(ninv, s);
+    }
   }
   if (t == 0) {
     const double c = n1 * ninv;
     *cond = isfinite(c) ? c : INFINITY;
   }
   // Y = M^{-1} C (solved with the factors for accuracy)
-  for (int j = 0; j < nrhs; ++j) {
-    double2* cj = C + j * k;
-    WVec b = wv_load(cj, k);
-    lu_solve_wave(LU, k, k, piv, b);
-    if (t < k) st2(cj, t, b.a);
-    if (t + 64 < k) st2(cj, t + 64, b.b);
+  if (X) {
+    for (int c0 = 0; c0 < nrhs; c0 += 64) {
+      const int j = c0 + t;
+      if (j < nrhs) {
+        double2* cj = C + j * k;
+        for (int i = 0; i < k; ++i) X[i * 64 + t] = cj[i];
+        lu_solve_own(LU, k, piv, X, t);
+        for (int i = 0; i < k; ++i) cj[i] = X[i * 64 + t];
+      }
+    }
+  } else {
+    for (int j = 0; j < nrhs; ++j) {
+      double2* cj = C + j * k;
+      WVec b = wv_load(cj, k);
+      lu_solve_wave(LU, k, k, piv, b);
+      if (t < k) st2(cj, t, b.a);
+      if (t + 64 < k) st2(cj, t + 64, b.b);
+    }
   }
 }
 
@@ -248,8 +301,9 @@ __global__ __launch_bounds__(NT) void k_lu_solve(const double2* __restrict__ M, 
                                                  double2* __restrict__ work, double* cond) {
   __shared__ double2 sh[LDS_CAP];
   __shared__ int piv[128];
-  if (k * k <= LDS_CAP) lu_solve_body(M, k, C, nrhs, sh, cond, piv);
-  else lu_solve_body(M, k, C, nrhs, work, cond, piv);
+  if (k * k + 64 * k <= LDS_CAP) lu_solve_body(M, k, C, nrhs, sh, sh + k * k, cond, piv);
+  else if (k * k <= LDS_CAP) lu_solve_body(M, k, C, nrhs, sh, nullptr, cond, piv);
+  else lu_solve_body(M, k, C, nrhs, work, nullptr, cond, piv);
 }
 
 // ----------------------------------------------------------------------------- eigenproblem
