@@ -356,10 +356,11 @@ __global__ __launch_bounds__(BL_BS) void k_xacc(VecSet vs, VecSet vs64, double2*
 }
 
 __global__ void k_mask_unselected(double2* __restrict__ Y, int k, int nrhs,
-                                  const RhsScal* __restrict__ sc) {
+                                  const RhsScal* __restrict__ sc, int reproj_only) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= k * nrhs) return;
-  if (!sc[i / k].sel) Y[i] = make_double2(0.0, 0.0);
+  const RhsScal& q = sc[i / k];
+  if (!q.sel || (reproj_only && !q.reproj)) Y[i] = make_double2(0.0, 0.0);
 }
 
 template <typename E>
@@ -430,9 +431,10 @@ void bicg_aux_f32(hipStream_t s, int op, const VecSet& vs32, const VecSet& vs64,
   else launch_fin_aux<AX_REPLACE>(s, vs32, sc, partials);
 }
 
-void mask_unselected_f64(hipStream_t s, double2* Y, int k, int nrhs, const RhsScal* sc) {
+void mask_unselected_f64(hipStream_t s, double2* Y, int k, int nrhs, const RhsScal* sc,
+                         bool reproj_only) {
   hipLaunchKernelGGL(k_mask_unselected, dim3((k * nrhs + 255) / 256), dim3(256), 0, s, Y, k, nrhs,
-                     sc);
+                     sc, reproj_only ? 1 : 0);
   DBQ_HIP(hipGetLastError());
 }
 

@@ -45,7 +45,7 @@ struct RhsScal {
   int nrel;        // FP64 residual replacements decided on the device (each one FP64 MVP)
   int since;       // iterations since the last residual replacement (mixed precision)
   int stalls;      // consecutive FP64 checks that found too little progress (mixed precision)
-  int pad;
+  int reproj;      // mixed precision: deflation projection again at each FP64 residual (host-set)
   double rr_prev;  // FP64 ||r||^2 at the previous check (mixed precision)
 };
 
@@ -189,8 +189,10 @@ void bicg_aux_f32(hipStream_t s, int op, const VecSet& vs32, const VecSet& vs64,
                   const double2* r64, float4* r, float4* rhat, float4* p, float4* v, float4* x32,
                   RhsScal* sc, double* partials);
 // x64 += widen(x32), x32 = 0 for rhs with sel != 0
-// Y[:, j] = 0 (k entries) for every rhs j < nrhs whose sel is clear (sc points at the first)
-void mask_unselected_f64(hipStream_t s, double2* Y, int k, int nrhs, const RhsScal* sc);
+// Y[:, j] = 0 (k entries) for every rhs j < nrhs whose sel is clear, or with reproj_only whose
+// reproj is clear as well (sc points at the first)
+void mask_unselected_f64(hipStream_t s, double2* Y, int k, int nrhs, const RhsScal* sc,
+                         bool reproj_only);
 void bicg_xacc(hipStream_t s, const VecSet& vs32, const VecSet& vs64, double2* x64, float4* x32,
                const RhsScal* sc);
 

@@ -536,7 +536,7 @@ namespace {
 // capture) ends the capture and the solve continues eagerly.
 struct LoopGraphs {
   struct G {
-    int n = 0;
+    int key = 0;
     hipGraphExec_t exec = nullptr;
     std::vector<dbq_ctx::GraphTimer> timers;
   };
@@ -563,9 +563,10 @@ struct LoopGraphs {
     c->schur_tmp = nullptr;
     c->schur_tmp_bytes = 0;
   }
-  // run a block of n iterations; returns the graph replayed, or null when it ran eagerly
+  // run a block of n iterations; returns the graph replayed, or null when it ran eagerly.  key
+  // names the block's launch sequence (its length and whatever else the caller varies)
   template <typename F>
-  const G* run(int n, F&& block) {
+  const G* run(int key, int n, F&& block) {
     if (!enabled || !warm) {
       block(n);
       warm = true;
@@ -573,9 +574,9 @@ struct LoopGraphs {
     }
     G* g = nullptr;
     for (auto& q : gs)
-      if (q->n == n) g = q.get();
+      if (q->key == key) g = q.get();
     if (!g) {
-      g = capture(n, block);
+      g = capture(key, n, block);
       if (!g) {
         enabled = false;
         block(n);
@@ -586,10 +587,10 @@ struct LoopGraphs {
     return g;
   }
   template <typename F>
-  G* capture(int n, F&& block) {
+  G* capture(int key, int n, F&& block) {
     if (!c->cap_stream) DBQ_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     std::unique_ptr<G> g(new G());
-    g->n = n;
+    g->key = key;
     const hipStream_t orig = c->stream;
     hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
@@ -735,7 +736,7 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
 
   std::vector<long long> mvb(NR, 0);
   std::vector<int> status(NR, DBQ_NOT_CONVERGED), restarts(NR, 0), relup(NR, 0);
-  std::vector<char> done(NR, 0), have_true(NR, 0), stalled(NR, 0);
+  std::vector<char> done(NR, 0), have_true(NR, 0), stalled(NR, 0), rescued(NR, 0);
   // FP32 iterations that produced a non-finite value: their FP32 correction is dropped, and
   // zero_start marks those whose FP64 solution is not finite either
   std::vector<char> discard(NR, 0), zero_start(NR, 0);
@@ -781,18 +782,25 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
   // ---- deflation: (U^H A V) y = U^H r0, x0 += V y with U = gamma5 V (roles swapped for A^H)
   bool any_defl = false;
   double* dcond = ws.get<double>(MAXLAT);
-  // DBQ_REPROJECT=1 (mixed precision only): the same projection is applied again to the FP64
-  // residual at every reliable update, with (U^H A V)^{-1} and W = A V kept from the start
+  // Mixed precision keeps W = A V (and forms (U^H A V)^{-1} when first needed) to apply the same
+  // projection again to the FP64 residual of an rhs whose FP32 recursion stalled, and from then
+  // on at each of its reliable updates, before a second stall gives it to the FP64 continuation.
+  // DBQ_REPROJECT=1 applies it to every rhs at every reliable update (measured: slower on the
+  // benchmark problem, where no rhs stalls)
   struct Reproj {
-    const double2 *left = nullptr, *right = nullptr, *W = nullptr;
-    double2 *Minv = nullptr, *C = nullptr, *Y = nullptr;
+    const double2 *left = nullptr, *right = nullptr, *W = nullptr, *M = nullptr;
+    double2 *Minv = nullptr, *C = nullptr, *Y = nullptr, *lw = nullptr;
     double* gwork = nullptr;
     size_t gw = 0;
+    bool inverted = false;
   };
   std::vector<Reproj> rp(nops);
   bool reproject = false;
   if (mixed)
     if (const char* e = std::getenv("DBQ_REPROJECT")) reproject = std::atoi(e) != 0;
+  // DBQ_STALL_REPROJECT=0 sends a stalled rhs straight to the FP64 continuation
+  bool rescue = mixed;
+  if (const char* e = std::getenv("DBQ_STALL_REPROJECT")) rescue = mixed && std::atoi(e) != 0;
   for (int i = 0; i < nops; ++i) {
     const int k = kk[i];
     if (k == 0) continue;
@@ -818,22 +826,18 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
     gram_f64(s, Vp, n, k, W, n, k, n, V, dagger ? 0 : 1, M, gwork, gw);
     gram_f64(s, Vp, n, k, r64 + o, n, nrhs[i], n, V, dagger ? 0 : 1, Cm, gwork, gw);
     double2* lw = ws.get<double2>(2 * k * k + k);
-    if (reproject) {
+    if (reproject || rescue) {
       Reproj& R = rp[i];
       R.left = Vp;
       R.right = Vp;
       R.W = W;
+      R.M = M;
+      R.lw = ws.get<double2>(2 * k * k + k);
       R.Minv = ws.get<double2>(size_t(k) * k);
       R.C = ws.get<double2>(size_t(k) * nrhs[i]);
       R.Y = ws.get<double2>(size_t(k) * nrhs[i]);
       R.gwork = gwork;
       R.gw = gw;
-      std::vector<double2> id(size_t(k) * k, make_double2(0.0, 0.0));
-      for (int q = 0; q < k; ++q) id[q + size_t(q) * k] = make_double2(1.0, 0.0);
-      DBQ_HIP(hipMemcpyAsync(R.Minv, id.data(), sizeof(double2) * id.size(),
-                             hipMemcpyHostToDevice, s));
-      DBQ_HIP(hipStreamSynchronize(s));
-      dense_lu_solve(s, M, k, R.Minv, k, lw, dcond + i);
     }
     dense_lu_solve(s, M, k, Cm, nrhs[i], lw, dcond + i);
     combine_f64(s, Vp, n, k, Cm, k, x64 + o, n, nrhs[i], n, V, dagger ? 1 : 0, 1);
@@ -979,23 +983,42 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
     if (const char* e = std::getenv("DBQ_RELUP_EVERY")) every = std::max(1, std::atoi(e));
     DsBatch bres_dec = bres;
     bres_dec.decide = 1;
+    // (U^H A V)^{-1}, formed when first needed (outside any captured block)
+    auto invert = [&]() {
+      for (int i = 0; i < nops; ++i) {
+        Reproj& R = rp[i];
+        if (!R.W || R.inverted) continue;
+        const int k = kk[i];
+        std::vector<double2> id(size_t(k) * k, make_double2(0.0, 0.0));
+        for (int q = 0; q < k; ++q) id[q + size_t(q) * k] = make_double2(1.0, 0.0);
+        DBQ_HIP(hipMemcpyAsync(R.Minv, id.data(), sizeof(double2) * id.size(),
+                               hipMemcpyHostToDevice, s));
+        DBQ_HIP(hipStreamSynchronize(s));
+        dense_lu_solve(s, R.M, k, R.Minv, k, R.lw, dcond + i);
+        R.inverted = true;
+      }
+    };
+    if (reproject) invert();
+    // y = (U^H A V)^{-1} U^H r for the selected rhs (with flagged_only, those with reproj set),
+    // x += V y, r -= W y (FP64; no products)
+    bool any_reproj = false;
+    auto project_sel = [&](bool flagged_only) {
+      for (int i = 0; i < nops; ++i) {
+        const Reproj& R = rp[i];
+        if (!R.W) continue;
+        const int k = kk[i];
+        const long long n = op[i].n(), V = op[i].sites(), o = off64[base[i]];
+        gram_f64(s, R.left, n, k, r64 + o, n, nrhs[i], n, V, dagger ? 0 : 1, R.C, R.gwork, R.gw);
+        combine_f64(s, R.Minv, k, k, R.C, k, R.Y, k, nrhs[i], k, 1, 0, 0);
+        mask_unselected_f64(s, R.Y, k, nrhs[i], sc + base[i], flagged_only);
+        combine_f64(s, R.right, n, k, R.Y, k, x64 + o, n, nrhs[i], n, V, dagger ? 1 : 0, 1);
+        combine_f64(s, R.W, n, k, R.Y, k, r64 + o, n, nrhs[i], n, V, 0, -1);
+      }
+    };
     auto relup_dev = [&]() {
       bicg_xacc(s, vs32, vs64, x64, x32, sc);
       run_dslash(c, false, bres_dec, dagger, EPI_RESID, sc, partials);
-      if (reproject)
-        for (int i = 0; i < nops; ++i) {
-          const Reproj& R = rp[i];
-          if (!R.W) continue;
-          const int k = kk[i];
-          const long long n = op[i].n(), V = op[i].sites(), o = off64[base[i]];
-          // y = (U^H A V)^{-1} U^H r for the rhs that continue (sel), x += V y, r -= W y
-          gram_f64(s, R.left, n, k, r64 + o, n, nrhs[i], n, V, dagger ? 0 : 1, R.C, R.gwork,
-                   R.gw);
-          combine_f64(s, R.Minv, k, k, R.C, k, R.Y, k, nrhs[i], k, 1, 0, 0);
-          mask_unselected_f64(s, R.Y, k, nrhs[i], sc + base[i]);
-          combine_f64(s, R.right, n, k, R.Y, k, x64 + o, n, nrhs[i], n, V, dagger ? 1 : 0, 1);
-          combine_f64(s, R.W, n, k, R.Y, k, r64 + o, n, nrhs[i], n, V, 0, -1);
-        }
+      if (reproject || any_reproj) project_sel(!reproject);
       bicg_aux_f32(s, AX_REPLACE, vs32, vs64, r64, r32, rhat32, p32, v32, x32, sc, partials);
     };
     auto block = [&](int n) {
@@ -1017,7 +1040,7 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
       if (replayed && c->timing) graph_timers_add(c, replayed->timers);
       replayed = nullptr;
       trace();
-      std::vector<int> Bk, Cc;
+      std::vector<int> Bk, Cc, Rs;
       bool live = false;
       for (int j = 0; j < NR; ++j) {
         if (done[j]) continue;
@@ -1029,10 +1052,17 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
           rrt[j] = q.rr_true;
           have_true[j] = 1;
         } else if (q.flags & F_STALL) {
-          done[j] = 1;
-          stalled[j] = 1;
-          rrt[j] = q.rr_true;
-          have_true[j] = 1;
+          if (rescue && !rescued[j] && rp[lat_of[j]].W) {
+            // first stall: the deflation projection again, then FP32 from there with the
+            // projection repeated at each FP64 residual of this rhs (a second stall hands it to
+            // the FP64 continuation)
+            Rs.push_back(j);
+          } else {
+            done[j] = 1;
+            stalled[j] = 1;
+            rrt[j] = q.rr_true;
+            have_true[j] = 1;
+          }
         } else if (q.flags & F_NAN) {
           // continued in FP64 like a stall, from the last accumulated solution
           done[j] = 1;
@@ -1059,6 +1089,27 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
         }
         if (Bk.empty()) push();
       }
+      if (!Rs.empty()) {
+        // r64 holds the stalled rhs' FP64 residual of that check and x64 its solution
+        for (int j = 0; j < NR; ++j)
+          if (!done[j]) hs[j].sel = 0;
+        for (int j : Rs) {
+          hs[j].sel = 1;
+          hs[j].flags = 0;
+          hs[j].stalls = 0;
+          hs[j].reproj = 1;
+          rescued[j] = 1;
+        }
+        any_reproj = true;
+        push();
+        invert();
+        project_sel(false);
+        bicg_aux_f32(s, AX_REPLACE, vs32, vs64, r64, r32, rhat32, p32, v32, x32, sc, partials);
+        pull();
+        for (int j : Rs) hs[j].rr_prev = hs[j].rr;  // the next check compares with this residual
+        push();
+        live = true;
+      }
       if (!Bk.empty()) {
         restart(Bk);
         live = true;
@@ -1067,7 +1118,7 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
       nchk = (Bk.empty() && Cc.empty()) ? std::min(nchk * 2, std::max(32, every)) : every;
       // every poll comes right after a reliable-update block
       nchk = ((nchk + every - 1) / every) * every;
-      replayed = graphs.run(nchk, block);
+      replayed = graphs.run(2 * nchk + (any_reproj ? 1 : 0), nchk, block);
     }
     for (int j = 0; j < NR; ++j)
       if (!done[j])

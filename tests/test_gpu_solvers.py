@@ -183,12 +183,17 @@ def test_dbicgstab_mixed_reaches_fp64_residual(gpu_lib):
         assert err <= 1e-6
 
 
-def test_dbicgstab_mixed_past_kappa_c_at_c1(gpu_lib, c1_vectors, capsys):
+@pytest.mark.parametrize("stall_reproject", ["1", "0"])
+def test_dbicgstab_mixed_past_kappa_c_at_c1(gpu_lib, c1_vectors, capsys, monkeypatch,
+                                            stall_reproject):
     """C1 as configured: kappa = 0.15 lies past kappa_c (about 0.140 for this field), so A has
     eigenvalues with negative real part.  Mixed-precision D-BiCGStab(6) with the oracle's
     GMRES-DR(20,6) vectors on the three Z2 sources: every solution meets 1e-8 on the oracle's
     FP64 residual, and the library's reported residual agrees with it.  Which sources the FP32
-    recursion finished and which the FP64 continuation finished is printed."""
+    recursion finished and which the FP64 continuation finished is printed.  The FP32 recursion
+    stalls here, so both ways of handling a first stall run: the deflation projection applied
+    again before FP32 resumes (default, "1"), and straight to the FP64 continuation ("0")."""
+    monkeypatch.setenv("DBQ_STALL_REPROJECT", stall_reproject)
     L, lat, U = _c1()
     B = synth.z2_sources(L, 3, 1101)
     Vt = dev(c1_vectors.T.reshape(-1, lat.V, 4, 3))
@@ -199,7 +204,8 @@ def test_dbicgstab_mixed_past_kappa_c_at_c1(gpu_lib, c1_vectors, capsys):
     for j in range(3):
         rel = _true_rel(U, lat, 0.15, 0.0, Xg[j].reshape(-1), B[j].reshape(-1))
         with capsys.disabled():
-            print(f"\n  [C1 kappa 0.15 mixed rhs {j}: {st[j]['matvecs']} MVPs, "
+            print(f"\n  [C1 kappa 0.15 mixed (stall reprojection {stall_reproject}) rhs {j}: "
+                  f"{st[j]['matvecs']} MVPs, "
                   f"{st[j]['reliable_updates']} reliable updates, fp64_continued "
                   f"{st[j]['fp64_continued']}, oracle residual {rel:.2e}]", flush=True)
         assert st[j]["status"] == 0 and rel <= 1.0001e-8
