@@ -19,6 +19,7 @@ namespace {
 
 template <typename E>
 struct ET;
+typedef float f4v __attribute__((ext_vector_type(4)));
 template <>
 struct ET<double2> {
   typedef double R;
@@ -29,6 +30,13 @@ struct ET<double2> {
   }
   __device__ __forceinline__ static void st(double2* p, long long i, const zd (&z)[1]) {
     p[i] = make_double2(z[0].re, z[0].im);
+  }
+  // FP64 single-rhs working sets stay in the last-level cache: no hint
+  __device__ __forceinline__ static void ld_last(const double2* p, long long i, zd (&z)[1]) {
+    ld(p, i, z);
+  }
+  __device__ __forceinline__ static void st_far(double2* p, long long i, const zd (&z)[1]) {
+    st(p, i, z);
   }
 };
 template <>
@@ -42,6 +50,18 @@ struct ET<float4> {
   }
   __device__ __forceinline__ static void st(float4* p, long long i, const zf (&z)[2]) {
     p[i] = make_float4(z[0].re, z[0].im, z[1].re, z[1].im);
+  }
+  // Non-temporal variants for operands this iteration does not read again (ld_last) or reads
+  // only in the next XR pass (x, st_far): with 12 rhs the seven vectors of the FP32 recursion
+  // exceed the last-level cache, and these hints leave it to the vectors read soon after.
+  __device__ __forceinline__ static void ld_last(const float4* p, long long i, zf (&z)[2]) {
+    const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p + i));
+    z[0] = zf{v.x, v.y};
+    z[1] = zf{v.z, v.w};
+  }
+  __device__ __forceinline__ static void st_far(float4* p, long long i, const zf (&z)[2]) {
+    __builtin_nontemporal_store(f4v{z[0].re, z[0].im, z[1].re, z[1].im},
+                                reinterpret_cast<f4v*>(p + i));
   }
 };
 
@@ -155,11 +175,11 @@ __global__ __launch_bounds__(BL_BS) void k_bicg_step(VecSet vs, E* __restrict__ 
           ET<E>::st(r, i, rr);
         } else {
           cx<R> xx[NC], pp[NC], ss[NC], tt[NC], vv[NC];
-          ET<E>::ld(x, i, xx);
+          ET<E>::ld_last(x, i, xx);
           ET<E>::ld(p, i, pp);
           ET<E>::ld(r, i, ss);
-          ET<E>::ld(t, i, tt);
-          ET<E>::ld(v, i, vv);
+          ET<E>::ld_last(t, i, tt);
+          ET<E>::ld_last(v, i, vv);
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
             xx[c] = xx[c] + al * pp[c] + om * ss[c];
@@ -168,7 +188,7 @@ __global__ __launch_bounds__(BL_BS) void k_bicg_step(VecSet vs, E* __restrict__ 
             const double br = double(ss[c].re), bi = double(ss[c].im);
             red[2] += br * br + bi * bi;
           }
-          ET<E>::st(x, i, xx);
+          ET<E>::st_far(x, i, xx);
           ET<E>::st(r, i, ss);
           ET<E>::st(p, i, pp);
         }

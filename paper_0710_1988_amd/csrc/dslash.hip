@@ -80,6 +80,14 @@ __device__ __forceinline__ void st_nt(float4* p, const float4& v) {
 __device__ __forceinline__ void st_nt(double2* p, const double2& v) {
   __builtin_nontemporal_store(nv_d2{v.x, v.y}, reinterpret_cast<nv_d2*>(p));
 }
+// A load with the non-temporal hint, for operands read once per iteration (the epilogue's
+// rhat), so that they do not displace the search vectors the next launches read again from the
+// L2 and the last-level cache.
+__device__ __forceinline__ float4 ld_nt(const float4* __restrict__ base, unsigned byte_off) {
+  const nv_f4 v = __builtin_nontemporal_load(
+      reinterpret_cast<const nv_f4*>(reinterpret_cast<const char*>(base) + byte_off));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
 template <typename E>
 __device__ __forceinline__ void sto(E* __restrict__ base, unsigned byte_off, const E& v) {
   E* p = reinterpret_cast<E*>(reinterpret_cast<char*>(base) + byte_off);
@@ -147,6 +155,16 @@ struct IO<float> {
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       const float4 v = ldo(b + (long long)k * V, o);
+      p[2 * k] = zf{v.x, v.y};
+      p[2 * k + 1] = zf{v.z, v.w};
+    }
+  }
+  __device__ __forceinline__ static void load_nt(const float4* __restrict__ b, int V, int s,
+                                                 zf (&p)[12]) {
+    const unsigned o = unsigned(s) * 16u;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const float4 v = ld_nt(b + (long long)k * V, o);
       p[2 * k] = zf{v.x, v.y};
       p[2 * k + 1] = zf{v.z, v.w};
     }
@@ -1014,7 +1032,7 @@ __global__ __launch_bounds__(DS_BS) void k_dslash_tile(DsBatch B, RhsScal* __res
     const int jn = next(j + 1);
     zf ax[12];
     if (own && EPI != EPI_NONE)
-      IO<float>::load((const float4*)L.aux + (long long)r * 6 * V, V, s, ax);
+      IO<float>::load_nt((const float4*)L.aux + (long long)r * 6 * V, V, s, ax);
     double red[DS_NSUM];
 #pragma unroll
     for (int i = 0; i < DS_NSUM; ++i) red[i] = 0.0;
@@ -1253,7 +1271,7 @@ __global__ __launch_bounds__(TH_BS) void k_dslash_tile_half(DsBatch B, RhsScal* 
       // halves the resident waves
       asm volatile("" ::: "memory");
       if (STEP == 2 && EPI != EPI_NONE)
-        IO<float>::load((const float4*)L.aux + (long long)r * 6 * Vh, Vh, h, ax);
+        IO<float>::load_nt((const float4*)L.aux + (long long)r * 6 * Vh, Vh, h, ax);
       zf o[12];
       if (STEP == 1) finish_odd<float>(ce, acc, coef, tm, o);
       else
