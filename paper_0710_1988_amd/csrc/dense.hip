@@ -5,7 +5,7 @@
 //
 // Every phase works on a copy in LDS where it fits: one shared area of 97 x 96 complex entries
 // (145.5 KiB), reused phase by phase, holds the (m+1) x m least-squares matrix (m <= 96), then the
-// m x m matrix of the eigenproblem (m <= 96) together with its Schur vectors (m <= 68), then the
+// m x m matrix of the eigenproblem (m <= 96) together with its Schur vectors (m <= 67), then the
 // restart basis and Hbar times it.  Larger problems use the same code on the global scratch area
 // (resident in L2).  The 64 lanes share every step: vectors that one lane would otherwise walk
 // serially (pivot search, triangular solves, eigenvectors of the triangular factor) are held one
@@ -310,13 +310,13 @@ __global__ __launch_bounds__(NT) void k_lu_solve(const double2* __restrict__ M, 
 // Householder reduction of G (n x n, ld n) to upper Hessenberg form.  Reflector j (acting on rows
 // and columns j+1..n-1) is kept below the subdiagonal of column j, its first entry in w0s[j] and
 // its factor in fs[j] (0: identity), for form_q; the caller zeroes that part afterwards.
-__device__ __forceinline__ void hessenberg(double2* G, int n, double2* v, double2* w0s, double* fs) {
+__device__ __forceinline__ void hessenberg(double2* G, int n, int ld, double2* v, double2* w0s, double* fs) {
   const int t = threadIdx.x;
   for (int j = 0; j + 2 < n; ++j) {
     const int len = n - j - 1;
     double p = 0;
     for (int i = t; i < len; i += NT) {
-      const double2 x = G[(j + 1 + i) + j * n];
+      const double2 x = G[(j + 1 + i) + j * ld];
       p += x.x * x.x + x.y * x.y;
       v[i] = x;
     }
@@ -331,40 +331,40 @@ __device__ __forceinline__ void hessenberg(double2* G, int n, double2* v, double
     }
     if (nx2 == 0.0) continue;
     // left: rows j+1.., columns j..n-1
-    for (int c = j + t; c < n; c += NT) reflect_col(G + c * n + j + 1, v, w0, len, f);
+    for (int c = j + t; c < n; c += NT) reflect_col(G + c * ld + j + 1, v, w0, len, f);
     wave_sync();
     // right: all rows, columns j+1..n-1
     for (int r = t; r < n; r += NT) {
-      double2* row = G + r + (j + 1) * n;
+      double2* row = G + r + (j + 1) * ld;
       zd s = ld2(row, 0) * w0;
 #pragma unroll 4
-      for (int i = 1; i < len; ++i) s = s + ld2(row, i * n) * ld2(v, i);
+      for (int i = 1; i < len; ++i) s = s + ld2(row, i * ld) * ld2(v, i);
       s = f * s;
       st2(row, 0, ld2(row, 0) - s * conj(w0));
 #pragma unroll 4
       for (int i = 1; i < len; ++i)
-        st2(row, i * n, ld2(row, i * n) - s * conj(ld2(v, i)));
+        st2(row, i * ld, ld2(row, i * ld) - s * conj(ld2(v, i)));
     }
     wave_sync();
-    for (int i = 1 + t; i < len; i += NT) G[(j + 1 + i) + j * n] = v[i];
+    for (int i = 1 + t; i < len; i += NT) G[(j + 1 + i) + j * ld] = v[i];
     wave_sync();
   }
 }
 
 // Q = H_0 H_1 ... H_{n-3} (so that G_in = Q G_out Q^H), accumulated backwards (Q <- H_j Q), one
 // column per lane: no lane reads another lane's column, so no barriers.
-__device__ __forceinline__ void form_q(const double2* G, int n, const double2* w0s,
+__device__ __forceinline__ void form_q(const double2* G, int n, int ld, const double2* w0s,
                                        const double* fs, double2* Q) {
   const int t = threadIdx.x;
   for (int c = t; c < n; c += NT) {
-    double2* qc = Q + c * n;
+    double2* qc = Q + c * ld;
     for (int r = 0; r < n; ++r) qc[r] = make_double2(r == c ? 1.0 : 0.0, 0.0);
     for (int j = min(n - 3, c - 1); j >= 0; --j) {
       const double f = fs[j];
       if (f == 0.0) continue;
       const int len = n - j - 1;
       const zd w0 = ld2(w0s, j);
-      const double2* w = G + j * n + j + 1;  // w[i], i >= 1
+      const double2* w = G + j * ld + j + 1;  // w[i], i >= 1
       double2* col = qc + j + 1;
       zd s = cmulc(w0, ld2(col, 0));
 #pragma unroll 4
@@ -384,7 +384,7 @@ __device__ __forceinline__ void form_q(const double2* G, int n, const double2* w
 // rotates the two rows, wave 1 the two columns, wave 3 the 2 x 2 block where both act, and waves
 // 2 and 3 the Schur vectors (zlds, Z in LDS).  Otherwise the sweep's rotations are recorded (rc,
 // rs) and applied to the rows of Z after the sweep.  Returns false if it did not converge.
-__device__ __forceinline__ bool schur(double2* G, double2* Z, int n, bool zlds, double* rc,
+__device__ __forceinline__ bool schur(double2* G, double2* Z, int n, int ld, bool zlds, double* rc,
                                       double2* rs) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const double eps = DBL_EPSILON;
@@ -396,14 +396,14 @@ __device__ __forceinline__ bool schur(double2* G, double2* Z, int n, bool zlds, 
       const int q = qb + lane;
       bool neg = false;
       if (q >= 1 && q <= hi) {
-        const double sd = nrm1(ld2(G, (q - 1) + (q - 1) * n)) + nrm1(ld2(G, q + q * n));
-        neg = nrm1(ld2(G, q + (q - 1) * n)) <= eps * (sd > 0 ? sd : 1e-300);
+        const double sd = nrm1(ld2(G, (q - 1) + (q - 1) * ld)) + nrm1(ld2(G, q + q * ld));
+        neg = nrm1(ld2(G, q + (q - 1) * ld)) <= eps * (sd > 0 ? sd : 1e-300);
       }
       const unsigned long long mask = __ballot(neg);
       if (mask) l = qb + 63 - __clzll(mask);
     }
     __syncthreads();  // every wave has read the entry before it is zeroed
-    if (l > 0 && tid == 0) G[l + (l - 1) * n] = make_double2(0.0, 0.0);
+    if (l > 0 && tid == 0) G[l + (l - 1) * ld] = make_double2(0.0, 0.0);
     if (l == hi) {
       --hi;
       iter = 0;
@@ -413,8 +413,8 @@ __device__ __forceinline__ bool schur(double2* G, double2* Z, int n, bool zlds, 
     // shift (every thread computes it)
     zd mu;
     {
-      const zd a = ld2(G, (hi - 1) + (hi - 1) * n), b = ld2(G, (hi - 1) + hi * n);
-      const zd c = ld2(G, hi + (hi - 1) * n), d = ld2(G, hi + hi * n);
+      const zd a = ld2(G, (hi - 1) + (hi - 1) * ld), b = ld2(G, (hi - 1) + hi * ld);
+      const zd c = ld2(G, hi + (hi - 1) * ld), d = ld2(G, hi + hi * ld);
       if (iter > 0 && iter % 11 == 0) {
         mu = d + zd{fabs(c.re) + fabs(c.im), 0.0};  // exceptional shift
       } else {
@@ -432,11 +432,11 @@ __device__ __forceinline__ bool schur(double2* G, double2* Z, int n, bool zlds, 
     for (int kk = l; kk < hi; ++kk) {
       zd x, y;
       if (kk == l) {
-        x = ld2(G, l + l * n) - mu;
-        y = ld2(G, (l + 1) + l * n);
+        x = ld2(G, l + l * ld) - mu;
+        y = ld2(G, (l + 1) + l * ld);
       } else {
-        x = ld2(G, kk + (kk - 1) * n);
-        y = ld2(G, (kk + 1) + (kk - 1) * n);
+        x = ld2(G, kk + (kk - 1) * ld);
+        y = ld2(G, (kk + 1) + (kk - 1) * ld);
       }
       // c = |x| / rho, s = (x / |x|) conj(y) / rho, rho = sqrt(|x|^2 + |y|^2) (entries far from
       // the range limits: no hypot-style scaling)
@@ -465,34 +465,34 @@ __device__ __forceinline__ bool schur(double2* G, double2* Z, int n, bool zlds, 
       if (wv == 0) {
         for (int q = lane; q < n; q += 64)
           if (q >= j0 && q != kk && q != kk + 1) {
-            const zd a = ld2(G, kk + q * n), b = ld2(G, (kk + 1) + q * n);
-            st2(G, kk + q * n, c * a + s * b);
-            st2(G, (kk + 1) + q * n, q == kk - 1 ? zd{0.0, 0.0} : c * b - conj(s) * a);
+            const zd a = ld2(G, kk + q * ld), b = ld2(G, (kk + 1) + q * ld);
+            st2(G, kk + q * ld, c * a + s * b);
+            st2(G, (kk + 1) + q * ld, q == kk - 1 ? zd{0.0, 0.0} : c * b - conj(s) * a);
           }
       } else if (wv == 1) {
         for (int q = lane; q <= rmax; q += 64)
           if (q != kk && q != kk + 1) {
-            const zd a = ld2(G, q + kk * n), b = ld2(G, q + (kk + 1) * n);
-            st2(G, q + kk * n, c * a + conj(s) * b);
-            st2(G, q + (kk + 1) * n, c * b - s * a);
+            const zd a = ld2(G, q + kk * ld), b = ld2(G, q + (kk + 1) * ld);
+            st2(G, q + kk * ld, c * a + conj(s) * b);
+            st2(G, q + (kk + 1) * ld, c * b - s * a);
           }
       } else {
         if (wv == 3 && lane == 0) {
-          const zd a11 = ld2(G, kk + kk * n), a12 = ld2(G, kk + (kk + 1) * n);
-          const zd a21 = ld2(G, (kk + 1) + kk * n), a22 = ld2(G, (kk + 1) + (kk + 1) * n);
+          const zd a11 = ld2(G, kk + kk * ld), a12 = ld2(G, kk + (kk + 1) * ld);
+          const zd a21 = ld2(G, (kk + 1) + kk * ld), a22 = ld2(G, (kk + 1) + (kk + 1) * ld);
           const zd b11 = c * a11 + s * a21, b12 = c * a12 + s * a22;
           const zd b21 = c * a21 - conj(s) * a11, b22 = c * a22 - conj(s) * a12;
-          st2(G, kk + kk * n, c * b11 + conj(s) * b12);
-          st2(G, kk + (kk + 1) * n, c * b12 - s * b11);
-          st2(G, (kk + 1) + kk * n, c * b21 + conj(s) * b22);
-          st2(G, (kk + 1) + (kk + 1) * n, c * b22 - s * b21);
+          st2(G, kk + kk * ld, c * b11 + conj(s) * b12);
+          st2(G, kk + (kk + 1) * ld, c * b12 - s * b11);
+          st2(G, (kk + 1) + kk * ld, c * b21 + conj(s) * b22);
+          st2(G, (kk + 1) + (kk + 1) * ld, c * b22 - s * b21);
         }
         if (zlds) {
           const int q = (wv - 2) * 64 + lane;
           if (q < n) {
-            const zd a = ld2(Z, q + kk * n), b = ld2(Z, q + (kk + 1) * n);
-            st2(Z, q + kk * n, c * a + conj(s) * b);
-            st2(Z, q + (kk + 1) * n, c * b - s * a);
+            const zd a = ld2(Z, q + kk * ld), b = ld2(Z, q + (kk + 1) * ld);
+            st2(Z, q + kk * ld, c * a + conj(s) * b);
+            st2(Z, q + (kk + 1) * ld, c * b - s * a);
           }
         } else if (wv == 2 && lane == 0) {
           rc[kk] = c;
@@ -505,23 +505,23 @@ __device__ __forceinline__ bool schur(double2* G, double2* Z, int n, bool zlds, 
       // the sweep's rotations on the rows of Z: column kk is final after rotation kk, column
       // kk+1 carried to the next one; the untouched columns are loaded ahead in groups of 16
       for (int r = tid; r < n; r += blockDim.x) {
-        zd za = ld2(Z, r + l * n);
+        zd za = ld2(Z, r + l * ld);
         for (int kb = l; kb < hi; kb += 16) {
           const int cnt = hi - kb < 16 ? hi - kb : 16;
           zd zb[16];
 #pragma unroll
           for (int u = 0; u < 16; ++u)
-            if (u < cnt) zb[u] = ld2(Z, r + (kb + 1 + u) * n);
+            if (u < cnt) zb[u] = ld2(Z, r + (kb + 1 + u) * ld);
 #pragma unroll
           for (int u = 0; u < 16; ++u)
             if (u < cnt) {
               const double cc = rc[kb + u];
               const zd ss = ld2(rs, kb + u);
-              st2(Z, r + (kb + u) * n, cc * za + conj(ss) * zb[u]);
+              st2(Z, r + (kb + u) * ld, cc * za + conj(ss) * zb[u]);
               za = cc * zb[u] - ss * za;
             }
         }
-        st2(Z, r + hi * n, za);
+        st2(Z, r + hi * ld, za);
       }
     }
     ++iter;
@@ -534,19 +534,19 @@ __device__ __forceinline__ bool schur(double2* G, double2* Z, int n, bool zlds, 
 // Eigenvector of the upper-triangular T (n x n) for diagonal position q, y with y_q = 1 and
 // y_j = 0 above q, solved backwards column by column across the wave; returns g = Z y normalised
 // in out[0..n) (column of ld-strided storage) and writes out[n] = 0 when pad.
-__device__ __forceinline__ void tri_eigvec(const double2* T, const double2* Z, int n, int q,
+__device__ __forceinline__ void tri_eigvec(const double2* T, const double2* Z, int n, int ld, int q,
                                            double tnorm, double2* out, bool pad) {
   const int t = threadIdx.x & 63;
-  const zd th = ld2(T, q + q * n);
+  const zd th = ld2(T, q + q * ld);
   const double small = fmax(DBL_EPSILON * tnorm, 1e-300);
   WVec acc{zd{0.0, 0.0}, zd{0.0, 0.0}};
   WVec y{zd{0.0, 0.0}, zd{0.0, 0.0}};
   wv_set(y, q, zd{1.0, 0.0});
   zd yj{1.0, 0.0};
   for (int j = q; j >= 1; --j) {
-    if (t < j) acc.a = acc.a + ld2(T, t + j * n) * yj;
-    if (t + 64 < j) acc.b = acc.b + ld2(T, t + 64 + j * n) * yj;
-    zd d = ld2(T, (j - 1) + (j - 1) * n) - th;
+    if (t < j) acc.a = acc.a + ld2(T, t + j * ld) * yj;
+    if (t + 64 < j) acc.b = acc.b + ld2(T, t + 64 + j * ld) * yj;
+    zd d = ld2(T, (j - 1) + (j - 1) * ld) - th;
     if (cabs_(d) < small) d = zd{small, 0.0};
     yj = -cdiv(wv_get(acc, j - 1), d);
     wv_set(y, j - 1, yj);
@@ -560,7 +560,7 @@ __device__ __forceinline__ void tri_eigvec(const double2* T, const double2* Z, i
     if (slot * 64 < n)
       for (int j = 0; j <= q; ++j) {
         const zd yv = wv_get(y, j);
-        if (r < n) s = s + ld2(Z, r + j * n) * yv;
+        if (r < n) s = s + ld2(Z, r + j * ld) * yv;
       }
     g[slot] = s;
     if (r < n) nn += norm2(s);
@@ -637,58 +637,58 @@ __device__ __forceinline__ double phase_ls(const CycleArgs& a, double2* QR, doub
 
 // harmonic Ritz matrix G = H_m + |h_{m+1,m}|^2 f e_m^T with H_m^H f = e_m (Bm: m x m area that
 // G then overwrites), or the Ritz matrix G = H_m (mode 2)
-__device__ __forceinline__ void phase_g(const CycleArgs& a, double2* G, int* piv) {
+__device__ __forceinline__ void phase_g(const CycleArgs& a, double2* G, int ld, int* piv) {
   const int t = threadIdx.x, m = a.m, m1 = m + 1;
   const double2* H = a.Hbar;
   WVec f{zd{0.0, 0.0}, zd{0.0, 0.0}};
   if (a.mode != 2) {
     for (int i = t; i < m * m; i += NT) {
       const int r = i % m, c = i / m;
-      st2(G, i, conj(ld2(H, c + r * m1)));
+      st2(G, r + c * ld, conj(ld2(H, c + r * m1)));
     }
     wave_sync();
-    lu_wave(G, m, m, piv);
+    lu_wave(G, m, ld, piv);
     wv_set(f, m - 1, zd{1.0, 0.0});
-    lu_solve_wave(G, m, m, piv, f);
+    lu_solve_wave(G, m, ld, piv, f);
     wave_sync();
   }
   for (int i = t; i < m * m; i += NT) {
     const int r = i % m, c = i / m;
-    G[i] = H[r + c * m1];
+    G[r + c * ld] = H[r + c * m1];
   }
   wave_sync();
   if (a.mode != 2) {
     const double h2 = norm2(ld2(H, m + (m - 1) * m1));
-    if (t < m) st2(G, t + (m - 1) * m, ld2(G, t + (m - 1) * m) + h2 * f.a);
+    if (t < m) st2(G, t + (m - 1) * ld, ld2(G, t + (m - 1) * ld) + h2 * f.a);
     if (t + 64 < m)
-      st2(G, t + 64 + (m - 1) * m, ld2(G, t + 64 + (m - 1) * m) + h2 * f.b);
+      st2(G, t + 64 + (m - 1) * ld, ld2(G, t + 64 + (m - 1) * ld) + h2 * f.b);
     wave_sync();
   }
 }
 
 // Hessenberg form of G (m x m) and the Q of the reduction in Z (one wave)
-__device__ __forceinline__ void phase_hess(const CycleArgs& a, double2* G, double2* Z, double2* v,
+__device__ __forceinline__ void phase_hess(const CycleArgs& a, double2* G, double2* Z, int ld, double2* v,
                                            double2* w0s, double* fs) {
   const int t = threadIdx.x, m = a.m;
-  hessenberg(G, m, v, w0s, fs);
-  form_q(G, m, w0s, fs, Z);
+  hessenberg(G, m, ld, v, w0s, fs);
+  form_q(G, m, ld, w0s, fs, Z);
   wave_sync();
   for (int c = t; c < m; c += NT)
-    for (int r = c + 2; r < m; ++r) G[r + c * m] = make_double2(0.0, 0.0);
+    for (int r = c + 2; r < m; ++r) G[r + c * ld] = make_double2(0.0, 0.0);
   wave_sync();
 }
 
 // eigenvalues of the Schur form T (in G) sorted into a.theta and order[]; returns the number of
 // vectors to keep (in every lane) and the largest |entry| of T in tn (one wave)
-__device__ __forceinline__ int phase_sort(const CycleArgs& a, const double2* G, int* order,
+__device__ __forceinline__ int phase_sort(const CycleArgs& a, const double2* G, int ld, int* order,
                                           int* s_kout, double& tn) {
   const int t = threadIdx.x, m = a.m, k = a.k;
   // sort: |theta| ascending (harmonic) or Re descending (Ritz), ties by (Re, Im, index)
   for (int i = t; i < m; i += NT) {
-    const zd ti = ld2(G, i + i * m);
+    const zd ti = ld2(G, i + i * ld);
     int rank = 0;
     for (int j = 0; j < m; ++j) {
-      const zd tj = ld2(G, j + j * m);
+      const zd tj = ld2(G, j + j * ld);
       bool less;
       if (a.mode != 2) {
         const double ai = cabs_(ti), aj = cabs_(tj);
@@ -701,12 +701,12 @@ __device__ __forceinline__ int phase_sort(const CycleArgs& a, const double2* G, 
     order[rank] = i;
   }
   wave_sync();
-  for (int i = t; i < m; i += NT) a.theta[i] = G[order[i] + order[i] * m];
+  for (int i = t; i < m; i += NT) a.theta[i] = G[order[i] + order[i] * ld];
   if (t == 0) {
     int kout = k;
     if (a.mode == 1 && k < m) {
-      const zd x = ld2(G, order[k - 1] + order[k - 1] * m);
-      const zd y = ld2(G, order[k] + order[k] * m);
+      const zd x = ld2(G, order[k - 1] + order[k - 1] * ld);
+      const zd y = ld2(G, order[k] + order[k] * ld);
       const double sc = cabs_(x);
       if (fabs(x.im) > 1e-3 * sc && cabs_(x - conj(y)) <= 1e-3 * sc) kout = k - 1;
     }
@@ -714,7 +714,7 @@ __device__ __forceinline__ int phase_sort(const CycleArgs& a, const double2* G, 
     a.info[1] = kout;
   }
   double mx = 0;
-  for (int i = t; i < m * m; i += NT) mx = fmax(mx, cabs_(ld2(G, i)));
+  for (int i = t; i < m * m; i += NT) mx = fmax(mx, cabs_(ld2(G, i % m + (i / m) * ld)));
   for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
   tn = mx;
   wave_sync();
@@ -766,12 +766,16 @@ __device__ __forceinline__ void phase_restart(const CycleArgs& a, double2* P, do
 __global__ __launch_bounds__(CY_BS) void k_cycle(CycleArgs a) {
   const int t = threadIdx.x, wv = t >> 6;
   const int m = a.m, m1 = m + 1, k = a.k;
+  // the eigenproblem's matrices (G, its Schur vectors Z) are stored with an odd leading
+  // dimension: a lane per column then walks LDS at an odd multiple of 16 bytes, which spreads a
+  // wave's accesses over all banks (a stride of m = 64 or 96 entries would hit one bank group)
+  const int ld = m | 1;
   // global scratch for what does not fit in LDS
   double2* w = a.work;
   double2* wA = w;                 // (m+1) x m
-  double2* wG = wA + m1 * m;       // m x m
-  double2* wZ = wG + m * m;        // m x m
-  double2* wT1 = wZ + m * m;       // (m+1) x m
+  double2* wG = wA + m1 * m;       // m x m, ld
+  double2* wZ = wG + m * ld;       // m x m, ld
+  double2* wT1 = wZ + m * ld;      // (m+1) x m
   __shared__ double2 sh[LDS_CAP];
   __shared__ double2 v[129];
   __shared__ double2 gr[129];      // c transformed by the least squares, then rho
@@ -781,7 +785,7 @@ __global__ __launch_bounds__(CY_BS) void k_cycle(CycleArgs a) {
   __shared__ int order[128];
   __shared__ int s_kout, s_exit;
   __shared__ double s_tn;
-  const bool g_lds = m * m <= LDS_CAP, z_lds = 2 * m * m <= LDS_CAP;
+  const bool g_lds = m * ld <= LDS_CAP, z_lds = 2 * m * ld <= LDS_CAP;
 
   // ---- wave 0: least squares, the eigenproblem's matrix and its Hessenberg form
   if (wv == 0) {
@@ -798,27 +802,28 @@ __global__ __launch_bounds__(CY_BS) void k_cycle(CycleArgs a) {
     if (t == 0) s_exit = ex;
     if (!ex) {
       if (z_lds) {
-        phase_g(a, sh, piv);
-        phase_hess(a, sh, sh + m * m, v, w0s, fs);
+        phase_g(a, sh, ld, piv);
+        phase_hess(a, sh, sh + m * ld, ld, v, w0s, fs);
       } else if (g_lds) {
-        phase_g(a, sh, piv);
-        phase_hess(a, sh, wZ, v, w0s, fs);
+        phase_g(a, sh, ld, piv);
+        phase_hess(a, sh, wZ, ld, v, w0s, fs);
       } else {
-        phase_g(a, wG, piv);
-        phase_hess(a, wG, wZ, v, w0s, fs);
+        phase_g(a, wG, ld, piv);
+        phase_hess(a, wG, wZ, ld, v, w0s, fs);
       }
     }
   }
   __syncthreads();
   if (s_exit) return;
   // ---- all waves: the QR iteration
-  const bool ok = z_lds ? schur(sh, sh + m * m, m, true, fs, w0s)
-                        : (g_lds ? schur(sh, wZ, m, false, fs, w0s) : schur(wG, wZ, m, false, fs, w0s));
+  const bool ok = z_lds ? schur(sh, sh + m * ld, m, ld, true, fs, w0s)
+                        : (g_lds ? schur(sh, wZ, m, ld, false, fs, w0s)
+                                 : schur(wG, wZ, m, ld, false, fs, w0s));
   // ---- wave 0: selection
   if (wv == 0) {
     if (t == 0) a.info[4] = ok ? 0.0 : 1.0;
     double tn;
-    g_lds ? phase_sort(a, sh, order, &s_kout, tn) : phase_sort(a, wG, order, &s_kout, tn);
+    g_lds ? phase_sort(a, sh, ld, order, &s_kout, tn) : phase_sort(a, wG, ld, order, &s_kout, tn);
     if (t == 0) s_tn = tn;
     for (int i = t; i < m1 * (k + 1); i += NT) a.P[i] = make_double2(0.0, 0.0);
   }
@@ -829,9 +834,9 @@ __global__ __launch_bounds__(CY_BS) void k_cycle(CycleArgs a) {
   const double tn = s_tn;
   for (int q = wv; q < ks; q += CY_BS / 64) {
     const int col = order[q];
-    if (z_lds) tri_eigvec(sh, sh + m * m, m, col, tn, a.P + q * m1, true);
-    else if (g_lds) tri_eigvec(sh, wZ, m, col, tn, a.P + q * m1, true);
-    else tri_eigvec(wG, wZ, m, col, tn, a.P + q * m1, true);
+    if (z_lds) tri_eigvec(sh, sh + m * ld, m, ld, col, tn, a.P + q * m1, true);
+    else if (g_lds) tri_eigvec(sh, wZ, m, ld, col, tn, a.P + q * m1, true);
+    else tri_eigvec(wG, wZ, m, ld, col, tn, a.P + q * m1, true);
   }
   __syncthreads();
   if (wv != 0) return;
@@ -866,7 +871,7 @@ __global__ void k_trsolve(const double2* __restrict__ R, int ldr, int n, double2
 
 size_t dense_cycle_work(int m) {
   const size_t m1 = m + 1;
-  return 2 * m1 * m + 2 * size_t(m) * m + 8;
+  return 2 * m1 * m + 2 * size_t(m) * size_t(m | 1) + 8;
 }
 
 void dense_lu_solve(hipStream_t s, const double2* M, int k, double2* C, int nrhs, double2* work,
