@@ -279,17 +279,44 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Wave sums of NP values (a power of two up to 64), scattered: lane l ends with the sum over the
+// wave of value l % NP.  Each halving step sends half of the values still held to the lane whose
+// index differs in one bit and keeps the half that bit selects; the single value left is then
+// summed over the lanes that hold the same one.  NP - 1 + log2(64 / NP) exchanges, against
+// 6 NP for separate sums; the order of the additions is fixed.
+template <int HALF, int NP>
+__device__ __forceinline__ void scatter_halve(double (&v)[NP], int lane) {
+  const bool up = (lane & HALF) != 0;
+#pragma unroll
+  for (int i = 0; i < HALF; ++i) {
+    const double lo = v[i], hi = v[i + HALF];
+    const double send = up ? lo : hi;
+    v[i] = (up ? hi : lo) + __shfl_xor(send, HALF, 64);
+  }
+  if constexpr (HALF > 1) scatter_halve<HALF / 2>(v, lane);
+}
+template <int NP>
+__device__ __forceinline__ double wave_sum_small(double (&v)[NP]) {
+  static_assert(NP >= 1 && NP <= 64 && (NP & (NP - 1)) == 0, "a power of two up to 64");
+  if constexpr (NP > 1) scatter_halve<NP / 2>(v, threadIdx.x & 63);
+  double s = v[0];
+#pragma unroll
+  for (int o = NP; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
+  return s;
+}
+
 // Block-wide sum of NV doubles per thread; result valid in thread 0. Fixed order.
 template <int NV, int BS>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh /* [NV * BS/64] */) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   constexpr int NW = BS / 64;
+  constexpr int NP = NV <= 1 ? 1 : NV <= 2 ? 2 : NV <= 4 ? 4 : NV <= 8 ? 8 : NV <= 16 ? 16 : NV <= 32 ? 32 : 64;
+  static_assert(NV <= 64, "at most 64 sums");
+  double t[NP];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
-  if (lane == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) sh[i * NW + w] = v[i];
-  }
+  for (int i = 0; i < NP; ++i) t[i] = i < NV ? v[i] : 0.0;
+  const double mine = wave_sum_small<NP>(t);
+  if (lane < NV) sh[lane * NW + w] = mine;
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll

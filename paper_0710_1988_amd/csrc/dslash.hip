@@ -502,6 +502,30 @@ __device__ __forceinline__ void finish_site(const cx<T> (&psi)[12], const cx<T> 
   }
 }
 
+// number of the DS_NSUM partial sums an epilogue fills (the others stay zero; 1 for the
+// output-only one, which reduces nothing)
+template <int EPI>
+constexpr int epi_sums() {
+  return EPI == EPI_TS ? 7 : (EPI == EPI_RHAT ? 2 : 1);
+}
+
+// block sums of the first epi_sums<EPI>() of the DS_NSUM sums of each of NB rhs (valid in
+// thread 0)
+template <int EPI, int NB, int BS>
+__device__ __forceinline__ void block_sum_epi(double* red, double* sh) {
+  constexpr int NS = epi_sums<EPI>();
+  double t[NB * NS];
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+#pragma unroll
+    for (int i = 0; i < NS; ++i) t[j * NS + i] = red[j * DS_NSUM + i];
+  block_sum<NB * NS, BS>(t, sh);
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+#pragma unroll
+    for (int i = 0; i < NS; ++i) red[j * DS_NSUM + i] = t[j * NS + i];
+}
+
 // <rhat, t> and <rhat, s> of the <t, s> epilogue go to a second partial-sum region after the
 // first (nrhs_total x pstride slots of 3 doubles), 4 doubles per slot
 __device__ __forceinline__ double* ts_extra(const DsBatch& B, double* partials, long long rhs,
@@ -626,7 +650,7 @@ void k_dslash(DsBatch B, RhsScal* __restrict__ sc, double* __restrict__ partials
   }
   if (EPI != EPI_NONE) {
     __shared__ double sh[NB * DS_NSUM * (DS_BS / 64)];
-    block_sum<NB * DS_NSUM, DS_BS>(red, sh);
+    block_sum_epi<EPI, NB, DS_BS>(red, sh);
     if (threadIdx.x == 0) {
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
@@ -748,7 +772,7 @@ void k_dslash_half(DsBatch B, RhsScal* __restrict__ sc, double* __restrict__ par
   }
   if (EPI != EPI_NONE) {
     __shared__ double sh[NB * DS_NSUM * (DS_BS / 64)];
-    block_sum<NB * DS_NSUM, DS_BS>(red, sh);
+    block_sum_epi<EPI, NB, DS_BS>(red, sh);
     if (threadIdx.x == 0) {
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
@@ -1056,7 +1080,7 @@ __global__ __launch_bounds__(DS_BS) void k_dslash_tile(DsBatch B, RhsScal* __res
     }
     if (EPI != EPI_NONE) {
       __shared__ double sh[DS_NSUM * (DS_BS / 64)];
-      block_sum<DS_NSUM, DS_BS>(red, sh);
+      block_sum_epi<EPI, 1, DS_BS>(red, sh);
       if (tid == 0) {
         store_sums<EPI>(B, partials, L.rhs_base + r, tile, red);
       }
@@ -1280,7 +1304,7 @@ __global__ __launch_bounds__(TH_BS) void k_dslash_tile_half(DsBatch B, RhsScal* 
     }
     if (EPI != EPI_NONE) {
       __shared__ double sh[DS_NSUM * (TH_BS / 64)];
-      block_sum<DS_NSUM, TH_BS>(red, sh);
+      block_sum_epi<EPI, 1, TH_BS>(red, sh);
       if (tid == 0) {
         store_sums<EPI>(B, partials, L.rhs_base + r, tile, red);
       }
