@@ -239,6 +239,16 @@ int link_force(dbq_ctx* ctx, const dbq_operator* op, const void* lambda, const v
 int kappa_critical(dbq_ctx* ctx, const int32_t L[4], const void* links, int32_t m, int32_t k,
                    double tol, int64_t max_mv, double* kappa_c, double* lambda, double* resid);
 
+/* kappa_critical, also returning the nritz (1 <= nritz <= k) Ritz values of largest real part of
+ * the final cycle in decreasing real part, ritz: HOST double [2 * nritz] (re, im), the first one
+ * being lambda.  Beyond the first, whose residual resid bounds, these are Ritz values of the same
+ * Krylov space, not converged eigenvalues: they show how far the rightmost one stands from the
+ * next ones (Sec. 3 defines kappa_c by the rightmost).  DBQ_EINVAL for nritz outside 0..k or a
+ * null ritz with nritz > 0; otherwise as kappa_critical. */
+int kappa_critical_ritz(dbq_ctx* ctx, const int32_t L[4], const void* links, int32_t m, int32_t k,
+                        double tol, int64_t max_mv, double* kappa_c, double* lambda, double* resid,
+                        int32_t nritz, double* ritz);
+
 /* Instrumentation: with timing on (dbq_set_timing with on = N >= 1), every N-th launch of each
  * class -- the Dslash launches of the full operator inside the library and the FP32 BiCGStab
  * update steps (x += alpha p + omega s, r = s - omega t, p = r + beta (p - omega v) with ||r||^2) -- is

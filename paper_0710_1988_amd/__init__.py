@@ -324,8 +324,10 @@ def link_force(L, links, kappa, lam, x, kind="su3"):
     return F
 
 
-def kappa_critical(L, links, m=48, k=16, tol=1e-10, max_mv=200000):
-    """kappa_c = 1 / max Re lambda(H).  Returns (kappa_c, lambda (complex), eigen-residual, status)."""
+def kappa_critical(L, links, m=48, k=16, tol=1e-10, max_mv=200000, nritz=0):
+    """kappa_c = 1 / max Re lambda(H).  Returns (kappa_c, lambda (complex), eigen-residual, status),
+    and with nritz > 0 also the final cycle's nritz Ritz values of largest real part (a list of
+    complex, decreasing real part, the first being lambda)."""
     L, Vol = _lattice(L)
     U = _links(links, Vol)
     Larr = (ctypes.c_int32 * 4)(*L)
@@ -333,11 +335,20 @@ def kappa_critical(L, links, m=48, k=16, tol=1e-10, max_mv=200000):
     lam = (ctypes.c_double * 2)()
     res = ctypes.c_double(0)
     h = _ctx(U.device)
-    st = _abi.load().kappa_critical(h, Larr, ctypes.c_void_p(U.data_ptr()), int(m), int(k),
-                                    float(tol), int(max_mv), ctypes.byref(kc), lam,
-                                    ctypes.byref(res))
+    lib = _abi.load()
+    if nritz > 0:
+        rz = (ctypes.c_double * (2 * int(nritz)))()
+        st = lib.kappa_critical_ritz(h, Larr, ctypes.c_void_p(U.data_ptr()), int(m), int(k),
+                                     float(tol), int(max_mv), ctypes.byref(kc), lam,
+                                     ctypes.byref(res), int(nritz), rz)
+    else:
+        st = lib.kappa_critical(h, Larr, ctypes.c_void_p(U.data_ptr()), int(m), int(k),
+                                float(tol), int(max_mv), ctypes.byref(kc), lam, ctypes.byref(res))
     _check(st, h)
-    return kc.value, complex(lam[0], lam[1]), res.value, st
+    out = (kc.value, complex(lam[0], lam[1]), res.value, st)
+    if nritz > 0:
+        out = out + ([complex(rz[2 * i], rz[2 * i + 1]) for i in range(int(nritz))],)
+    return out
 
 
 def geometry(L, device=None):

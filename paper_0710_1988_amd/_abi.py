@@ -19,7 +19,8 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EBREAKDOWN", -3:
 
 EXPORTED = ["dbq_create", "dbq_destroy", "dbq_last_error", "dbq_set_stream", "dbq_geometry",
             "dbq_geometry_host", "dbq_site_tile", "wilson_apply", "gmresdr_first_rhs", "dbicgstab_solve",
-            "project_shifts", "gmres_proj_solve", "link_force", "kappa_critical", "dbq_set_timing",
+            "project_shifts", "gmres_proj_solve", "link_force", "kappa_critical",
+            "kappa_critical_ritz", "dbq_set_timing",
             "dbq_kernel_time",
             "dbq_reset_timing", "dbq_version", "dbq_tile_schedule_host", "dbq_stream_probe",
             "wilson_apply_noalloc"]
@@ -76,6 +77,7 @@ def load():
         "gmres_proj_solve": ([P, POP, P, I32, P, P, I32, I32, D, I64, PST], ctypes.c_int),
         "link_force": ([P, POP, P, P, I32, I32, P], ctypes.c_int),
         "kappa_critical": ([P, PI32, P, I32, I32, D, I64, PD, PD, PD], ctypes.c_int),
+        "kappa_critical_ritz": ([P, PI32, P, I32, I32, D, I64, PD, PD, PD, I32, PD], ctypes.c_int),
         "dbq_set_timing": ([P, I32], ctypes.c_int),
         "dbq_kernel_time": ([P, I32, PD, ctypes.POINTER(I64), PD], ctypes.c_int),
         "dbq_reset_timing": ([P], ctypes.c_int),

@@ -201,7 +201,17 @@ int link_force(dbq_ctx* c, const dbq_operator* op, const void* lambda, const voi
 
 int kappa_critical(dbq_ctx* c, const int32_t L[4], const void* links, int32_t m, int32_t k,
                    double tol, int64_t max_mv, double* kappa_c, double* lambda, double* resid) {
-  return guarded(c, [&]() { return dbq::kappa_crit(c, L, links, m, k, tol, max_mv, kappa_c, lambda, resid); });
+  return guarded(c, [&]() {
+    return dbq::kappa_crit(c, L, links, m, k, tol, max_mv, kappa_c, lambda, resid, 0, nullptr);
+  });
+}
+
+int kappa_critical_ritz(dbq_ctx* c, const int32_t L[4], const void* links, int32_t m, int32_t k,
+                        double tol, int64_t max_mv, double* kappa_c, double* lambda, double* resid,
+                        int32_t nritz, double* ritz) {
+  return guarded(c, [&]() {
+    return dbq::kappa_crit(c, L, links, m, k, tol, max_mv, kappa_c, lambda, resid, nritz, ritz);
+  });
 }
 
 int dbq_set_timing(dbq_ctx* c, int32_t on) {

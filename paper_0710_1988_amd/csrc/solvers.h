@@ -13,7 +13,8 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
 int gmresdr(dbq_ctx* c, const dbq_operator* o, const void* b, void* x, int m, int k, double tol,
             int64_t max_mv, void* Vout, double* theta, int32_t* k_out, dbq_stats* st);
 int kappa_crit(dbq_ctx* c, const int32_t L[4], const void* links, int m, int k, double tol,
-               int64_t max_mv, double* kappa_c, double* lambda, double* resid);
+               int64_t max_mv, double* kappa_c, double* lambda, double* resid, int nritz,
+               double* ritz);
 int mr_project(dbq_ctx* c, const dbq_operator* o, const void* Q, int nq, const void* B, void* X0,
                int nrhs, double* rn);
 int gmres_proj(dbq_ctx* c, const dbq_operator* o, const void* V, int k, const void* B, void* X,

@@ -1590,9 +1590,11 @@ int gmresdr(dbq_ctx* c, const dbq_operator* o, const void* b, void* x, int m, in
 
 // ============================================================================ kappa_c
 int kappa_crit(dbq_ctx* c, const int32_t L[4], const void* links, int m, int k, double tol,
-               int64_t max_mv, double* kappa_c, double* lambda, double* resid) {
+               int64_t max_mv, double* kappa_c, double* lambda, double* resid, int nritz,
+               double* ritz) {
   DBQ_CHECK(L && links && kappa_c && lambda && resid, "null argument");
   DBQ_CHECK(k >= 2 && k < m && m <= 128, "need 2 <= k < m <= 128");
+  DBQ_CHECK(nritz >= 0 && nritz <= k && (nritz == 0 || ritz), "nritz must be in 0..k");
   dbq_operator o;
   for (int i = 0; i < 4; ++i) o.L[i] = L[i];
   o.links = links;
@@ -1632,6 +1634,16 @@ int kappa_crit(dbq_ctx* c, const int32_t L[4], const void* links, int m, int k, 
     j0 = k;
   }
   timer_collect(c);
+  if (nritz > 0) {
+    // the final cycle's Ritz values of largest real part (of I + H, sorted by real part)
+    double2* th_h = (double2*)(hp + 64);
+    DBQ_HIP(hipMemcpyAsync(th_h, ar.theta, sizeof(double2) * nritz, hipMemcpyDeviceToHost, s));
+    DBQ_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < nritz; ++i) {
+      ritz[2 * i] = th_h[i].x - 1.0;
+      ritz[2 * i + 1] = th_h[i].y;
+    }
+  }
   lambda[0] = lam_re;
   lambda[1] = lam_im;
   *resid = res;

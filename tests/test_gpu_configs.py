@@ -14,7 +14,7 @@ import synth
 from oracle import force as F
 from oracle import solvers as S
 from oracle import wilson as W
-from gpuhelp import dev, host
+from gpuhelp import dev, host, same_eigenvalues
 
 pytestmark = pytest.mark.gpu
 
@@ -79,6 +79,26 @@ def test_kappa_critical_96_vectors_matches_stored_oracle_value(gpu_lib):
     assert st == 0 and res <= 1e-9
     assert abs(kc - g["kappa_c"]) <= 1e-8 * g["kappa_c"]
     assert abs(lam.real - g["lambda_re"][0]) <= 1e-8 * g["lambda_re"][0]
+
+
+def test_kappa_critical_ritz_values_match_stored_oracle_eigenvalues(gpu_lib):
+    """The final cycle's three Ritz values of largest real part on the C4 8^4 field against the
+    oracle's three rightmost eigenvalues of H (ARPACK, stored): the rightmost complex-conjugate
+    pair as a set, then the third by its real part and |imaginary part| (the next pair's two
+    members share the real part, so which one comes third is decided by rounding)."""
+    g = _golden("c4_8x8x8x8")
+    L = C4["L"]
+    U = synth.gauge_field(L, C4["c"], C4["seed"])
+    kc, lam, res, st, rz = gpu_lib.kappa_critical(L, dev(U), m=96, k=32, tol=1e-11, nritz=3)
+    assert st == 0 and len(rz) == 3
+    assert rz[0] == lam
+    assert rz[0].real >= rz[1].real >= rz[2].real
+    ref = [complex(a, b) for a, b in zip(g["lambda_re"], g["lambda_im"])]
+    assert same_eigenvalues(rz[:2], ref[:2], rtol=1e-8, atol=0.0)
+    assert abs(rz[2].real - ref[2].real) <= 1e-6 * ref[2].real
+    assert abs(abs(rz[2].imag) - abs(ref[2].imag)) <= 1e-6 * abs(ref[2])
+    with pytest.raises(RuntimeError):
+        gpu_lib.kappa_critical(L, dev(U), m=96, k=32, tol=1e-11, nritz=33)
 
 
 # ----------------------------------------------------------------------------- C3
