@@ -83,10 +83,26 @@ __device__ void reduce_rhs(const VecSet& vs, const double* partials, Fn fn) {
     const int nch = (vs.nelem[rhs] + BL_CHUNK - 1) / BL_CHUNK;
     const double* pp = partials + (long long)rhs * vs.pstride * 3;
     double a0 = 0, a1 = 0, a2 = 0;
-    for (int j = lane; j < nch; j += 64) {
-      a0 += pp[3 * j];
-      a1 += pp[3 * j + 1];
-      a2 += pp[3 * j + 2];
+    // FIN_U partials per lane in flight together; additions in the order j = lane, lane + 64, ...
+    for (int j0 = lane; j0 < nch; j0 += 64 * FIN_U) {
+      double v[FIN_U][3];
+#pragma unroll
+      for (int u = 0; u < FIN_U; ++u) {
+        const int j = j0 + 64 * u;
+        if (j < nch) {
+          v[u][0] = pp[3 * j];
+          v[u][1] = pp[3 * j + 1];
+          v[u][2] = pp[3 * j + 2];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < FIN_U; ++u) {
+        if (j0 + 64 * u < nch) {
+          a0 += v[u][0];
+          a1 += v[u][1];
+          a2 += v[u][2];
+        }
+      }
     }
     a0 = wave_sum(a0);
     a1 = wave_sum(a1);

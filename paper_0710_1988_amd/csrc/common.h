@@ -272,6 +272,10 @@ __device__ __forceinline__ int xcd_block(int b, int n) {
   return start + loc;
 }
 
+// Partial sums a finalize lane loads before adding any of them (one load latency per FIN_U
+// partials instead of one per partial).
+constexpr int FIN_U = 8;
+
 // sum over a 64-lane wavefront, fixed butterfly order (deterministic)
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -338,15 +338,38 @@ __device__ void finalize(const DsBatch& B, RhsScal* sc, const double* partials) 
     const double* pp = partials + (long long)rhs * B.pstride * 3;
     const double* px = partials + (long long)B.nrhs_total * B.pstride * 3 +
                        (long long)rhs * B.pstride * 4;
-    for (int j = lane; j < nsb; j += 64) {
-      a0 += pp[3 * j];
-      a1 += pp[3 * j + 1];
-      a2 += pp[3 * j + 2];
-      if (EPI == EPI_TS) {
-        a3 += px[4 * j];
-        a4 += px[4 * j + 1];
-        a5 += px[4 * j + 2];
-        a6 += px[4 * j + 3];
+    // FIN_U partials per lane are loaded before any of them is added, so their loads are in
+    // flight together; the additions keep the order j = lane, lane + 64, ...
+    for (int j0 = lane; j0 < nsb; j0 += 64 * FIN_U) {
+      double v[FIN_U][7];
+#pragma unroll
+      for (int u = 0; u < FIN_U; ++u) {
+        const int j = j0 + 64 * u;
+        if (j < nsb) {
+          v[u][0] = pp[3 * j];
+          v[u][1] = pp[3 * j + 1];
+          v[u][2] = pp[3 * j + 2];
+          if (EPI == EPI_TS) {
+            v[u][3] = px[4 * j];
+            v[u][4] = px[4 * j + 1];
+            v[u][5] = px[4 * j + 2];
+            v[u][6] = px[4 * j + 3];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < FIN_U; ++u) {
+        if (j0 + 64 * u < nsb) {
+          a0 += v[u][0];
+          a1 += v[u][1];
+          a2 += v[u][2];
+          if (EPI == EPI_TS) {
+            a3 += v[u][3];
+            a4 += v[u][4];
+            a5 += v[u][5];
+            a6 += v[u][6];
+          }
+        }
       }
     }
     a0 = wave_sum(a0);
