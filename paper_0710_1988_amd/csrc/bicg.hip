@@ -123,36 +123,6 @@ __device__ __forceinline__ void store_partial(const VecSet& vs, double* partials
   }
 }
 
-// end of an iteration: rr = ||r||^2; rho takes the value the <t, s> epilogue prepared
-__device__ void fin_xr(RhsScal& q, double a2) {
-  if (!q.active) return;
-  q.iters += 1;
-  q.since += 1;
-  q.rr = a2;
-  if (!fin(a2)) {
-    q.flags |= F_NAN;
-    q.active = 0;
-    return;
-  }
-  const zd rn = q.rho_next;
-  if (a2 <= q.stop2) q.flags |= F_CONV;
-  if (q.delta2 > 0.0) {
-    if (a2 > q.rr_max) q.rr_max = a2;
-    // a drop by the reliable-update factor, or a long stretch without one (checked for a
-    // stall by the FP64 residual that follows), or growth by 100x over the last FP64
-    // residual (checked for divergence)
-    if (a2 < q.delta2 * q.rr_max || q.since >= STALL_ITERS || a2 > 1e4 * q.rr_prev)
-      q.flags |= F_RELIABLE;
-  }
-  if (norm2(rn) <= 1e-28 * q.rhat2 * a2) q.flags |= F_BREAK;
-  if (q.flags & F_OMEGA0) q.flags |= F_BREAK;
-  q.rho_prev = q.rho;
-  q.rho = rn;
-  if (q.flags & (F_CONV | F_RELIABLE | F_BREAK | F_NAN)) q.active = 0;
-  // a convergence claim or a reliable update asks for the FP64 residual of this rhs
-  if (q.flags & (F_CONV | F_RELIABLE)) q.sel = 1;
-}
-
 template <typename E, int OP>
 __global__ __launch_bounds__(BL_BS) void k_bicg_step(VecSet vs, E* __restrict__ x,
                                                      E* __restrict__ r,

@@ -334,6 +334,24 @@ __device__ void finalize(const DsBatch& B, RhsScal* sc, const double* partials) 
     for (int i = 1; i < B.nlat; ++i)
       if (rhs >= B.lat[i].rhs_base) l = i;
     const int nsb = B.lat[l].nsb;
+    if (EPI == EPI_RHAT && B.xr_part) {
+      // the end of the previous iteration, whose own finalize launch was left out: ||r||^2 from
+      // the update step's partials in the order the update step's finalize adds them
+      const int nch = (B.xr_nelem[rhs] + BL_CHUNK - 1) / BL_CHUNK;
+      const double* pr = B.xr_part + (long long)rhs * B.xr_pstride * 3;
+      double r2 = 0;
+      for (int j0 = lane; j0 < nch; j0 += 64 * FIN_U) {
+        double v[FIN_U];
+#pragma unroll
+        for (int u = 0; u < FIN_U; ++u)
+          if (j0 + 64 * u < nch) v[u] = pr[3 * (j0 + 64 * u) + 2];
+#pragma unroll
+        for (int u = 0; u < FIN_U; ++u)
+          if (j0 + 64 * u < nch) r2 += v[u];
+      }
+      r2 = wave_sum(r2);
+      if (lane == 0) fin_xr(sc[rhs], r2);
+    }
     double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, a6 = 0;
     const double* pp = partials + (long long)rhs * B.pstride * 3;
     const double* px = partials + (long long)B.nrhs_total * B.pstride * 3 +

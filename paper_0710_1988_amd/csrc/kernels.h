@@ -57,6 +57,39 @@ struct RhsScal {
 // restarts the recursion.)
 constexpr int STALL_ITERS = 500;
 
+// End of a BiCGStab iteration for one rhs, from a2 = ||r||^2 of the update step: rr = a2, rho
+// takes the value the <t, s> epilogue prepared, and the flags that end the rhs's run of
+// iterations (convergence claim, reliable update, breakdown, non-finite values) are raised.
+// Called by the update step's finalize, or by the <rhat, v> finalize of the next iteration.
+__device__ inline void fin_xr(RhsScal& q, double a2) {
+  if (!q.active) return;
+  q.iters += 1;
+  q.since += 1;
+  q.rr = a2;
+  if (!isfinite(a2)) {
+    q.flags |= F_NAN;
+    q.active = 0;
+    return;
+  }
+  const zd rn = q.rho_next;
+  if (a2 <= q.stop2) q.flags |= F_CONV;
+  if (q.delta2 > 0.0) {
+    if (a2 > q.rr_max) q.rr_max = a2;
+    // a drop by the reliable-update factor, or a long stretch without one (checked for a
+    // stall by the FP64 residual that follows), or growth by 100x over the last FP64
+    // residual (checked for divergence)
+    if (a2 < q.delta2 * q.rr_max || q.since >= STALL_ITERS || a2 > 1e4 * q.rr_prev)
+      q.flags |= F_RELIABLE;
+  }
+  if (norm2(rn) <= 1e-28 * q.rhat2 * a2) q.flags |= F_BREAK;
+  if (q.flags & F_OMEGA0) q.flags |= F_BREAK;
+  q.rho_prev = q.rho;
+  q.rho = rn;
+  if (q.flags & (F_CONV | F_RELIABLE | F_BREAK | F_NAN)) q.active = 0;
+  // a convergence claim or a reliable update asks for the FP64 residual of this rhs
+  if (q.flags & (F_CONV | F_RELIABLE)) q.sel = 1;
+}
+
 // ----------------------------------------------------------------------------- batches
 constexpr int MAXLAT = 8;
 constexpr int DS_BS = 256;  // Dslash threads per block = sites per block
@@ -102,6 +135,12 @@ struct DsBatch {
   DsAcct acct;     // zero unless the caller accounts bytes of a gated launch
   int decide;      // RESID finalize also decides convergence / replacement (device loop)
   int schur;       // the lattices' operator is the even-odd reduced one (half vectors)
+  // With xr_part set, the <rhat, v> finalize first ends the previous iteration (fin_xr) from the
+  // update step's partials of ||r||^2: for rhs j, ceil(xr_nelem[j] / BL_CHUNK) slots of 3
+  // doubles (the third is ||r||^2) from xr_part + 3 j xr_pstride.
+  const double* xr_part;
+  const int* xr_nelem;
+  int xr_pstride;
 };
 
 enum Epi : int { EPI_NONE = 0, EPI_RHAT = 1, EPI_TS = 2, EPI_RESID = 3 };

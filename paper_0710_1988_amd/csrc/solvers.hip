@@ -891,6 +891,17 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
     }
   }
   const DsBatch bv = make_batch(sv), bt = make_batch(stt);
+  // Mixed precision: the update step's partial sums of ||r||^2 go to the second partial region
+  // (which only the <t, s> epilogue uses, later in the iteration), so that they outlast the next
+  // iteration's v = A p and the <rhat, v> finalize (batch bv_xr) can end the iteration in place
+  // of a separate finalize launch.  FP64 keeps the separate launch and the first region.
+  double* xr_part = mixed ? partials + size_t(NR) * pstride * 3 : partials;
+  DsBatch bv_xr = bv;
+  if (mixed) {
+    bv_xr.xr_part = xr_part;
+    bv_xr.xr_nelem = vs32.nelem;
+    bv_xr.xr_pstride = vs32.pstride;
+  }
 
   pull();
   for (int j = 0; j < NR; ++j) {
@@ -912,18 +923,21 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
   else
     bicg_aux_f64(s, AX_INIT, vs64, r64, r64, rhat, p, v, sc, partials);
 
-  auto iterate = [&]() {
+  // pending: the previous iteration's end (fin_xr) is still to be done, by this iteration's
+  // <rhat, v> finalize; defer: leave this iteration's end to the next one (mixed precision only,
+  // and only where another iteration follows before anything reads the scalars)
+  auto iterate = [&](bool pending, bool defer) {
     if (mixed) {
-      run_dslash(c, true, bv, dagger, EPI_RHAT, sc, partials);
+      run_dslash(c, true, pending ? bv_xr : bv, dagger, EPI_RHAT, sc, partials);
       bicg_step_f32(s, BI_S, vs32, x32, r32, rhat32, p32, v32, t32, sc, partials);
       run_dslash(c, true, bt, dagger, EPI_TS, sc, partials);
       // the update kernel alone is timed (kind 2), its bytes counted on the device
       hipEvent_t e0;
       timer_begin(c, 2, &e0);
-      bicg_step_f32(s, BI_XR, vs32, x32, r32, rhat32, p32, v32, t32, sc, partials,
+      bicg_step_f32(s, BI_XR, vs32, x32, r32, rhat32, p32, v32, t32, sc, xr_part,
                     e0 ? c->acct + 2 : nullptr);
       timer_end(c, 2, e0, 0.0);
-      bicg_fin_xr(s, vs32, sc, partials);
+      if (!defer) bicg_fin_xr(s, vs32, sc, xr_part);
     } else {
       run_dslash(c, false, bv, dagger, EPI_RHAT, sc, partials);
       bicg_step_f64(s, BI_S, vs64, x64, r64, rhat, p, v, t, sc, partials);
@@ -1021,13 +1035,15 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
       if (reproject || any_reproj) project_sel(!reproject);
       bicg_aux_f32(s, AX_REPLACE, vs32, vs64, r64, r32, rhat32, p32, v32, x32, sc, partials);
     };
+    // an iteration followed by another one leaves its end to that one's <rhat, v> finalize;
+    // the last one before a reliable-update step ends itself
     auto block = [&](int n) {
       for (int it = 1; it <= n; ++it) {
-        iterate();
+        iterate(it > 1 && (it - 1) % every != 0, it % every != 0);
         if (it % every == 0) relup_dev();
       }
     };
-    // Blocks of iterations between two polls run as HIP graphs: the launches of a block (7 per
+    // Blocks of iterations between two polls run as HIP graphs: the launches of a block (6-7 per
     // iteration, 5 for the reliable-update step) are captured once per solve and block length
     // and replayed, so the host issues one launch per block.  The first block runs eagerly
     // (it tunes the launch shapes and settles the workspace the graphs capture).
@@ -1130,7 +1146,7 @@ int dbicgstab(dbq_ctx* c, const dbq_operator* ops, int nops, const void* const* 
     bool first = true;
     while (true) {
       if (!first)
-        for (int it = 0; it < nchk; ++it) iterate();
+        for (int it = 0; it < nchk; ++it) iterate(false, false);
       first = false;
       pull();
       if (debug) {
