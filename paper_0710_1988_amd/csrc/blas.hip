@@ -308,24 +308,9 @@ __global__ __launch_bounds__(256) void k_gram_mfma_final(const double* __restric
   const int o = (a * TB + b) * 512 + (i & 15) * 16 + (j & 15);
   constexpr int NV = TA * TB * 2 * 256;
   double re = 0.0, im = 0.0;
-  // FIN_U partials per lane in flight together; additions in the order k = lane, lane + 64, ...
-  for (int k0 = lane; k0 < nblocks; k0 += 64 * FIN_U) {
-    double vr[FIN_U], vi[FIN_U];
-#pragma unroll
-    for (int u = 0; u < FIN_U; ++u) {
-      const int k = k0 + 64 * u;
-      if (k < nblocks) {
-        vr[u] = work[(long long)k * NV + o];
-        vi[u] = work[(long long)k * NV + o + 256];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < FIN_U; ++u) {
-      if (k0 + 64 * u < nblocks) {
-        re += vr[u];
-        im += vi[u];
-      }
-    }
+  for (int k = lane; k < nblocks; k += 64) {
+    re += work[(long long)k * NV + o];
+    im += work[(long long)k * NV + o + 256];
   }
   re = wave_sum(re);
   im = wave_sum(im);
