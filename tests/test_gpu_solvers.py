@@ -314,6 +314,37 @@ def test_mixed_breakdown_restart_with_uneven_reliable_update_interval(gpu_lib, m
         assert _true_rel(U, lat, 0.13, 0.0, Xh[j].reshape(-1), B[j].reshape(-1)) <= 1.0001e-8
 
 
+def test_iteration_end_in_next_finalize_changes_nothing(gpu_lib, monkeypatch):
+    """Inside a block of iterations the end of a mixed-precision iteration (||r||^2, the next rho,
+    the flags that stop an rhs) is taken by the next iteration's <rhat, v> finalize.  With a
+    reliable-update step after every iteration (DBQ_RELUP_EVERY=1) each iteration ends in its
+    own launch instead; an rhs that waits for a check does not iterate, so both schedules give
+    every rhs the same iterations: the same products and the same solution bit for bit (8^4
+    field at 0.99 kappa_c, 6 Z2 sources), each below 1e-8 on the oracle's residual."""
+    L = (8, 8, 8, 8)
+    lat = W.Lattice(L)
+    U = synth.gauge_field(L, 0.5, 104)
+    kap = 0.99 * 0.17585446225413343  # kappa_c of this field (stored oracle value)
+    B = synth.z2_sources(L, 6, 1108)
+    spec = [dict(L=L, links=dev(U), kappa=kap, B=dev(B))]
+    runs = []
+    for every in (None, "1"):
+        if every is None:
+            monkeypatch.delenv("DBQ_RELUP_EVERY", raising=False)
+        else:
+            monkeypatch.setenv("DBQ_RELUP_EVERY", every)
+        X, st, status = gpu_lib.dbicgstab_solve(spec, tol=1e-8, prec="mixed")
+        assert status == 0, st
+        runs.append((host(X[0]), [(q["matvecs"], q["reliable_updates"]) for q in st]))
+    (X16, s16), (X1, s1) = runs
+    print("products and reliable updates per rhs:", s16)
+    assert min(m for m, _ in s16) > 2 * 16 * 3  # several blocks of deferred iteration ends
+    assert s16 == s1
+    assert np.array_equal(X16, X1)
+    for j in range(6):
+        assert _true_rel(U, lat, kap, 0.0, X16[j].reshape(-1), B[j].reshape(-1)) <= 1.0001e-8
+
+
 def test_max_mv_reports_not_converged(gpu_lib):
     L, lat, U = _c1()
     X, st, status = gpu_lib.dbicgstab_solve(
