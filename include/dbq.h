@@ -228,7 +228,8 @@ int gmres_proj_solve(dbq_ctx* ctx, const dbq_operator* op, const void* V, int32_
  * kind 0: F = DEVICE double [4][V][8], F[mu][y][a] = Re(i tr[T_a U_mu(y) G_mu(y)^H]), T_a = Gell-Mann/2,
  *         the derivative along U -> exp(i theta T_a) U.
  * kind 1: F = DEVICE complex128 [4][V][3][3] = G itself (dL = Re sum conj(G) dU).
- * op->schur must be 0. */
+ * op->schur must be 0: solves on the reduced system return the full x and lambda, whose gradient
+ * is the one of the full operator (pass them with schur = 0). */
 int link_force(dbq_ctx* ctx, const dbq_operator* op, const void* lambda, const void* x,
                int32_t nrhs, int32_t kind, void* F);
 

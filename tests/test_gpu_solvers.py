@@ -427,10 +427,12 @@ def test_link_force_matches_oracle(gpu_lib):
     assert relerr(Fg, Fo) <= 1e-12
 
 
-def test_autograd_matches_finite_differences(gpu_lib):
+@pytest.mark.parametrize("schur", [False, True])
+def test_autograd_matches_finite_differences(gpu_lib, schur):
     """C4 recipe on 4^4 (8^4 in the full check): L = Re(eta^H A^{-1} b); the autograd gradient
     along random su(3) link directions and along b agrees with central differences of FP64
-    solves."""
+    solves.  With schur the forward and adjoint solves run on the even-odd reduced system,
+    deflated with GMRES-DR(20,6) vectors of the reduced operator."""
     import torch
     L = (4, 4, 4, 4)
     lat = W.Lattice(L)
@@ -439,9 +441,14 @@ def test_autograd_matches_finite_differences(gpu_lib):
     kap = 0.9 * kc
     b = synth.z2_sources(L, 1, 1104)
     eta = synth.gaussian_sources(L, 1, 2104)
+    V = None
+    if schur:
+        _, V, _, st = gpu_lib.gmresdr_first_rhs(L, dev(U), dev(synth.point_source(L)), kap, 20, 6,
+                                                tol=1e-10, schur=True)
+        assert st["status"] == 0
     Ut = dev(U).requires_grad_(True)
     bt = dev(b).requires_grad_(True)
-    x = gpu_lib.DeflatedSolve.apply(Ut, bt, L, kap, 0.0, None, 1e-13, "fp64", 100000)
+    x = gpu_lib.DeflatedSolve.apply(Ut, bt, L, kap, 0.0, V, 1e-13, "fp64", 100000, schur)
     loss = (dev(eta).conj() * x).sum().real
     loss.backward()
     gU = host(Ut.grad)
