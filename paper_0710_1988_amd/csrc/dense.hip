@@ -308,12 +308,24 @@ __global__ __launch_bounds__(NT) void k_lu_solve(const double2* __restrict__ M, 
 
 // ----------------------------------------------------------------------------- eigenproblem
 // Householder reduction of G (n x n, ld n) to upper Hessenberg form.  Reflector j (acting on rows
-// and columns j+1..n-1) is kept below the subdiagonal of column j, its first entry in w0s[j] and
-// its factor in fs[j] (0: identity), for form_q; the caller zeroes that part afterwards.
-__device__ __forceinline__ void hessenberg(double2* G, int n, int ld, double2* v, double2* w0s, double* fs) {
+// and columns j+1..j+hl[j]) is kept below the subdiagonal of column j, its first entry in w0s[j],
+// its factor in fs[j] (0: identity) and its length in hl[j], for form_q; the caller zeroes that
+// part afterwards.  Column j's nonzeros below the diagonal end at some row `last` (after a thick
+// restart the matrix is Hessenberg but for a dense leading block, whose fill moves down one row
+// per reduced column), so the reflector and both applications are restricted to rows and columns
+// j+1..last: the terms left out are products with exact zeros.
+__device__ __forceinline__ void hessenberg(double2* G, int n, int ld, double2* v, double2* w0s, double* fs,
+                                           int* hl) {
   const int t = threadIdx.x;
   for (int j = 0; j + 2 < n; ++j) {
-    const int len = n - j - 1;
+    int lastl = j + 1;
+    for (int r = j + 2 + t; r < n; r += NT) {
+      const double2 x = G[r + j * ld];
+      if (x.x != 0.0 || x.y != 0.0) lastl = r;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) lastl = max(lastl, __shfl_xor(lastl, o, 64));
+    const int len = lastl - j;
     double p = 0;
     for (int i = t; i < len; i += NT) {
       const double2 x = G[(j + 1 + i) + j * ld];
@@ -328,12 +340,13 @@ __device__ __forceinline__ void hessenberg(double2* G, int n, int ld, double2* v
     if (t == 0) {
       w0s[j] = make_double2(w0.re, w0.im);
       fs[j] = f;
+      hl[j] = len;
     }
     if (nx2 == 0.0) continue;
-    // left: rows j+1.., columns j..n-1
+    // left: rows j+1..j+len, columns j..n-1
     for (int c = j + t; c < n; c += NT) reflect_col(G + c * ld + j + 1, v, w0, len, f);
     wave_sync();
-    // right: all rows, columns j+1..n-1
+    // right: all rows, columns j+1..j+len
     for (int r = t; r < n; r += NT) {
       double2* row = G + r + (j + 1) * ld;
       zd s = ld2(row, 0) * w0;
@@ -354,7 +367,7 @@ __device__ __forceinline__ void hessenberg(double2* G, int n, int ld, double2* v
 // Q = H_0 H_1 ... H_{n-3} (so that G_in = Q G_out Q^H), accumulated backwards (Q <- H_j Q), one
 // column per lane: no lane reads another lane's column, so no barriers.
 __device__ __forceinline__ void form_q(const double2* G, int n, int ld, const double2* w0s,
-                                       const double* fs, double2* Q) {
+                                       const double* fs, const int* hl, double2* Q) {
   const int t = threadIdx.x;
   for (int c = t; c < n; c += NT) {
     double2* qc = Q + c * ld;
@@ -362,7 +375,7 @@ __device__ __forceinline__ void form_q(const double2* G, int n, int ld, const do
     for (int j = min(n - 3, c - 1); j >= 0; --j) {
       const double f = fs[j];
       if (f == 0.0) continue;
-      const int len = n - j - 1;
+      const int len = hl[j];
       const zd w0 = ld2(w0s, j);
       const double2* w = G + j * ld + j + 1;  // w[i], i >= 1
       double2* col = qc + j + 1;
@@ -668,10 +681,10 @@ __device__ __forceinline__ void phase_g(const CycleArgs& a, double2* G, int ld, 
 
 // Hessenberg form of G (m x m) and the Q of the reduction in Z (one wave)
 __device__ __forceinline__ void phase_hess(const CycleArgs& a, double2* G, double2* Z, int ld, double2* v,
-                                           double2* w0s, double* fs) {
+                                           double2* w0s, double* fs, int* hl) {
   const int t = threadIdx.x, m = a.m;
-  hessenberg(G, m, ld, v, w0s, fs);
-  form_q(G, m, ld, w0s, fs, Z);
+  hessenberg(G, m, ld, v, w0s, fs, hl);
+  form_q(G, m, ld, w0s, fs, hl, Z);
   wave_sync();
   for (int c = t; c < m; c += NT)
     for (int r = c + 2; r < m; ++r) G[r + c * ld] = make_double2(0.0, 0.0);
@@ -781,6 +794,7 @@ __global__ __launch_bounds__(CY_BS) void k_cycle(CycleArgs a) {
   __shared__ double2 gr[129];      // c transformed by the least squares, then rho
   __shared__ double2 w0s[128];     // Hessenberg reflectors, then the sweep's rotations
   __shared__ double fs[128];
+  __shared__ int hl[128];          // Hessenberg reflector lengths
   __shared__ int piv[128];
   __shared__ int order[128];
   __shared__ int s_kout, s_exit;
@@ -803,13 +817,13 @@ __global__ __launch_bounds__(CY_BS) void k_cycle(CycleArgs a) {
     if (!ex) {
       if (z_lds) {
         phase_g(a, sh, ld, piv);
-        phase_hess(a, sh, sh + m * ld, ld, v, w0s, fs);
+        phase_hess(a, sh, sh + m * ld, ld, v, w0s, fs, hl);
       } else if (g_lds) {
         phase_g(a, sh, ld, piv);
-        phase_hess(a, sh, wZ, ld, v, w0s, fs);
+        phase_hess(a, sh, wZ, ld, v, w0s, fs, hl);
       } else {
         phase_g(a, wG, ld, piv);
-        phase_hess(a, wG, wZ, ld, v, w0s, fs);
+        phase_hess(a, wG, wZ, ld, v, w0s, fs, hl);
       }
     }
   }
