@@ -212,8 +212,38 @@ __host__ __device__ __forceinline__ int eo_neighbour(const Geom& g, const int c[
 //      one region slice away, and the chunks of a tile are adjacent.
 //   2: the regions of 1, and inside a region every tile for one rhs chunk before the next chunk
 //      (neighbouring tiles then stage the same rhs at the same time).
+//   3: the tile grid cut in halves along z and in quarters along t into eight regions, each with
+//      the whole x and y extent; inside a region tiles run lexicographically, so the x and y
+//      neighbours of a tile (whose faces use a quarter of each line they touch) are one tile or
+//      one tile row away, and its t neighbour one region slice away; the chunks of a tile adjacent.
 __host__ __device__ __forceinline__ void tile_of_block(const Geom& g, int loc, int nch, int order,
                                               int (&tc)[4], int& tile, int& chunk) {
+  if (order == 3) {
+    const int sz = (g.NT[2] + 1) >> 1;
+    int base = 0, z0 = 0, ez = 1, t0 = 0, et = 1;
+    // region rho = a + 2b takes the upper z half if a and the t quarter b; uniform, so scalar
+    for (int rho = 0; rho < 8; ++rho) {
+      const int a = rho & 1, b = rho >> 1;
+      z0 = a ? sz : 0;
+      ez = a ? g.NT[2] - sz : sz;
+      t0 = (b * g.NT[3]) >> 2;
+      et = (((b + 1) * g.NT[3]) >> 2) - t0;
+      const int n = g.NT[0] * g.NT[1] * ez * et * nch;
+      if (loc < base + n) break;
+      base += n;
+    }
+    const int local = loc - base;
+    int tl = local / nch;
+    chunk = local - tl * nch;
+    tc[0] = tl % g.NT[0];
+    tl /= g.NT[0];
+    tc[1] = tl % g.NT[1];
+    tl /= g.NT[1];
+    tc[2] = z0 + tl % ez;
+    tc[3] = t0 + tl / ez;
+    tile = tc[0] + g.NT[0] * (tc[1] + g.NT[1] * (tc[2] + g.NT[2] * tc[3]));
+    return;
+  }
   if (order == 0) {
     tile = loc / nch;
     chunk = loc - tile * nch;

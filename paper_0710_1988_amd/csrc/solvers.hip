@@ -126,7 +126,7 @@ bool forced_shape(bool f32, bool half, Shape& sh) {
   if (nb == 0 && !f32) nb = 1;
   sh.nb = nb;
   sh.rg = e_rg ? std::max(0, std::atoi(e_rg)) : 0;
-  sh.order = e_to ? std::min(2, std::max(0, std::atoi(e_to))) : 0;
+  sh.order = e_to ? std::min(3, std::max(0, std::atoi(e_to))) : 0;
   return true;
 }
 
@@ -148,8 +148,8 @@ Shape choose_shape(dbq_ctx* c, bool f32, const DsBatch& b) {
   if (f32) {
     for (int g : {1, 2, 3, 4, 6, 0})
       if (g < maxr)
-        for (int o : {0, 1, 2})
-          if (o < 2 || (g != 0 && g < maxr)) cand.push_back(Shape{0, g, o});
+        for (int o : {0, 1, 2, 3})
+          if (o != 2 || (g != 0 && g < maxr)) cand.push_back(Shape{0, g, o});
   }
   if (cand.size() == 1) return cand[0];
   int big = 0;
@@ -223,8 +223,8 @@ Shape choose_shape_half(dbq_ctx* c, bool f32, const DsBatch& b) {
   if (f32) {
     for (int g : {1, 2, 3, 4, 6, 0})
       if (g < maxr)
-        for (int o : {0, 1, 2})
-          if (o < 2 || (g != 0 && g < maxr)) cand.push_back(Shape{0, g, o});
+        for (int o : {0, 1, 2, 3})
+          if (o != 2 || (g != 0 && g < maxr)) cand.push_back(Shape{0, g, o});
   }
   if (cand.size() == 1) return cand[0];
   int big = 0;

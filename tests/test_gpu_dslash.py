@@ -54,11 +54,12 @@ def test_apply_fp32_matches_oracle(gpu_lib, L, dagger):
 @pytest.mark.parametrize("L", LATS + [(8, 8, 4, 12), (16, 8, 12, 8)])
 @pytest.mark.parametrize("shape", [("0", "1"), ("0", "2"), ("0", "0"), ("1", "1"), ("1", "0"),
                                    ("2", "1"), ("4", "0"), ("0", "1", "1"), ("0", "0", "1"),
-                                   ("0", "2", "2"), ("0", "1", "2"), ("0", "1", "0", "1")])
+                                   ("0", "2", "2"), ("0", "1", "2"), ("0", "1", "0", "1"),
+                                   ("0", "1", "3"), ("0", "0", "3")])
 def test_every_fp32_launch_shape_matches_oracle(gpu_lib, monkeypatch, L, shape):
     """Each FP32 launch shape: rhs per thread 1/2/4 with rhs grouping, and the LDS-staged tile
     kernel (nb 0) with 1, 2 or all rhs per block in each tile order (lexicographic; eight x/y/z
-    regions; regions with rhs chunks outermost); 5 rhs leave a ragged last chunk, and the tile
+    regions; regions with rhs chunks outermost; eight z/t regions); 5 rhs leave a ragged last chunk, and the tile
     grids include odd and unit tile counts, whose regions are uneven or empty, and tiles smaller
     than 4^4."""
     monkeypatch.setenv("DBQ_DS_NB", shape[0])
@@ -149,7 +150,7 @@ def _big_batch():
     return _BIG
 
 
-@pytest.mark.parametrize("order", [None, "0", "1", "2"])
+@pytest.mark.parametrize("order", [None, "0", "1", "2", "3"])
 def test_full_size_24x48_batch_of_12_sampled_sites(gpu_lib, monkeypatch, order):
     """The HBM-sized operator launch: 24^3 x 48 with 12 Z2 sources in one FP32 call, in the tuned
     launch shape (None) and as the LDS tile kernel with 4 rhs per block in each tile order; 128

@@ -55,7 +55,7 @@ def test_schur_apply_fp32_matches_oracle(gpu_lib, L, nrhs):
 @pytest.mark.parametrize("L", LATS)
 @pytest.mark.parametrize("shape", [("0", "1"), ("0", "2"), ("0", "0"), ("1", "1"), ("1", "0"),
                                    ("2", "0"), ("2", "2"), ("0", "1", "1"), ("0", "0", "1"),
-                                   ("0", "2", "2")])
+                                   ("0", "2", "2"), ("0", "1", "3")])
 def test_every_schur_fp32_launch_shape_matches_oracle(gpu_lib, monkeypatch, L, shape):
     """Each FP32 launch shape of the half-lattice kernels: the LDS-staged tile kernel (nb 0) with
     1, 2 or all rhs per block in each tile order, and 1 or 2 rhs per thread; 5 rhs leave a
