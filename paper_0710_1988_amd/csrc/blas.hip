@@ -596,6 +596,96 @@ __global__ void k_zero(double2* __restrict__ x, long long n) {
 
 inline unsigned nb256(long long n) { return unsigned((n + 255) / 256); }
 
+// ---- Basis combinations Y = beta Y + sg(e) A M with several output columns, on FP64 matrix
+// cores.  With A and Y as real matrices over interleaved (re, im) doubles, the complex product is
+// a real one: output column (j, re) takes a.re M_cj.re - a.im M_cj.im and (j, im) takes
+// a.re M_cj.im + a.im M_cj.re.  A wave owns 16 rows (elements) of Y and all 8 NT complex output
+// columns (NT 16-wide accumulator tiles, lane l holding D[l / 16 + 4 v][l % 16]); in a step,
+// lane group q = l / 16 reads the element of its row in column c0 + q of A (one 16-byte load)
+// and feeds its real part and its imaginary part to two instructions per tile, so every element
+// of A is read once per launch.  The rows of M the steps need sit in LDS, CM_KC at a time.
+constexpr int CM_BS = 256;  // 4 waves, 64 rows of Y per block
+constexpr int CM_KC = 32;   // rows of M per LDS chunk (a multiple of 4)
+constexpr int CM_U = 4;     // steps whose loads are in flight together
+
+template <int NT>
+__global__ __launch_bounds__(CM_BS) void k_combine_mfma(const double2* __restrict__ A,
+                                                        long long lda, int na,
+                                                        const double2* __restrict__ M, int ldm,
+                                                        double2* __restrict__ Y, long long ldy,
+                                                        int nb, long long n, long long V, int g5,
+                                                        int beta) {
+  constexpr int NC = 8 * NT;  // complex output columns held
+  __shared__ double2 Ps[CM_KC * NC];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int q = lane >> 4, r = lane & 15, part = r & 1;
+  const long long row0 = ((long long)blockIdx.x * (CM_BS / 64) + wv) * 16;
+  const long long row = row0 + r;
+  const bool in = row < n;
+  f64x4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < na; k0 += CM_KC) {
+    const int kc = min(CM_KC, na - k0);
+    __syncthreads();  // the previous chunk is no longer read
+    for (int e = threadIdx.x; e < CM_KC * NC; e += CM_BS) {
+      const int c = e / NC, j = e - c * NC;
+      Ps[e] = (c < kc && j < nb) ? M[(k0 + c) + (long long)j * ldm] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    // steps of 4 columns; a step's column stays below CM_KC (a multiple of 4), the rows of Ps
+    // past kc are zero and so are the loads past it
+    for (int c0 = 0; c0 < kc; c0 += 4 * CM_U) {
+      double2 a[CM_U];
+#pragma unroll
+      for (int u = 0; u < CM_U; ++u) {
+        const int c = c0 + 4 * u + q;
+        a[u] = (in && c < kc) ? A[(long long)(k0 + c) * lda + row] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < CM_U; ++u) {
+        if (c0 + 4 * u >= kc) break;  // uniform over the wave
+        const int c = c0 + 4 * u + q;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const double2 p = Ps[c * NC + 8 * t + (r >> 1)];
+          const double yre = part ? p.y : p.x;
+          const double yim = part ? p.x : -p.y;
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, yre, acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].y, yim, acc[t], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // lane l holds rows row0 + q + 4 v of output column 8 t + r / 2, the real part on even r and
+  // the imaginary part on odd r: the even lane stores both
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double mine = acc[t][v];
+      const double other = __shfl_xor(mine, 1, 64);
+      const long long orow = row0 + q + 4 * v;
+      const int j = 8 * t + (r >> 1);
+      if (part == 0 && orow < n && j < nb) {
+        const double sg = g5sign(orow, V, g5);
+        double2* y = Y + (long long)j * ldy + orow;
+        double2 o = make_double2(sg * mine, sg * other);
+        if (beta == 1) {
+          const double2 yv = *y;
+          o.x += yv.x;
+          o.y += yv.y;
+        } else if (beta == -1) {
+          const double2 yv = *y;
+          o.x = yv.x - o.x;
+          o.y = yv.y - o.y;
+        }
+        *y = o;
+      }
+    }
+  }
+}
+
 }  // namespace
 
 void write_col_f64(hipStream_t s, double2* M, int ld, int col, int count, const double2* h1,
@@ -686,10 +776,28 @@ void arn_combine_f64(hipStream_t s, double2* Q, long long ld, int j, long long n
   DBQ_HIP(hipGetLastError());
 }
 
+// DBQ_COMBINE_MFMA=0 keeps the FMA kernel for every shape (for comparison)
+static bool combine_mfma_enabled() {
+  const char* e = std::getenv("DBQ_COMBINE_MFMA");
+  return !(e && std::atoi(e) == 0);
+}
+
 void combine_f64(hipStream_t s, const double2* A, long long lda, int na, const double2* M, int ldm,
                  double2* Y, long long ldy, int nb, long long n, long long V, int g5, int beta) {
   if (nb <= 0) return;
   if (na <= 0 && beta != 0) return;
+  // 9 to 40 columns of Y: one pass over A on the matrix cores (8 NT columns per wave)
+  if (nb > 8 && nb <= 40 && na > 0 && combine_mfma_enabled()) {
+    const dim3 grid(unsigned((n + CM_BS / 4 - 1) / (CM_BS / 4)));
+    switch ((nb + 7) / 8) {
+      case 2: hipLaunchKernelGGL((k_combine_mfma<2>), grid, dim3(CM_BS), 0, s, A, lda, na, M, ldm, Y, ldy, nb, n, V, g5, beta); break;
+      case 3: hipLaunchKernelGGL((k_combine_mfma<3>), grid, dim3(CM_BS), 0, s, A, lda, na, M, ldm, Y, ldy, nb, n, V, g5, beta); break;
+      case 4: hipLaunchKernelGGL((k_combine_mfma<4>), grid, dim3(CM_BS), 0, s, A, lda, na, M, ldm, Y, ldy, nb, n, V, g5, beta); break;
+      default: hipLaunchKernelGGL((k_combine_mfma<5>), grid, dim3(CM_BS), 0, s, A, lda, na, M, ldm, Y, ldy, nb, n, V, g5, beta); break;
+    }
+    DBQ_HIP(hipGetLastError());
+    return;
+  }
   // up to 16 columns of Y per pass over A (one pass for the 12-source projection)
   if (nb <= 8) {
     dim3 grid(nb256(n), 1);
