@@ -121,7 +121,10 @@ int dbq_site_tile(const int32_t L[4], int32_t* T);
  * order 0: tiles in lexicographic order, the chunks of one tile adjacent; order 1: the tile grid
  * cut in halves along x, y and z into eight regions taken one after the other, tiles
  * lexicographic inside a region, chunks adjacent; order 2: the regions of order 1, inside a
- * region every tile for one chunk before the next chunk.  tile, chunk: HOST int32
+ * region every tile for one chunk before the next chunk; order 3: the tile grid cut in halves
+ * along z and quarters along t (t quarter b = [floor(b NT_t / 4), floor((b + 1) NT_t / 4))) into
+ * eight regions taken one after the other (z half fastest), each with the whole x and y extent,
+ * tiles lexicographic inside a region, chunks adjacent.  tile, chunk: HOST int32
  * [ntiles * nchunks].  DBQ_EINVAL for odd extents, nchunks < 1 or another order. */
 int dbq_tile_schedule_host(const int32_t L[4], int32_t nchunks, int32_t order, int32_t* tile,
                            int32_t* chunk);

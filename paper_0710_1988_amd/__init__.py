@@ -390,7 +390,7 @@ def site_tile(L):
 
 def tile_schedule_host(L, nchunks, order):
     """(tile, chunk) visited by each logical block of an LDS-tile Dslash launch with ``nchunks``
-    chunks of right-hand sides in tile order ``order`` (0, 1 or 2), as numpy int32 arrays."""
+    chunks of right-hand sides in tile order ``order`` (0 to 3), as numpy int32 arrays."""
     L, V = _lattice(L)
     T = site_tile(L)
     nt = (L[0] // T[0]) * (L[1] // T[1]) * (L[2] // T[2]) * (L[3] // T[3])

@@ -127,7 +127,7 @@ int dbq_geometry_host(const int32_t L[4], int32_t* lex_of_eo, int32_t* nbr) {
 
 int dbq_tile_schedule_host(const int32_t L[4], int32_t nchunks, int32_t order, int32_t* tile,
                            int32_t* chunk) {
-  if (!L || !tile || !chunk || nchunks < 1 || order < 0 || order > 2) return DBQ_EINVAL;
+  if (!L || !tile || !chunk || nchunks < 1 || order < 0 || order > 3) return DBQ_EINVAL;
   for (int i = 0; i < 4; ++i)
     if (L[i] < 2 || L[i] % 2) return DBQ_EINVAL;
   const dbq::Geom g = dbq::make_geom(L);

@@ -83,18 +83,32 @@ def test_tile_schedule_is_a_permutation_with_regions(L, nch):
     """Every LDS-tile launch order visits each (tile, rhs chunk) pair exactly once; order 0 is
     tile-major; orders 1 and 2 keep each of the eight x/y/z half-regions of the tile grid in one
     contiguous run of blocks (one run per XCD when the tile counts are even), and order 2 runs
-    the chunks of a region one after the other."""
+    the chunks of a region one after the other; order 3 does the same with eight z-half and
+    t-quarter regions spanning all of x and y, tile-lexicographic inside, chunks adjacent."""
     import paper_0710_1988_amd as dbq
     T = dbq.site_tile(L)
     NT = [L[i] // T[i] for i in range(4)]
     nt = int(np.prod(NT))
-    for order in (0, 1, 2):
+    for order in (0, 1, 2, 3):
         tile, chunk = dbq.tile_schedule_host(L, nch, order)
         pairs = tile.astype(np.int64) * nch + chunk
         assert np.array_equal(np.sort(pairs), np.arange(nt * nch)), order
         if order == 0:
             b = np.arange(nt * nch)
             assert np.array_equal(tile, b // nch) and np.array_equal(chunk, b % nch)
+            continue
+        if order == 3:
+            z = (tile // (NT[0] * NT[1])) % NT[2]
+            t = tile // (NT[0] * NT[1] * NT[2])
+            zq = (z >= (NT[2] + 1) // 2).astype(int)
+            tq = np.array([max(b for b in range(4) if (b * NT[3]) // 4 <= tv) for tv in t])
+            region = zq + 2 * tq
+            assert np.all(np.diff(region) >= 0)
+            for rho in range(8):
+                sel = region == rho
+                # tiles lexicographic inside the region, the chunks of a tile adjacent
+                assert np.all(np.diff(tile[sel][::nch]) > 0)
+                assert np.array_equal(chunk[sel], np.tile(np.arange(nch), sel.sum() // nch))
             continue
         tc = [tile % NT[0], (tile // NT[0]) % NT[1], (tile // (NT[0] * NT[1])) % NT[2]]
         half = [(NT[d] + 1) // 2 for d in range(3)]
@@ -115,5 +129,5 @@ def test_tile_schedule_rejects_bad_arguments():
     lib = _abi.load()
     L = (ctypes.c_int32 * 4)(4, 4, 4, 4)
     buf = (ctypes.c_int32 * 16)()
-    assert lib.dbq_tile_schedule_host(L, 1, 3, buf, buf) == _abi.DBQ_EINVAL
+    assert lib.dbq_tile_schedule_host(L, 1, 4, buf, buf) == _abi.DBQ_EINVAL
     assert lib.dbq_tile_schedule_host(L, 0, 1, buf, buf) == _abi.DBQ_EINVAL
